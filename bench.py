@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Throughput of the InfOli step on one MI355X.
+
+A "step" advances every network of the workload by one synchronous time step
+(dt = 0.05 ms): gap-junction currents plus the three-compartment update of
+every cell, all in the library's HIP kernels. Inputs are synthetic (seeded),
+shaped like the paper's networks, and resident in device memory before the
+timed region starts.
+
+Workloads (--workload):
+  csr4096  three 4,096-cell symmetric Erdos-Renyi CSR networks at 1 %, 10 %
+           and 50 % density (g = 0.04, bias N(0, 0.5), 6 uA/cm^2 pulse at
+           20-25 ms), stepped together: the default, 20,000 steps
+  uni96    96 cells all-to-all (g = 0.04), 2,000 steps
+  uni16k   16,384 cells all-to-all (g = 0.04*96/N), 4,000 steps
+
+Prints one JSON line (rank 0) with the throughput, a roofline entry for the
+step kernel and the CPU oracle timed on a bounded sample of the same work.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from paper_1612_01501_amd import inputs as I  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "csr4096": dict(steps=20000, warmup=1000),
+    "uni96": dict(steps=2000, warmup=200),
+    "uni16k": dict(steps=4000, warmup=100),
+}
+
+
+def build_workload(name):
+    if name == "csr4096":
+        nets = [I.config1(p) for p in (0.01, 0.1, 0.5)]
+        desc = ("3 x 4,096-cell symmetric Erdos-Renyi gap graphs (1/10/50 % density) as CSR, "
+                "g=0.04 mS/cm^2, bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms")
+    elif name == "uni96":
+        nets = [I.config0()]
+        desc = "96 cells all-to-all, g=0.04 mS/cm^2, 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms"
+    elif name == "uni16k":
+        nets = [I.config2()]
+        desc = "16,384 cells all-to-all, g=0.04*96/N mS/cm^2, +-1 mV jitter, no input, FP32, dt=0.05 ms"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return nets, desc
+
+
+def algorithmic_bytes(nets):
+    """Bytes one step launch must move at minimum: per cell 14 state floats in
+    and out plus the bias (116 B); per CSR edge its int32 column (4 B; the
+    weight is the network's uniform g); per CSR row its row pointer (8 B).
+    Gathered neighbour voltages are cache hits and not counted."""
+    b = 0
+    for n in nets:
+        b += 116 * n.n
+        if n.conn == "csr":
+            b += 4 * int(n.row_ptr[-1]) + 8 * n.n
+        elif n.conn == "dense":
+            b += 4 * n.n * n.n
+    return b
+
+
+def cpu_baseline(nets, budget_s=15.0):
+    """The fp32 oracle on the host cores, a bounded number of steps of the
+    same networks (timed per network, summed)."""
+    from oracle import Oracle, max_threads
+    o = Oracle("f32")
+    x0s = [o.initial_state(n) for n in nets]
+    t0 = time.perf_counter()
+    for n, x in zip(nets, x0s):
+        o.run(n, 2, x0=x)
+    probe = max(time.perf_counter() - t0, 1e-4) / 2.0
+    steps = int(max(2, min(5000, budget_s / probe)))
+    t0 = time.perf_counter()
+    for n, x in zip(nets, x0s):
+        o.run(n, steps, x0=x)
+    dt = time.perf_counter() - t0
+    cells = sum(n.n for n in nets)
+    return {"value": cells * steps / dt, "unit": "cell-steps/s", "cores": max_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the same {len(nets)} network(s) ({cells} cells) from the initial state, fp32 oracle, OpenMP over cells"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="csr4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="graph", choices=["graph", "launch", "auto"])
+    ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the per-step Vd exchange across GPUs is not implemented)", file=sys.stderr)
+        sys.exit(2)
+    steps = args.steps if args.steps is not None else WORKLOADS[args.workload]["steps"]
+    warmup = args.warmup if args.warmup is not None else WORKLOADS[args.workload]["warmup"]
+
+    import torch
+    from paper_1612_01501_amd import infoli
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    nets, desc = build_workload(args.workload)
+    x0s = [infoli.initial_state(n) for n in nets]
+    stream = torch.cuda.current_stream().cuda_stream
+    sim = infoli.Simulator(nets, init_states=x0s, stream=stream, step_mode=args.mode,
+                           graph_chunk=args.graph_chunk)
+    info = sim.info()
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    dev_ms = sim.last_step_ms()
+    sim.close()
+
+    cells = sum(n.n for n in nets)
+    pairs = sum(n.pairs_per_step() for n in nets)
+    cell_steps_s = cells * steps / wall
+    launch_s = dev_ms * 1e-3 / steps        # one step kernel launch per step
+    abytes = algorithmic_bytes(nets)
+    achieved = abytes / launch_s / 1e9
+    out = {
+        "metric": "cell-steps/sec (plain InfOli step, gap junctions + compartments)",
+        "value": cell_steps_s,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "cells": cells,
+                   "gap_pairs_per_step": pairs, "step_mode": args.mode,
+                   "tiles": info["n_tiles"], "lanes_per_row": info["lanes_per_row"]},
+        "gap_pairs_per_s": pairs * steps / wall,
+        "device_ms_per_step": dev_ms / steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "infoli::k_step<256>", "algorithmic_bytes_per_launch": abytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * infoli.h - C ABI of the MI355X (gfx950) InfOli network simulator.
+ *
+ * The library advances networks of three-compartment inferior-olive cells
+ * (dendrite, soma, axon) coupled through dendritic gap junctions, the
+ * workload of Smaragdos et al., "BrainFrame" (arXiv:1612.01501):
+ *
+ *   - Section 2.2: every step n -> n+1 updates all compartments of all cells
+ *     and all gap junctions from the step-n state only (synchronous forward
+ *     Euler, dt = 50 us by default); each cell gets one evoked input value per
+ *     step; its output is the axon voltage.
+ *   - Section 2.3 (Algorithm 1): the gap current into cell i is
+ *       I_gap,i = sum_j w_ij * dV * (0.8 * exp(-dV^2 / 100) + 0.2),
+ *       dV = Vd_i - Vd_j  (mV; w in mS/cm^2; I in uA/cm^2),
+ *     an outward current of the dendrite. Connectivity is an N x N weight
+ *     matrix given before the run (Section 2.3), stored uniform, dense or CSR.
+ *   - Section 2.4.3: the whole run's inputs are placed on the device once at
+ *     initialisation; no host-to-device traffic happens while stepping.
+ *
+ * Conventions (all entry points):
+ *   - Every function returns an infoli_status; none aborts, exits or lets a
+ *     C++ exception escape. On failure nothing observable changes and
+ *     infoli_last_error() describes the failure.
+ *   - Host pointers are read during the call only: the caller keeps ownership
+ *     and may free them when the call returns. Output buffers are allocated
+ *     by the caller, with an explicit capacity; a too-small capacity returns
+ *     INFOLI_E_INVALID_ARG and writes nothing.
+ *   - A context owns all device memory it allocates; infoli_destroy frees it.
+ *     A context is used by one host thread at a time; contexts are independent.
+ *   - Device work is queued on the context's stream (the caller's HIP stream
+ *     when options.hip_stream is set, else a stream the context owns).
+ *     infoli_step only queues work; infoli_sync and the read functions wait.
+ *   - State is structure-of-arrays, float32: element (v, i) of an instance
+ *     with n cells is at offset v * n + i, v in [0, INFOLI_NUM_STATE).
+ *   - Results are deterministic: repeated runs give bitwise identical states
+ *     (fixed reduction order, no floating-point atomics).
+ */
+#ifndef INFOLI_API_H_
+#define INFOLI_API_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum infoli_status {
+    INFOLI_OK = 0,
+    INFOLI_E_INVALID_ARG = 1,   /* NULL pointer, bad size, bad enum, capacity too small */
+    INFOLI_E_BAD_GRAPH = 2,     /* CSR not monotone, column out of range, non-finite weight */
+    INFOLI_E_OUT_OF_MEMORY = 3, /* device or host allocation failed                        */
+    INFOLI_E_DEVICE = 4,        /* HIP runtime error, or no gfx950 device                   */
+    INFOLI_E_NUMERIC = 5,       /* a state value became NaN or infinite while stepping      */
+    INFOLI_E_STATE = 6,         /* call not valid in the context's current state            */
+    INFOLI_E_UNSUPPORTED = 7    /* valid request that this build does not implement        */
+} infoli_status;
+
+/* Connectivity storage of one network (Section 2.3: N x N weights). */
+typedef enum infoli_conn {
+    INFOLI_CONN_NONE = 0,        /* no gap junctions (independent cells)                    */
+    INFOLI_CONN_UNIFORM_ALL = 1, /* all-to-all, w_ij = g_uniform for i != j                 */
+    INFOLI_CONN_DENSE = 2,       /* explicit n*n row-major matrix, row i = weights INTO i   */
+    INFOLI_CONN_CSR = 3          /* CSR by receiving cell: row i lists the j coupled to i   */
+} infoli_conn;
+
+/* Cell state variables (structure-of-arrays order). Voltages in mV. */
+enum {
+    INFOLI_VD = 0,  /* dendrite voltage                       */
+    INFOLI_CA = 1,  /* dendritic [Ca2+]                       */
+    INFOLI_R = 2,   /* high-threshold Ca activation           */
+    INFOLI_S = 3,   /* Ca-activated K activation              */
+    INFOLI_Q = 4,   /* h-current activation                   */
+    INFOLI_VS = 5,  /* soma voltage                           */
+    INFOLI_K = 6,   /* low-threshold Ca activation            */
+    INFOLI_L = 7,   /* low-threshold Ca inactivation          */
+    INFOLI_H = 8,   /* soma Na inactivation                   */
+    INFOLI_N = 9,   /* soma delayed-rectifier K activation    */
+    INFOLI_X = 10,  /* soma K activation                      */
+    INFOLI_VA = 11, /* axon voltage: the cell output          */
+    INFOLI_HA = 12, /* axon Na inactivation                   */
+    INFOLI_XA = 13, /* axon K activation                      */
+    INFOLI_NUM_STATE = 14
+};
+
+/* The 20 per-cell conductances (mS/cm^2), area ratios and reversal
+ * potentials (mV) of Table 1 ("neuron conductances: 20"), in this order:
+ * g_CaH g_KCa g_h g_ld g_CaL g_Na_s g_Kdr_s g_K_s g_ls g_Na_a g_K_a g_la
+ * g_int p1 p2 V_Na V_K V_Ca V_h V_L. */
+enum { INFOLI_NUM_PARAMS = 20 };
+
+/* An evoked-input pulse: amplitude (uA/cm^2, into the dendrite) added for the
+ * integer steps step_begin <= n < step_end, on cells cell_begin <= i < cell_end
+ * of its network (cell_end < 0 means every cell). */
+typedef struct infoli_pulse {
+    int64_t step_begin;
+    int64_t step_end;
+    float amplitude;
+    int32_t cell_begin;
+    int32_t cell_end;
+} infoli_pulse;
+
+enum { INFOLI_MAX_PULSES = 64 }; /* per network */
+
+/* One network. All pointers are host pointers; NULL where marked optional. */
+typedef struct infoli_network_spec {
+    int32_t n_cells;            /* >= 1                                                    */
+    float dt_ms;                /* > 0; the paper's step is 0.05 ms                        */
+    int32_t conn;               /* infoli_conn                                             */
+    float g_uniform;            /* UNIFORM_ALL weight; CSR weight when w_csr is NULL       */
+    const float *w_dense;       /* DENSE: [n][n], finite                                   */
+    const int64_t *row_ptr;     /* CSR: [n+1], row_ptr[0] = 0, non-decreasing, = nnz at n  */
+    const int32_t *col;         /* CSR: [nnz], 0 <= col < n                                */
+    const float *w_csr;         /* CSR: [nnz] finite weights, optional                     */
+    int64_t nnz;                /* CSR: number of directed edges                           */
+    const float *params;        /* optional [INFOLI_NUM_PARAMS]; NULL => defaults          */
+    const float *init_state;    /* optional [INFOLI_NUM_STATE][n]; NULL => rest state      */
+    const float *i_bias;        /* optional [n] constant input current, uA/cm^2            */
+    const infoli_pulse *pulses; /* optional [n_pulses], n_pulses <= INFOLI_MAX_PULSES      */
+    int32_t n_pulses;
+    const float *i_stream;      /* optional dense input [i_stream_steps][n], uA/cm^2,
+                                   added at steps 0 <= n < i_stream_steps (Section 2.4.3) */
+    int64_t i_stream_steps;
+    int64_t step0;              /* absolute index of the first step (resume); >= 0        */
+} infoli_network_spec;
+
+/* How steps are driven on the device. */
+typedef enum infoli_step_mode {
+    INFOLI_MODE_AUTO = 0,       /* library choice                                          */
+    INFOLI_MODE_LAUNCH = 1,     /* one kernel launch per step                              */
+    INFOLI_MODE_GRAPH = 2,      /* chunks of steps captured in a HIP graph and replayed    */
+    INFOLI_MODE_PERSISTENT = 3  /* one launch for many steps; workgroup barriers only,
+                                   for networks that fit one workgroup each               */
+} infoli_step_mode;
+
+typedef struct infoli_options {
+    void *hip_stream;            /* hipStream_t to queue on; NULL => context-owned stream  */
+    int32_t step_mode;           /* infoli_step_mode                                       */
+    int32_t graph_chunk;         /* steps per captured graph (GRAPH mode), >= 2, even      */
+    int32_t max_spikes_per_cell; /* spike times kept per cell (ring); 0 => counts only     */
+    int32_t tile_rows;           /* 0 => tuned; else rows per workgroup tile               */
+    int32_t lanes_per_row;       /* 0 => tuned; CSR/dense lanes per row: 4..64, power of 2 */
+    int32_t check_finite;        /* 1 => a NaN/Inf state makes infoli_sync fail            */
+} infoli_options;
+
+typedef struct infoli_ctx infoli_ctx;
+
+/* Fill *opt with the defaults (AUTO mode, 64 spike times, tuned tiles, checks on). */
+infoli_status infoli_default_options(infoli_options *opt);
+
+/* Copy the default cell parameters (see INFOLI_NUM_PARAMS) into out[20]. */
+infoli_status infoli_default_params(float *out);
+
+/* Rest state of one cell: every voltage at v0_mv, every gate at its steady
+ * state there, [Ca2+] at its steady state. params NULL => defaults.
+ * out[INFOLI_NUM_STATE]. */
+infoli_status infoli_rest_state(const float *params, float v0_mv, float *out);
+
+/* Create a context for one network: validates the spec, copies every array
+ * to the device and prepares the step kernels. On failure *out = NULL. */
+infoli_status infoli_init(const infoli_network_spec *spec, const infoli_options *opt,
+                          infoli_ctx **out);
+
+/* Create a context for n_instances independent networks of any sizes and
+ * connectivities, stepped together by the same launches. Instance k's cells
+ * are numbered 0..n_cells-1 within the instance. All specs share step0. */
+infoli_status infoli_batch_init(const infoli_network_spec *specs, int32_t n_instances,
+                                const infoli_options *opt, infoli_ctx **out);
+
+/* Queue n_steps synchronous steps (n_steps >= 0). Returns without waiting. */
+infoli_status infoli_step(infoli_ctx *ctx, int64_t n_steps);
+
+/* Wait for queued work. Returns INFOLI_E_NUMERIC if check_finite is on and a
+ * state value became non-finite. */
+infoli_status infoli_sync(infoli_ctx *ctx);
+
+/* Blocking copy of instance `instance`'s state to host_soa
+ * ([INFOLI_NUM_STATE][n], capacity cap_floats) and of the absolute step
+ * index reached to *step_out (optional). */
+infoli_status infoli_read_state(infoli_ctx *ctx, int32_t instance, float *host_soa,
+                                int64_t cap_floats, int64_t *step_out);
+
+/* Like infoli_read_state, into device memory dev_soa (>= 14*n floats) on
+ * the context's stream, without waiting. */
+infoli_status infoli_read_state_device(infoli_ctx *ctx, int32_t instance, float *dev_soa);
+
+/* Replace instance `instance`'s state and set the absolute step index of all
+ * instances to `step` (resume: a run split at step k and continued from the
+ * state read there matches the straight run bitwise). */
+infoli_status infoli_write_state(infoli_ctx *ctx, int32_t instance, const float *host_soa,
+                                 int64_t step);
+
+/* Gap currents I_gap,i (uA/cm^2) of every cell of the instance, computed from
+ * the current Vd by the same kernel code the step uses. Blocking. host[n]. */
+infoli_status infoli_read_gap_current(infoli_ctx *ctx, int32_t instance, float *host,
+                                      int64_t cap);
+
+/* Spikes of the instance: counts[n] (upward 0 mV crossings of Va) and, when
+ * times_ms is not NULL, the last max_spikes_per_cell spike times of each cell,
+ * times_ms[i * max_spikes_per_cell + (k mod max_spikes_per_cell)] for its k-th
+ * spike (linear interpolation between steps, ms from step 0). Blocking. */
+infoli_status infoli_read_spikes(infoli_ctx *ctx, int32_t instance, int32_t *counts,
+                                 int64_t counts_cap, float *times_ms, int64_t times_cap);
+
+/* Reset spike counts and times to zero. */
+infoli_status infoli_clear_spikes(infoli_ctx *ctx);
+
+/* Description of what the context runs. */
+typedef struct infoli_info {
+    int32_t n_instances;
+    int64_t total_cells;
+    int64_t pairs_per_step;     /* directed gap pair-interactions evaluated per step    */
+    int64_t step;               /* absolute step index reached (after queued work)     */
+    int32_t step_mode;          /* mode in use                                          */
+    int32_t n_tiles;            /* workgroups per step launch                           */
+    int32_t tile_rows;          /* rows per tile of the largest instance               */
+    int32_t lanes_per_row;
+    int64_t device_bytes;       /* device memory held                                   */
+} infoli_info;
+infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
+
+/* Duration (ms, HIP events on the context stream) of the last infoli_step
+ * call's device work; valid after infoli_sync. */
+infoli_status infoli_last_step_ms(infoli_ctx *ctx, float *ms);
+
+/* Names of state variables ("Vd", "Ca", ...); NULL when out of range. */
+const char *infoli_state_var_name(int32_t v);
+
+/* Last error message of ctx, or of the calling thread's last failed call
+ * when ctx is NULL. Never NULL. */
+const char *infoli_last_error(const infoli_ctx *ctx);
+
+/* Free the context and all its device memory. NULL is allowed. */
+void infoli_destroy(infoli_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INFOLI_API_H_ */

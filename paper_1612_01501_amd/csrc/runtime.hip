@@ -1,0 +1,798 @@
+// Host side of the C ABI declared in include/infoli.h: spec validation,
+// device-resident network data (Section 2.4.3: everything the run needs is
+// copied to the device once), tile planning and the step driver (one
+// launch per step, or chunks of steps replayed from a HIP graph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/infoli.h"
+#include "cell_model.hpp"
+#include "step_kernel.hpp"
+
+using namespace infoli;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+// Default cell parameters, in the order of INFOLI_NUM_PARAMS, of the
+// published three-compartment inferior-olive model.
+const float kDefaultParams[INFOLI_NUM_PARAMS] = {
+    4.5f,    // g_CaH
+    35.0f,   // g_KCa
+    0.125f,  // g_h
+    0.016f,  // g_ld
+    0.68f,   // g_CaL
+    150.0f,  // g_Na_s
+    9.0f,    // g_Kdr_s
+    5.0f,    // g_K_s
+    0.016f,  // g_ls
+    240.0f,  // g_Na_a
+    20.0f,   // g_K_a
+    0.016f,  // g_la
+    0.13f,   // g_int
+    0.25f,   // p1
+    0.15f,   // p2
+    55.0f,   // V_Na
+    -75.0f,  // V_K
+    120.0f,  // V_Ca
+    -43.0f,  // V_h
+    10.0f,   // V_L
+};
+
+const char* const kStateNames[INFOLI_NUM_STATE] = {"Vd", "Ca", "r", "s", "q", "Vs", "k",
+                                                   "l",  "h",  "n", "x", "Va", "ha", "xa"};
+
+struct Fail {
+    infoli_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(infoli_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    throw Fail{code, buf};
+}
+
+#define HIPX(expr)                                                                   \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            fail(e_ == hipErrorOutOfMemory ? INFOLI_E_OUT_OF_MEMORY : INFOLI_E_DEVICE, \
+                 "%s: %s", #expr, hipGetErrorString(e_));                            \
+    } while (0)
+
+bool finite_all(const float* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Host copy of one rest-state computation (every voltage at v0, gates and
+// [Ca2+] at their steady state there).
+void rest_state_host(const float* P, float v0, float* x) {
+    auto boltz = [](float v, float vh, float k) { return 1.0f / (1.0f + std::exp(-(v - vh) / k)); };
+    auto rexp = [](float y, float s) { return y == 0.0f ? s : y / std::expm1(y / s); };
+    const float ar = 1.7f / (1.0f + std::exp(-(v0 - 5.0f) / 13.9f));
+    const float br = 0.02f * rexp(v0 + 8.5f, 5.0f);
+    const float r = ar / (ar + br);
+    const float icah = P[0] * r * r * (v0 - P[17]);
+    const float ca = -3.0f * icah / 0.075f;
+    const float as = std::min(0.00002f * ca, 0.01f);
+    const float ax = 0.13f * rexp(-(v0 + 25.0f), 10.0f);
+    const float bx = 1.69f * std::exp(-0.0125f * (v0 + 35.0f));
+    x[SV_VD] = v0;
+    x[SV_CA] = ca;
+    x[SV_R] = r;
+    x[SV_S] = as / (as + 0.015f);
+    x[SV_Q] = boltz(v0, -80.0f, -4.0f);
+    x[SV_VS] = v0;
+    x[SV_K] = boltz(v0, -61.0f, 4.2f);
+    x[SV_L] = boltz(v0, -85.5f, -8.5f);
+    x[SV_H] = boltz(v0, -70.0f, -5.8f);
+    x[SV_N] = boltz(v0, -3.0f, 10.0f);
+    x[SV_X] = ax / (ax + bx);
+    x[SV_VA] = v0;
+    x[SV_HA] = boltz(v0, -60.0f, -5.8f);
+    x[SV_XA] = ax / (ax + bx);
+}
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct infoli_ctx {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    infoli_options opt{};
+    std::string err;
+
+    int32_t n_inst = 0;
+    std::vector<InstDesc> inst;     // host copies of the descriptors
+    std::vector<Tile> tiles;
+    int64_t total_cells = 0;
+    int64_t stride = 0;
+    int64_t pairs_per_step = 0;
+    float dt = 0.05f;
+    int block = 256;
+
+    // device memory
+    std::vector<void*> allocs;
+    size_t device_bytes = 0;
+    float* state[2] = {nullptr, nullptr};
+    int cur = 0;
+    float* igap = nullptr;
+    float* bias = nullptr;
+    InstDesc* d_inst = nullptr;
+    Tile* d_tiles = nullptr;
+    DevPulse* d_pulses = nullptr;
+    int64_t* d_rowptr = nullptr;
+    int32_t* d_col = nullptr;
+    float* d_w = nullptr;
+    float* d_stream = nullptr;
+    int32_t* d_spk_count = nullptr;
+    float* d_spk_times = nullptr;
+    int32_t* d_flags = nullptr;
+    int64_t* d_step = nullptr;
+
+    int64_t step = 0;               // absolute index of the next step to run
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // by starting buffer parity
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+
+    template <typename T>
+    T* alloc(size_t count) {
+        if (count == 0) count = 1;
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess)
+            fail(INFOLI_E_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                 hipGetErrorString(e));
+        allocs.push_back(p);
+        device_bytes += count * sizeof(T);
+        return static_cast<T*>(p);
+    }
+
+    void release() {
+        for (int k = 0; k < 2; ++k)
+            if (graph[k]) (void)hipGraphExecDestroy(graph[k]);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* p : allocs) (void)hipFree(p);
+        allocs.clear();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+void set_err(infoli_ctx* ctx, const std::string& m) {
+    g_thread_error = m;
+    if (ctx) ctx->err = m;
+}
+
+template <typename F>
+infoli_status guarded(infoli_ctx* ctx, F&& f) {
+    try {
+        f();
+        return INFOLI_OK;
+    } catch (const Fail& e) {
+        set_err(ctx, e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_err(ctx, "host allocation failed");
+        return INFOLI_E_OUT_OF_MEMORY;
+    } catch (...) {
+        set_err(ctx, "unexpected internal error");
+        return INFOLI_E_DEVICE;
+    }
+}
+
+void validate_spec(const infoli_network_spec& s, int k) {
+    if (s.n_cells < 1) fail(INFOLI_E_INVALID_ARG, "network %d: n_cells must be >= 1", k);
+    if (s.n_cells > (1 << 26)) fail(INFOLI_E_INVALID_ARG, "network %d: n_cells too large", k);
+    if (!(s.dt_ms > 0.0f) || !std::isfinite(s.dt_ms))
+        fail(INFOLI_E_INVALID_ARG, "network %d: dt_ms must be finite and > 0", k);
+    if (s.step0 < 0) fail(INFOLI_E_INVALID_ARG, "network %d: step0 must be >= 0", k);
+    const int64_t n = s.n_cells;
+    switch (s.conn) {
+        case INFOLI_CONN_NONE: break;
+        case INFOLI_CONN_UNIFORM_ALL:
+            if (!std::isfinite(s.g_uniform)) fail(INFOLI_E_BAD_GRAPH, "network %d: g_uniform not finite", k);
+            break;
+        case INFOLI_CONN_DENSE:
+            if (!s.w_dense) fail(INFOLI_E_INVALID_ARG, "network %d: DENSE needs w_dense", k);
+            if (n > 46340) fail(INFOLI_E_INVALID_ARG, "network %d: dense n*n overflows", k);
+            if (!finite_all(s.w_dense, n * n))
+                fail(INFOLI_E_BAD_GRAPH, "network %d: non-finite dense weight", k);
+            break;
+        case INFOLI_CONN_CSR: {
+            if (!s.row_ptr) fail(INFOLI_E_INVALID_ARG, "network %d: CSR needs row_ptr", k);
+            if (s.nnz < 0) fail(INFOLI_E_INVALID_ARG, "network %d: nnz < 0", k);
+            if (s.nnz > 0 && !s.col) fail(INFOLI_E_INVALID_ARG, "network %d: CSR needs col", k);
+            if (s.row_ptr[0] != 0) fail(INFOLI_E_BAD_GRAPH, "network %d: row_ptr[0] != 0", k);
+            for (int64_t i = 0; i < n; ++i)
+                if (s.row_ptr[i + 1] < s.row_ptr[i])
+                    fail(INFOLI_E_BAD_GRAPH, "network %d: row_ptr decreases at row %lld", k, (long long)i);
+            if (s.row_ptr[n] != s.nnz)
+                fail(INFOLI_E_BAD_GRAPH, "network %d: row_ptr[n] = %lld != nnz = %lld", k,
+                     (long long)s.row_ptr[n], (long long)s.nnz);
+            for (int64_t e = 0; e < s.nnz; ++e)
+                if (s.col[e] < 0 || s.col[e] >= s.n_cells)
+                    fail(INFOLI_E_BAD_GRAPH, "network %d: column %d out of range at edge %lld", k,
+                         s.col[e], (long long)e);
+            if (s.w_csr && !finite_all(s.w_csr, s.nnz))
+                fail(INFOLI_E_BAD_GRAPH, "network %d: non-finite CSR weight", k);
+            if (!s.w_csr && !std::isfinite(s.g_uniform))
+                fail(INFOLI_E_BAD_GRAPH, "network %d: g_uniform not finite", k);
+            break;
+        }
+        default: fail(INFOLI_E_INVALID_ARG, "network %d: unknown conn %d", k, s.conn);
+    }
+    if (s.params && !finite_all(s.params, INFOLI_NUM_PARAMS))
+        fail(INFOLI_E_INVALID_ARG, "network %d: non-finite parameter", k);
+    if (s.params && (s.params[13] <= 0.0f || s.params[13] >= 1.0f || s.params[14] <= 0.0f ||
+                     s.params[14] >= 1.0f))
+        fail(INFOLI_E_INVALID_ARG, "network %d: area ratios p1, p2 must lie in (0, 1)", k);
+    if (s.init_state && !finite_all(s.init_state, INFOLI_NUM_STATE * n))
+        fail(INFOLI_E_INVALID_ARG, "network %d: non-finite initial state", k);
+    if (s.i_bias && !finite_all(s.i_bias, n)) fail(INFOLI_E_INVALID_ARG, "network %d: non-finite bias", k);
+    if (s.n_pulses < 0 || s.n_pulses > INFOLI_MAX_PULSES)
+        fail(INFOLI_E_INVALID_ARG, "network %d: n_pulses must be in [0, %d]", k, INFOLI_MAX_PULSES);
+    if (s.n_pulses > 0 && !s.pulses) fail(INFOLI_E_INVALID_ARG, "network %d: pulses is NULL", k);
+    for (int p = 0; p < s.n_pulses; ++p) {
+        const infoli_pulse& q = s.pulses[p];
+        const int32_t c1 = q.cell_end < 0 ? s.n_cells : q.cell_end;
+        if (!std::isfinite(q.amplitude) || q.step_end < q.step_begin || q.cell_begin < 0 ||
+            c1 > s.n_cells || q.cell_begin > c1)
+            fail(INFOLI_E_INVALID_ARG, "network %d: pulse %d has a bad range or amplitude", k, p);
+    }
+    if (s.i_stream) {
+        if (s.i_stream_steps <= 0) fail(INFOLI_E_INVALID_ARG, "network %d: i_stream_steps must be > 0", k);
+        if (!finite_all(s.i_stream, s.i_stream_steps * n))
+            fail(INFOLI_E_INVALID_ARG, "network %d: non-finite input stream", k);
+    }
+}
+
+int pick_lanes(double mean_degree) {
+    if (mean_degree >= 48) return 64;
+    if (mean_degree >= 24) return 32;
+    if (mean_degree >= 12) return 16;
+    if (mean_degree >= 6) return 8;
+    return 4;
+}
+
+void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t ninst,
+                   const infoli_options* opt) {
+    if (!specs || ninst < 1) fail(INFOLI_E_INVALID_ARG, "need at least one network spec");
+    infoli_default_options(&c->opt);
+    if (opt) c->opt = *opt;
+    if (c->opt.step_mode < 0 || c->opt.step_mode > INFOLI_MODE_PERSISTENT)
+        fail(INFOLI_E_INVALID_ARG, "unknown step_mode %d", c->opt.step_mode);
+    if (c->opt.step_mode == INFOLI_MODE_PERSISTENT)
+        fail(INFOLI_E_UNSUPPORTED, "PERSISTENT step mode is not available in this build");
+    if (c->opt.graph_chunk < 2 || (c->opt.graph_chunk & 1))
+        fail(INFOLI_E_INVALID_ARG, "graph_chunk must be even and >= 2");
+    if (c->opt.max_spikes_per_cell < 0 || c->opt.max_spikes_per_cell > 4096)
+        fail(INFOLI_E_INVALID_ARG, "max_spikes_per_cell must be in [0, 4096]");
+    if (c->opt.lanes_per_row != 0 &&
+        (c->opt.lanes_per_row < 4 || c->opt.lanes_per_row > 64 ||
+         (c->opt.lanes_per_row & (c->opt.lanes_per_row - 1))))
+        fail(INFOLI_E_INVALID_ARG, "lanes_per_row must be 0 or a power of two in [4, 64]");
+    if (c->opt.tile_rows < 0 || c->opt.tile_rows > kMaxTileRows)
+        fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
+    for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
+    for (int k = 1; k < ninst; ++k) {
+        if (specs[k].step0 != specs[0].step0) fail(INFOLI_E_INVALID_ARG, "all networks must share step0");
+        if (specs[k].dt_ms != specs[0].dt_ms) fail(INFOLI_E_INVALID_ARG, "all networks must share dt_ms");
+    }
+
+    int dev = 0;
+    HIPX(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPX(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        fail(INFOLI_E_DEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+
+    c->n_inst = ninst;
+    c->dt = specs[0].dt_ms;
+    c->step = specs[0].step0;
+    c->block = 256;
+
+    // ---- layout of the flattened networks
+    int64_t cells = 0, rp_total = 0, w_total = 0, col_total = 0, stream_total = 0;
+    int32_t pulses_total = 0;
+    c->inst.resize(ninst);
+    for (int k = 0; k < ninst; ++k) {
+        const infoli_network_spec& s = specs[k];
+        InstDesc& d = c->inst[k];
+        std::memset(&d, 0, sizeof(d));
+        d.cell_off = cells;
+        d.n = s.n_cells;
+        d.conn = s.conn;
+        d.g = s.g_uniform;
+        d.stream_off = -1;
+        std::memcpy(&d.p, s.params ? s.params : kDefaultParams, sizeof(CellParams));
+        cells += s.n_cells;
+        if (s.conn == INFOLI_CONN_DENSE) {
+            d.w_off = w_total;
+            w_total += (int64_t)s.n_cells * s.n_cells;
+            c->pairs_per_step += (int64_t)s.n_cells * s.n_cells;
+        } else if (s.conn == INFOLI_CONN_CSR) {
+            d.rp_off = rp_total;
+            rp_total += s.n_cells + 1;
+            d.w_off = col_total;
+            col_total += s.nnz;
+            d.has_w = s.w_csr ? 1 : 0;
+            const double deg = (double)s.nnz / s.n_cells;
+            d.lanes_per_row = c->opt.lanes_per_row ? c->opt.lanes_per_row : pick_lanes(deg);
+            c->pairs_per_step += s.nnz;
+        } else if (s.conn == INFOLI_CONN_UNIFORM_ALL) {
+            c->pairs_per_step += (int64_t)s.n_cells * (s.n_cells - 1);
+        }
+        d.pulse_off = pulses_total;
+        d.n_pulses = s.n_pulses;
+        pulses_total += s.n_pulses;
+        if (s.i_stream) {
+            d.stream_off = stream_total;
+            d.stream_steps = s.i_stream_steps;
+            stream_total += s.i_stream_steps * s.n_cells;
+        }
+    }
+    if (w_total > 0 && col_total > 0)
+        fail(INFOLI_E_UNSUPPORTED, "a batch may not mix DENSE and CSR networks");
+    c->total_cells = cells;
+    c->stride = (cells + 63) & ~int64_t(63);
+
+    // ---- tiles: blocks of consecutive rows of one network
+    for (int k = 0; k < ninst; ++k) {
+        const InstDesc& d = c->inst[k];
+        int rows;
+        switch (d.conn) {
+            case CONN_UNIFORM: rows = kUniformRows; break;
+            case CONN_DENSE: rows = 16; break;
+            case CONN_CSR: rows = c->opt.tile_rows ? c->opt.tile_rows : std::max(4, c->block / d.lanes_per_row); break;
+            default: rows = kMaxTileRows; break;
+        }
+        if (c->opt.tile_rows && d.conn != CONN_UNIFORM) rows = c->opt.tile_rows;
+        rows = std::min(rows, kMaxTileRows);
+        for (int r = 0; r < d.n; r += rows) c->tiles.push_back(Tile{k, r, std::min(d.n, r + rows), 0});
+    }
+    if (c->tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
+
+    // ---- stream
+    if (c->opt.hip_stream) {
+        c->stream = static_cast<hipStream_t>(c->opt.hip_stream);
+    } else {
+        HIPX(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    HIPX(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPX(hipEventCreate(&c->ev0));
+    HIPX(hipEventCreate(&c->ev1));
+
+    // ---- host staging of everything, then one copy each (Section 2.4.3)
+    const int64_t S = c->stride;
+    std::vector<float> h_state((size_t)INFOLI_NUM_STATE * S, 0.0f);
+    std::vector<float> h_bias((size_t)S, 0.0f);
+    std::vector<int64_t> h_rp((size_t)std::max<int64_t>(rp_total, 1));
+    std::vector<int32_t> h_col((size_t)std::max<int64_t>(col_total, 1));
+    std::vector<float> h_w((size_t)std::max<int64_t>(std::max(w_total, col_total), 1));
+    std::vector<float> h_stream((size_t)std::max<int64_t>(stream_total, 1));
+    std::vector<DevPulse> h_pulses((size_t)std::max(pulses_total, 1));
+    for (int k = 0; k < ninst; ++k) {
+        const infoli_network_spec& s = specs[k];
+        const InstDesc& d = c->inst[k];
+        const int64_t n = s.n_cells;
+        float rest[INFOLI_NUM_STATE];
+        rest_state_host(s.params ? s.params : kDefaultParams, -60.0f, rest);
+        for (int v = 0; v < INFOLI_NUM_STATE; ++v)
+            for (int64_t i = 0; i < n; ++i)
+                h_state[v * S + d.cell_off + i] = s.init_state ? s.init_state[v * n + i] : rest[v];
+        if (s.i_bias)
+            for (int64_t i = 0; i < n; ++i) h_bias[d.cell_off + i] = s.i_bias[i];
+        if (s.conn == INFOLI_CONN_DENSE)
+            std::memcpy(&h_w[d.w_off], s.w_dense, sizeof(float) * n * n);
+        if (s.conn == INFOLI_CONN_CSR) {
+            std::memcpy(&h_rp[d.rp_off], s.row_ptr, sizeof(int64_t) * (n + 1));
+            if (s.nnz) std::memcpy(&h_col[d.w_off], s.col, sizeof(int32_t) * s.nnz);
+            if (s.w_csr && s.nnz) std::memcpy(&h_w[d.w_off], s.w_csr, sizeof(float) * s.nnz);
+        }
+        for (int p = 0; p < s.n_pulses; ++p) {
+            const infoli_pulse& q = s.pulses[p];
+            DevPulse& dp = h_pulses[d.pulse_off + p];
+            dp.n0 = q.step_begin;
+            dp.n1 = q.step_end;
+            dp.amp = q.amplitude;
+            dp.c0 = q.cell_begin;
+            dp.c1 = q.cell_end < 0 ? s.n_cells : q.cell_end;
+            dp.pad0 = 0;
+        }
+        if (s.i_stream)
+            std::memcpy(&h_stream[d.stream_off], s.i_stream, sizeof(float) * s.i_stream_steps * n);
+    }
+
+    c->state[0] = c->alloc<float>((size_t)INFOLI_NUM_STATE * S);
+    c->state[1] = c->alloc<float>((size_t)INFOLI_NUM_STATE * S);
+    c->igap = c->alloc<float>(S);
+    c->bias = c->alloc<float>(S);
+    c->d_inst = c->alloc<InstDesc>(ninst);
+    c->d_tiles = c->alloc<Tile>(c->tiles.size());
+    c->d_pulses = c->alloc<DevPulse>(h_pulses.size());
+    c->d_rowptr = c->alloc<int64_t>(h_rp.size());
+    c->d_col = c->alloc<int32_t>(h_col.size());
+    c->d_w = c->alloc<float>(h_w.size());
+    c->d_stream = c->alloc<float>(h_stream.size());
+    c->d_spk_count = c->alloc<int32_t>(S);
+    const int cap = c->opt.max_spikes_per_cell;
+    c->d_spk_times = c->alloc<float>((size_t)S * std::max(cap, 1));
+    c->d_flags = c->alloc<int32_t>(4);
+    c->d_step = c->alloc<int64_t>(1);
+
+    HIPX(hipMemcpy(c->state[0], h_state.data(), sizeof(float) * h_state.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->state[1], h_state.data(), sizeof(float) * h_state.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->bias, h_bias.data(), sizeof(float) * S, hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDesc) * ninst, hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->d_tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->d_pulses, h_pulses.data(), sizeof(DevPulse) * h_pulses.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->d_rowptr, h_rp.data(), sizeof(int64_t) * h_rp.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->d_col, h_col.data(), sizeof(int32_t) * h_col.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->d_w, h_w.data(), sizeof(float) * h_w.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->d_stream, h_stream.data(), sizeof(float) * h_stream.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemset(c->d_spk_count, 0, sizeof(int32_t) * S));
+    HIPX(hipMemset(c->d_spk_times, 0, sizeof(float) * (size_t)S * std::max(cap, 1)));
+    HIPX(hipMemset(c->d_flags, 0, sizeof(int32_t) * 4));
+    HIPX(hipMemset(c->igap, 0, sizeof(float) * S));
+    HIPX(hipDeviceSynchronize());
+}
+
+StepArgs make_args(const infoli_ctx* c, bool device_step) {
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.inst = c->d_inst;
+    a.tiles = c->d_tiles;
+    a.pulses = c->d_pulses;
+    a.bias = c->bias;
+    a.row_ptr = c->d_rowptr;
+    a.col = c->d_col;
+    a.w = c->d_w;
+    a.i_stream = c->d_stream;
+    a.spike_count = c->d_spk_count;
+    a.spike_times = c->d_spk_times;
+    a.flags = c->d_flags;
+    a.igap_out = c->igap;
+    a.d_step = device_step ? c->d_step : nullptr;
+    a.stride = c->stride;
+    a.dt = c->dt;
+    a.spike_cap = c->opt.max_spikes_per_cell;
+    a.gap_only = 0;
+    return a;
+}
+
+void launch_step(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
+                 int32_t off) {
+    hipLaunchKernelGGL(k_step<256>, dim3((unsigned)c->tiles.size()), dim3(256), 0, st, a,
+                       c->state[from], c->state[from ^ 1], step_arg, off);
+}
+
+hipGraphExec_t get_graph(infoli_ctx* c, int parity) {
+    if (c->graph[parity]) return c->graph[parity];
+    const StepArgs a = make_args(c, true);
+    hipGraph_t g = nullptr;
+    HIPX(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int from = parity;
+    for (int k = 0; k < c->opt.graph_chunk; ++k) {
+        launch_step(c, c->cap_stream, a, from, 0, k);
+        from ^= 1;
+    }
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess) fail(INFOLI_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) fail(INFOLI_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    c->graph[parity] = ex;
+    return ex;
+}
+
+void run_steps(infoli_ctx* c, int64_t n_steps) {
+    if (n_steps < 0) fail(INFOLI_E_INVALID_ARG, "n_steps must be >= 0");
+    HIPX(hipEventRecord(c->ev0, c->stream));
+    int64_t left = n_steps;
+    const int mode = c->opt.step_mode;
+    const int64_t chunk = c->opt.graph_chunk;
+    const bool use_graph = (mode == INFOLI_MODE_GRAPH) || (mode == INFOLI_MODE_AUTO && n_steps >= 2 * chunk);
+    if (use_graph) {
+        while (left >= chunk) {
+            hipGraphExec_t ex = get_graph(c, c->cur);
+            hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, c->stream, c->d_step, c->step);
+            HIPX(hipGraphLaunch(ex, c->stream));
+            c->step += chunk;
+            left -= chunk;
+        }
+    }
+    if (left > 0) {
+        const StepArgs a = make_args(c, false);
+        for (int64_t k = 0; k < left; ++k) {
+            launch_step(c, c->stream, a, c->cur, c->step, 0);
+            c->cur ^= 1;
+            c->step += 1;
+        }
+    }
+    HIPX(hipGetLastError());
+    HIPX(hipEventRecord(c->ev1, c->stream));
+    c->timed = true;
+}
+
+void check_instance(const infoli_ctx* c, int32_t k) {
+    if (k < 0 || k >= c->n_inst) fail(INFOLI_E_INVALID_ARG, "instance %d out of range", k);
+}
+
+}  // namespace
+
+extern "C" {
+
+infoli_status infoli_default_options(infoli_options* opt) {
+    if (!opt) {
+        g_thread_error = "opt is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    std::memset(opt, 0, sizeof(*opt));
+    opt->hip_stream = nullptr;
+    opt->step_mode = INFOLI_MODE_AUTO;
+    opt->graph_chunk = 100;
+    opt->max_spikes_per_cell = 64;
+    opt->tile_rows = 0;
+    opt->lanes_per_row = 0;
+    opt->check_finite = 1;
+    return INFOLI_OK;
+}
+
+infoli_status infoli_default_params(float* out) {
+    if (!out) {
+        g_thread_error = "out is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    std::memcpy(out, kDefaultParams, sizeof(kDefaultParams));
+    return INFOLI_OK;
+}
+
+infoli_status infoli_rest_state(const float* params, float v0_mv, float* out) {
+    return guarded(nullptr, [&] {
+        if (!out) fail(INFOLI_E_INVALID_ARG, "out is NULL");
+        if (!std::isfinite(v0_mv)) fail(INFOLI_E_INVALID_ARG, "v0 not finite");
+        if (params && !finite_all(params, INFOLI_NUM_PARAMS)) fail(INFOLI_E_INVALID_ARG, "non-finite parameter");
+        rest_state_host(params ? params : kDefaultParams, v0_mv, out);
+    });
+}
+
+infoli_status infoli_batch_init(const infoli_network_spec* specs, int32_t n_instances,
+                                const infoli_options* opt, infoli_ctx** out) {
+    if (!out) {
+        g_thread_error = "out is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    infoli_ctx* c = new (std::nothrow) infoli_ctx();
+    if (!c) {
+        g_thread_error = "host allocation failed";
+        return INFOLI_E_OUT_OF_MEMORY;
+    }
+    infoli_status st = guarded(nullptr, [&] { build_context(c, specs, n_instances, opt); });
+    if (st != INFOLI_OK) {
+        c->release();
+        delete c;
+        return st;
+    }
+    *out = c;
+    return INFOLI_OK;
+}
+
+infoli_status infoli_init(const infoli_network_spec* spec, const infoli_options* opt, infoli_ctx** out) {
+    return infoli_batch_init(spec, 1, opt, out);
+}
+
+infoli_status infoli_step(infoli_ctx* ctx, int64_t n_steps) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] { run_steps(ctx, n_steps); });
+}
+
+infoli_status infoli_sync(infoli_ctx* ctx) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        HIPX(hipStreamSynchronize(ctx->stream));
+        if (ctx->opt.check_finite) {
+            int32_t flag = 0;
+            HIPX(hipMemcpy(&flag, ctx->d_flags, sizeof(flag), hipMemcpyDeviceToHost));
+            if (flag) fail(INFOLI_E_NUMERIC, "a state value became NaN or infinite");
+        }
+    });
+}
+
+infoli_status infoli_read_state(infoli_ctx* ctx, int32_t instance, float* host_soa, int64_t cap_floats,
+                                int64_t* step_out) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        check_instance(ctx, instance);
+        const InstDesc& d = ctx->inst[instance];
+        if (!host_soa) fail(INFOLI_E_INVALID_ARG, "host_soa is NULL");
+        if (cap_floats < (int64_t)INFOLI_NUM_STATE * d.n)
+            fail(INFOLI_E_INVALID_ARG, "capacity %lld < %lld", (long long)cap_floats,
+                 (long long)INFOLI_NUM_STATE * d.n);
+        HIPX(hipStreamSynchronize(ctx->stream));
+        HIPX(hipMemcpy2D(host_soa, sizeof(float) * d.n, ctx->state[ctx->cur] + d.cell_off,
+                         sizeof(float) * ctx->stride, sizeof(float) * d.n, INFOLI_NUM_STATE,
+                         hipMemcpyDeviceToHost));
+        if (step_out) *step_out = ctx->step;
+    });
+}
+
+infoli_status infoli_read_state_device(infoli_ctx* ctx, int32_t instance, float* dev_soa) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        check_instance(ctx, instance);
+        if (!dev_soa) fail(INFOLI_E_INVALID_ARG, "dev_soa is NULL");
+        const InstDesc& d = ctx->inst[instance];
+        HIPX(hipMemcpy2DAsync(dev_soa, sizeof(float) * d.n, ctx->state[ctx->cur] + d.cell_off,
+                              sizeof(float) * ctx->stride, sizeof(float) * d.n, INFOLI_NUM_STATE,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    });
+}
+
+infoli_status infoli_write_state(infoli_ctx* ctx, int32_t instance, const float* host_soa, int64_t step) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        check_instance(ctx, instance);
+        const InstDesc& d = ctx->inst[instance];
+        if (!host_soa) fail(INFOLI_E_INVALID_ARG, "host_soa is NULL");
+        if (step < 0) fail(INFOLI_E_INVALID_ARG, "step must be >= 0");
+        if (!finite_all(host_soa, (int64_t)INFOLI_NUM_STATE * d.n))
+            fail(INFOLI_E_INVALID_ARG, "non-finite state");
+        HIPX(hipStreamSynchronize(ctx->stream));
+        HIPX(hipMemcpy2D(ctx->state[ctx->cur] + d.cell_off, sizeof(float) * ctx->stride, host_soa,
+                         sizeof(float) * d.n, sizeof(float) * d.n, INFOLI_NUM_STATE,
+                         hipMemcpyHostToDevice));
+        ctx->step = step;
+    });
+}
+
+infoli_status infoli_read_gap_current(infoli_ctx* ctx, int32_t instance, float* host, int64_t cap) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        check_instance(ctx, instance);
+        const InstDesc& d = ctx->inst[instance];
+        if (!host) fail(INFOLI_E_INVALID_ARG, "host is NULL");
+        if (cap < d.n) fail(INFOLI_E_INVALID_ARG, "capacity %lld < %d", (long long)cap, d.n);
+        StepArgs a = make_args(ctx, false);
+        a.gap_only = 1;
+        launch_step(ctx, ctx->stream, a, ctx->cur, ctx->step, 0);
+        HIPX(hipGetLastError());
+        HIPX(hipStreamSynchronize(ctx->stream));
+        HIPX(hipMemcpy(host, ctx->igap + d.cell_off, sizeof(float) * d.n, hipMemcpyDeviceToHost));
+    });
+}
+
+infoli_status infoli_read_spikes(infoli_ctx* ctx, int32_t instance, int32_t* counts, int64_t counts_cap,
+                                 float* times_ms, int64_t times_cap) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        check_instance(ctx, instance);
+        const InstDesc& d = ctx->inst[instance];
+        const int cap = ctx->opt.max_spikes_per_cell;
+        if (!counts) fail(INFOLI_E_INVALID_ARG, "counts is NULL");
+        if (counts_cap < d.n) fail(INFOLI_E_INVALID_ARG, "counts capacity too small");
+        if (times_ms && times_cap < (int64_t)d.n * cap) fail(INFOLI_E_INVALID_ARG, "times capacity too small");
+        HIPX(hipStreamSynchronize(ctx->stream));
+        HIPX(hipMemcpy(counts, ctx->d_spk_count + d.cell_off, sizeof(int32_t) * d.n, hipMemcpyDeviceToHost));
+        if (times_ms && cap > 0)
+            HIPX(hipMemcpy(times_ms, ctx->d_spk_times + d.cell_off * cap, sizeof(float) * d.n * cap,
+                           hipMemcpyDeviceToHost));
+    });
+}
+
+infoli_status infoli_clear_spikes(infoli_ctx* ctx) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        HIPX(hipStreamSynchronize(ctx->stream));
+        HIPX(hipMemset(ctx->d_spk_count, 0, sizeof(int32_t) * ctx->stride));
+        const int cap = std::max(ctx->opt.max_spikes_per_cell, 1);
+        HIPX(hipMemset(ctx->d_spk_times, 0, sizeof(float) * ctx->stride * cap));
+        HIPX(hipDeviceSynchronize());
+    });
+}
+
+infoli_status infoli_get_info(const infoli_ctx* ctx, infoli_info* info) {
+    if (!ctx || !info) {
+        g_thread_error = "ctx or info is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    std::memset(info, 0, sizeof(*info));
+    info->n_instances = ctx->n_inst;
+    info->total_cells = ctx->total_cells;
+    info->pairs_per_step = ctx->pairs_per_step;
+    info->step = ctx->step;
+    info->step_mode = ctx->opt.step_mode;
+    info->n_tiles = (int32_t)ctx->tiles.size();
+    int32_t rows = 0, lanes = 0;
+    for (const Tile& t : ctx->tiles) rows = std::max(rows, t.row1 - t.row0);
+    for (const InstDesc& d : ctx->inst) lanes = std::max(lanes, d.lanes_per_row);
+    info->tile_rows = rows;
+    info->lanes_per_row = lanes;
+    info->device_bytes = (int64_t)ctx->device_bytes;
+    return INFOLI_OK;
+}
+
+infoli_status infoli_last_step_ms(infoli_ctx* ctx, float* ms) {
+    if (!ctx || !ms) {
+        g_thread_error = "ctx or ms is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        if (!ctx->timed) fail(INFOLI_E_STATE, "no step has been timed yet");
+        HIPX(hipEventSynchronize(ctx->ev1));
+        HIPX(hipEventElapsedTime(ms, ctx->ev0, ctx->ev1));
+    });
+}
+
+const char* infoli_state_var_name(int32_t v) {
+    if (v < 0 || v >= INFOLI_NUM_STATE) return nullptr;
+    return kStateNames[v];
+}
+
+const char* infoli_last_error(const infoli_ctx* ctx) {
+    if (ctx) return ctx->err.c_str();
+    return g_thread_error.c_str();
+}
+
+void infoli_destroy(infoli_ctx* ctx) {
+    if (!ctx) return;
+    try {
+        ctx->release();
+    } catch (...) {
+    }
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+// One synchronous simulation step for a list of tiles (Section 2.2): every
+// workgroup takes one tile = a block of consecutive cells of one network,
+// computes their gap-junction currents from the step-n dendritic voltages
+// (Section 2.3, Algorithm 1) and then their compartment update into the
+// step-n+1 buffer. Reads only the step-n buffer and writes only the step-n+1
+// buffer, so the kernel boundary is the step barrier.
+//
+// Gap-current layouts (per network):
+//   UNIFORM_ALL  lanes = receiving cells (64 per tile); the waves of the
+//                workgroup split the sending cells j, whose prescaled Vd is
+//                staged in LDS in chunks and read as wave-wide broadcasts.
+//                w = g is factored out and the linear part 0.2*sum_j dV is
+//                taken in closed form, 0.2*(n*Vd_i - sum_j Vd_j), in fp64.
+//   DENSE        lanes = sending cells j of one row (coalesced weight rows),
+//                one row per wave at a time, butterfly reduction.
+//   CSR          groups of L lanes per row stride over the row's edges and
+//                gather Vd of the neighbours; butterfly reduction per group.
+// Every reduction has a fixed order: results are bitwise reproducible.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cell_model.hpp"
+
+namespace infoli {
+
+enum : int { CONN_NONE = 0, CONN_UNIFORM = 1, CONN_DENSE = 2, CONN_CSR = 3 };
+
+constexpr int kMaxTileRows = 256;   // rows (cells) per tile, any layout
+constexpr int kUniformRows = 64;    // rows per UNIFORM_ALL tile (one per lane)
+constexpr int kChunk = 4096;        // Vd values staged in LDS per pass
+
+// log2(e)/100: exp(-dV^2/100) = 2^(-(dV*a)^2) with a = sqrt(log2(e)/100).
+constexpr float kL2eOver100 = 0.014426950408889634f;
+constexpr float kPreScale = 0.12011224087864498f;      // sqrt(log2(e)/100)
+constexpr float kInvPreScale = 8.325546111576977f;     // 1/kPreScale
+constexpr float kSentinel = 1.0e19f;                   // prescaled pad: term == -0
+
+struct InstDesc {
+    int64_t cell_off;      // flattened index of the network's cell 0
+    int64_t rp_off;        // CSR: offset of the network's row_ptr[0]
+    int64_t w_off;         // DENSE: offset of w[0][0]; CSR: offset of edge 0
+    int64_t stream_off;    // offset of the network's dense input stream, -1 none
+    int64_t stream_steps;
+    int32_t n;
+    int32_t conn;
+    float g;
+    int32_t has_w;         // CSR: per-edge weights present
+    int32_t pulse_off;
+    int32_t n_pulses;
+    int32_t lanes_per_row; // CSR: lanes per row (4..64)
+    int32_t pad0;
+    CellParams p;
+};
+
+struct Tile {
+    int32_t inst;
+    int32_t row0;
+    int32_t row1;
+    int32_t pad0;
+};
+
+struct DevPulse {
+    int64_t n0, n1;        // active for steps n0 <= step < n1
+    float amp;
+    int32_t c0, c1;        // on local cells c0 <= i < c1
+    int32_t pad0;
+};
+
+struct StepArgs {
+    const InstDesc* inst;
+    const Tile* tiles;
+    const DevPulse* pulses;
+    const float* bias;         // [cells]
+    const int64_t* row_ptr;    // CSR row pointers of all networks
+    const int32_t* col;        // CSR columns (local cell index)
+    const float* w;            // DENSE matrices and CSR weights
+    const float* i_stream;     // dense input streams
+    int32_t* spike_count;      // [cells]
+    float* spike_times;        // [cells][spike_cap]
+    int32_t* flags;            // [0]: non-finite state seen
+    float* igap_out;           // gap-only mode: [cells]
+    const int64_t* d_step;     // when set, step = *d_step + step offset
+    int64_t stride;            // state row stride (floats)
+    float dt;
+    int32_t spike_cap;
+    int32_t gap_only;
+    int32_t pad0;
+};
+
+__device__ __forceinline__ float wave_sum_xor(float v, int width) {
+    // butterfly over `width` consecutive lanes (power of two <= 64)
+    for (int m = width >> 1; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ float gap_factor(float dv) {
+    // 0.8*exp(-dv^2/100) + 0.2 via the hardware 2^x
+    return fmaf(0.8f, __builtin_amdgcn_exp2f(-(dv * dv) * kL2eOver100), 0.2f);
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                            const float* __restrict__ vd, float* s_ig,
+                                            float4* s_v4, float* s_part, double* s_red) {
+    constexpr int W = BLOCK / 64;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nrows = t.row1 - t.row0;
+    const int n = d.n;
+    const bool valid = lane < nrows;
+    const float vi = valid ? vd[t.row0 + lane] : 0.0f;
+    const float vis = vi * kPreScale;
+    float* s_v = reinterpret_cast<float*>(s_v4);
+    float acc0 = 0.0f, acc1 = 0.0f;
+    double vsum = 0.0;
+    for (int c0 = 0; c0 < n; c0 += kChunk) {
+        const int cn = min(kChunk, n - c0);
+        // per-wave share, a multiple of 8 values; the tail is padded with a
+        // sentinel whose term is exactly -0
+        const int per = (((cn + W - 1) / W) + 7) & ~7;
+        __syncthreads();
+        for (int k = threadIdx.x; k < W * per; k += BLOCK) {
+            if (k < cn) {
+                const float v = vd[c0 + k];
+                s_v[k] = v * kPreScale;
+                vsum += (double)v;
+            } else {
+                s_v[k] = kSentinel;
+            }
+        }
+        __syncthreads();
+        const float4* p = s_v4 + (wave * per) / 4;
+        for (int q = 0; q < per / 4; q += 2) {
+            const float4 u = p[q];
+            const float4 v = p[q + 1];
+            float d0 = vis - u.x, d1 = vis - u.y, d2 = vis - u.z, d3 = vis - u.w;
+            acc0 = fmaf(d0, __builtin_amdgcn_exp2f(-(d0 * d0)), acc0);
+            acc1 = fmaf(d1, __builtin_amdgcn_exp2f(-(d1 * d1)), acc1);
+            acc0 = fmaf(d2, __builtin_amdgcn_exp2f(-(d2 * d2)), acc0);
+            acc1 = fmaf(d3, __builtin_amdgcn_exp2f(-(d3 * d3)), acc1);
+            d0 = vis - v.x; d1 = vis - v.y; d2 = vis - v.z; d3 = vis - v.w;
+            acc0 = fmaf(d0, __builtin_amdgcn_exp2f(-(d0 * d0)), acc0);
+            acc1 = fmaf(d1, __builtin_amdgcn_exp2f(-(d1 * d1)), acc1);
+            acc0 = fmaf(d2, __builtin_amdgcn_exp2f(-(d2 * d2)), acc0);
+            acc1 = fmaf(d3, __builtin_amdgcn_exp2f(-(d3 * d3)), acc1);
+        }
+    }
+    s_part[wave * 64 + lane] = acc0 + acc1;
+    // fixed-order reduction of sum_j Vd_j (fp64)
+    for (int m = 32; m > 0; m >>= 1) vsum += __shfl_xor(vsum, m, 64);
+    if (lane == 0) s_red[wave] = vsum;
+    __syncthreads();
+    if (threadIdx.x < 64 && valid) {
+        float e = 0.0f;
+        for (int w = 0; w < W; ++w) e += s_part[w * 64 + lane];
+        double tot = 0.0;
+        for (int w = 0; w < W; ++w) tot += s_red[w];
+        const float lin = (float)((double)n * (double)vi - tot);
+        s_ig[lane] = d.g * (0.8f * (e * kInvPreScale) + 0.2f * lin);
+    }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void gap_dense(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                          const float* __restrict__ vd, float* s_ig) {
+    constexpr int W = BLOCK / 64;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = d.n;
+    for (int r = t.row0 + wave; r < t.row1; r += W) {
+        const float vi = vd[r];
+        const float* wr = a.w + d.w_off + (int64_t)r * n;
+        float acc = 0.0f;
+        for (int j = lane; j < n; j += 64) {
+            const float dv = vi - vd[j];
+            acc = fmaf(wr[j], dv * gap_factor(dv), acc);
+        }
+        acc = wave_sum_xor(acc, 64);
+        if (lane == 0) s_ig[r - t.row0] = acc;
+    }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                        const float* __restrict__ vd, float* s_ig) {
+    const int L = d.lanes_per_row;
+    const int groups = BLOCK / L;
+    const int grp = threadIdx.x / L;
+    const int lig = threadIdx.x % L;
+    const int64_t* rp = a.row_ptr + d.rp_off;
+    const int32_t* col = a.col + d.w_off;
+    const float* wv = a.w + d.w_off;
+    for (int r0 = t.row0; r0 < t.row1; r0 += groups) {
+        const int r = r0 + grp;
+        float acc = 0.0f;
+        if (r < t.row1) {
+            const float vi = vd[r];
+            const int64_t b = rp[r], e = rp[r + 1];
+            if (d.has_w) {
+                for (int64_t k = b + lig; k < e; k += L) {
+                    const float dv = vi - vd[col[k]];
+                    acc = fmaf(wv[k], dv * gap_factor(dv), acc);
+                }
+            } else {
+                for (int64_t k = b + lig; k < e; k += L) {
+                    const float dv = vi - vd[col[k]];
+                    acc = fmaf(dv, gap_factor(dv), acc);
+                }
+            }
+        }
+        // all lanes of a group run the butterfly together
+        acc = wave_sum_xor(acc, L);
+        if (r < t.row1 && lig == 0) s_ig[r - t.row0] = d.has_w ? acc : d.g * acc;
+    }
+}
+
+__device__ __forceinline__ float evoked_input(const StepArgs& a, const InstDesc& d, int64_t step,
+                                              int li, int64_t cell) {
+    float iapp = a.bias[cell];
+    for (int k = 0; k < d.n_pulses; ++k) {
+        const DevPulse pl = a.pulses[d.pulse_off + k];
+        if (step >= pl.n0 && step < pl.n1 && li >= pl.c0 && li < pl.c1) iapp += pl.amp;
+    }
+    if (d.stream_off >= 0 && step >= 0 && step < d.stream_steps)
+        iapp += a.i_stream[d.stream_off + step * (int64_t)d.n + li];
+    return iapp;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restrict__ xin,
+                                                float* __restrict__ xout, int64_t step_arg,
+                                                int32_t step_off) {
+    __shared__ float s_ig[kMaxTileRows];
+    __shared__ float4 s_v4[(kChunk + 8 * (BLOCK / 64)) / 4];
+    __shared__ float s_part[BLOCK];
+    __shared__ double s_red[BLOCK / 64];
+
+    const Tile t = a.tiles[blockIdx.x];
+    const InstDesc& d = a.inst[t.inst];
+    const int64_t step = (a.d_step ? *a.d_step : step_arg) + step_off;
+    const float* vd = xin + (int64_t)SV_VD * a.stride + d.cell_off;
+    const int nrows = t.row1 - t.row0;
+
+    switch (d.conn) {
+        case CONN_UNIFORM: gap_uniform<BLOCK>(a, d, t, vd, s_ig, s_v4, s_part, s_red); break;
+        case CONN_DENSE: gap_dense<BLOCK>(a, d, t, vd, s_ig); break;
+        case CONN_CSR: gap_csr<BLOCK>(a, d, t, vd, s_ig); break;
+        default:
+            for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
+            break;
+    }
+    __syncthreads();
+
+    for (int k = threadIdx.x; k < nrows; k += BLOCK) {
+        const int li = t.row0 + k;
+        const int64_t cell = d.cell_off + li;
+        if (a.gap_only) {
+            a.igap_out[cell] = s_ig[k];
+            continue;
+        }
+        float x[NSV], y[NSV];
+#pragma unroll
+        for (int v = 0; v < NSV; ++v) x[v] = xin[v * a.stride + cell];
+        const float iapp = evoked_input(a, d, step, li, cell);
+        cell_step(d.p, x, s_ig[k], iapp, a.dt, y);
+        float chk = 0.0f;
+#pragma unroll
+        for (int v = 0; v < NSV; ++v) {
+            xout[v * a.stride + cell] = y[v];
+            chk += y[v];
+        }
+        if (!isfinite(chk)) atomicOr(a.flags, 1);
+        // axon output: upward 0 mV crossing, time interpolated within the step
+        if (x[SV_VA] < 0.0f && y[SV_VA] >= 0.0f) {
+            const int c = a.spike_count[cell];
+            if (a.spike_cap > 0) {
+                const float frac = (0.0f - x[SV_VA]) / (y[SV_VA] - x[SV_VA]);
+                a.spike_times[cell * a.spike_cap + (c % a.spike_cap)] = ((float)step + frac) * a.dt;
+            }
+            a.spike_count[cell] = c + 1;
+        }
+    }
+}
+
+__global__ void k_set_step(int64_t* d_step, int64_t value) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_step = value;
+}
+
+}  // namespace infoli
