@@ -54,19 +54,46 @@ def build_workload(name):
     return nets, desc
 
 
+# Uniform all-to-all kernel: per directed pair one v_sub, one v_mul, one
+# v_exp_f32 and one v_fma (w = g factored out, the linear 0.2*dV part in
+# closed form). Full-rate VALU ops cost 1 lane-slot, the transcendental
+# v_exp_f32 costs EXP_SLOTS (quarter rate); 256 CUs x 64 lanes x 2.4 GHz.
+LANE_SLOTS_PER_S = 256 * 64 * 2.4e9
+EXP_SLOTS = 4
+UNIFORM_SLOTS_PER_PAIR = 3 + EXP_SLOTS
+
+
 def algorithmic_bytes(nets):
     """Bytes one step launch must move at minimum: per cell 14 state floats in
-    and out plus the bias (116 B); per CSR edge its int32 column (4 B; the
-    weight is the network's uniform g); per CSR row its row pointer (8 B).
-    Gathered neighbour voltages are cache hits and not counted."""
+    and out plus the bias (116 B); per CSR edge its column in the streamed
+    format (uint16 when every network has <= 65,536 cells, else int32) plus
+    its fp32 weight when the network has per-edge weights; per CSR row its
+    row pointer (8 B). Gathered neighbour voltages are cache hits and not
+    counted."""
+    col_b = 2 if all(n.n <= 65536 for n in nets if n.conn == "csr") else 4
     b = 0
     for n in nets:
         b += 116 * n.n
         if n.conn == "csr":
-            b += 4 * int(n.row_ptr[-1]) + 8 * n.n
+            b += (col_b + (4 if n.w_csr is not None else 0)) * int(n.row_ptr[-1]) + 8 * n.n
         elif n.conn == "dense":
             b += 4 * n.n * n.n
     return b
+
+
+def roofline(nets, launch_s):
+    if all(n.conn == "uniform" for n in nets):
+        pairs = sum(n.n * n.n for n in nets)       # the kernel evaluates the diagonal too
+        achieved = pairs / launch_s / 1e9
+        peak = LANE_SLOTS_PER_S / UNIFORM_SLOTS_PER_PAIR / 1e9
+        return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
+                "frac": achieved / peak, "traffic": None, "kernel": "infoli::k_step<256>",
+                "slots_per_pair": UNIFORM_SLOTS_PER_PAIR, "pairs_per_launch": pairs}
+    abytes = algorithmic_bytes(nets)
+    achieved = abytes / launch_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "infoli::k_step<256>",
+            "algorithmic_bytes_per_launch": abytes}
 
 
 def cpu_baseline(nets, budget_s=15.0):
@@ -133,8 +160,6 @@ def main():
     pairs = sum(n.pairs_per_step() for n in nets)
     cell_steps_s = cells * steps / wall
     launch_s = dev_ms * 1e-3 / steps        # one step kernel launch per step
-    abytes = algorithmic_bytes(nets)
-    achieved = abytes / launch_s / 1e9
     out = {
         "metric": "cell-steps/sec (plain InfOli step, gap junctions + compartments)",
         "value": cell_steps_s,
@@ -153,9 +178,7 @@ def main():
                    "tiles": info["n_tiles"], "lanes_per_row": info["lanes_per_row"]},
         "gap_pairs_per_s": pairs * steps / wall,
         "device_ms_per_step": dev_ms / steps,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "infoli::k_step<256>", "algorithmic_bytes_per_launch": abytes},
+        "roofline": roofline(nets, launch_s),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)

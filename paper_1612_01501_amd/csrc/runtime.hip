@@ -144,6 +144,7 @@ struct infoli_ctx {
     DevPulse* d_pulses = nullptr;
     int64_t* d_rowptr = nullptr;
     int32_t* d_col = nullptr;
+    uint16_t* d_col16 = nullptr;
     float* d_w = nullptr;
     float* d_stream = nullptr;
     int32_t* d_spk_count = nullptr;
@@ -362,20 +363,47 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->total_cells = cells;
     c->stride = (cells + 63) & ~int64_t(63);
 
-    // ---- tiles: blocks of consecutive rows of one network
+    // ---- per-network kernel layout and tiles (blocks of consecutive rows)
+    bool col16 = col_total > 0;
+    for (int k = 0; k < ninst; ++k)
+        if (c->inst[k].conn == CONN_CSR && c->inst[k].n > 65536) col16 = false;
+    std::vector<int> rows_of(ninst);
     for (int k = 0; k < ninst; ++k) {
-        const InstDesc& d = c->inst[k];
+        InstDesc& d = c->inst[k];
         int rows;
         switch (d.conn) {
             case CONN_UNIFORM: rows = kUniformRows; break;
-            case CONN_DENSE: rows = 16; break;
-            case CONN_CSR: rows = c->opt.tile_rows ? c->opt.tile_rows : std::max(4, c->block / d.lanes_per_row); break;
-            default: rows = kMaxTileRows; break;
+            case CONN_DENSE: rows = c->opt.tile_rows ? c->opt.tile_rows : 16; break;
+            case CONN_CSR: {
+                const double deg = (double)specs[k].nnz / d.n;
+                const int per_pass = c->block / d.lanes_per_row;
+                // about 16k edges per tile, whole passes of row groups
+                int r = deg > 0 ? (int)(16384.0 / deg) : kMaxTileRows;
+                r = std::max(per_pass, std::min(kMaxTileRows, (r / per_pass) * per_pass));
+                rows = c->opt.tile_rows ? c->opt.tile_rows : r;
+                d.col16 = col16 ? 1 : 0;
+                d.vd_lds = (d.n <= kChunk && (double)rows * deg >= 2.0 * d.n) ? 1 : 0;
+                break;
+            }
+            default: rows = c->opt.tile_rows ? c->opt.tile_rows : kMaxTileRows; break;
         }
-        if (c->opt.tile_rows && d.conn != CONN_UNIFORM) rows = c->opt.tile_rows;
-        rows = std::min(rows, kMaxTileRows);
-        for (int r = 0; r < d.n; r += rows) c->tiles.push_back(Tile{k, r, std::min(d.n, r + rows), 0});
+        rows_of[k] = std::min(rows, kMaxTileRows);
     }
+    // estimated cost of a tile (issue slots): the longest tiles go first
+    std::vector<std::pair<double, Tile>> planned;
+    for (int k = 0; k < ninst; ++k) {
+        const InstDesc& d = c->inst[k];
+        const double deg = d.conn == CONN_CSR ? (double)specs[k].nnz / d.n
+                         : (d.conn == CONN_NONE ? 0.0 : (double)d.n);
+        for (int r = 0; r < d.n; r += rows_of[k]) {
+            const int r1 = std::min(d.n, r + rows_of[k]);
+            const double cost = (r1 - r) * (deg * 8.0 + 400.0);
+            planned.push_back({cost, Tile{k, r, r1, 0}});
+        }
+    }
+    std::stable_sort(planned.begin(), planned.end(),
+                     [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (const auto& pt : planned) c->tiles.push_back(pt.second);
     if (c->tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
 
     // ---- stream
@@ -438,7 +466,16 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->d_tiles = c->alloc<Tile>(c->tiles.size());
     c->d_pulses = c->alloc<DevPulse>(h_pulses.size());
     c->d_rowptr = c->alloc<int64_t>(h_rp.size());
-    c->d_col = c->alloc<int32_t>(h_col.size());
+    if (col16) {
+        std::vector<uint16_t> h_c16(h_col.size());
+        for (size_t e = 0; e < h_col.size(); ++e) h_c16[e] = (uint16_t)h_col[e];
+        c->d_col16 = c->alloc<uint16_t>(h_c16.size());
+        HIPX(hipMemcpy(c->d_col16, h_c16.data(), sizeof(uint16_t) * h_c16.size(), hipMemcpyHostToDevice));
+        c->d_col = c->alloc<int32_t>(1);
+    } else {
+        c->d_col = c->alloc<int32_t>(h_col.size());
+        c->d_col16 = c->alloc<uint16_t>(1);
+    }
     c->d_w = c->alloc<float>(h_w.size());
     c->d_stream = c->alloc<float>(h_stream.size());
     c->d_spk_count = c->alloc<int32_t>(S);
@@ -454,7 +491,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     HIPX(hipMemcpy(c->d_tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(), hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->d_pulses, h_pulses.data(), sizeof(DevPulse) * h_pulses.size(), hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->d_rowptr, h_rp.data(), sizeof(int64_t) * h_rp.size(), hipMemcpyHostToDevice));
-    HIPX(hipMemcpy(c->d_col, h_col.data(), sizeof(int32_t) * h_col.size(), hipMemcpyHostToDevice));
+    if (!col16)
+        HIPX(hipMemcpy(c->d_col, h_col.data(), sizeof(int32_t) * h_col.size(), hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->d_w, h_w.data(), sizeof(float) * h_w.size(), hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->d_stream, h_stream.data(), sizeof(float) * h_stream.size(), hipMemcpyHostToDevice));
     HIPX(hipMemset(c->d_spk_count, 0, sizeof(int32_t) * S));
@@ -473,6 +511,7 @@ StepArgs make_args(const infoli_ctx* c, bool device_step) {
     a.bias = c->bias;
     a.row_ptr = c->d_rowptr;
     a.col = c->d_col;
+    a.col16 = c->d_col16;
     a.w = c->d_w;
     a.i_stream = c->d_stream;
     a.spike_count = c->d_spk_count;

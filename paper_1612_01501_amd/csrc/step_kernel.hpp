@@ -14,7 +14,11 @@
 //   DENSE        lanes = sending cells j of one row (coalesced weight rows),
 //                one row per wave at a time, butterfly reduction.
 //   CSR          groups of L lanes per row stride over the row's edges and
-//                gather Vd of the neighbours; butterfly reduction per group.
+//                gather Vd of the neighbours, from a copy of the network's
+//                Vd staged in LDS when the tile's edges outnumber the cells,
+//                else from global memory; columns are 16-bit when every
+//                network has at most 65,536 cells. Butterfly reduction per
+//                group.
 // Every reduction has a fixed order: results are bitwise reproducible.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -28,7 +32,7 @@ enum : int { CONN_NONE = 0, CONN_UNIFORM = 1, CONN_DENSE = 2, CONN_CSR = 3 };
 
 constexpr int kMaxTileRows = 256;   // rows (cells) per tile, any layout
 constexpr int kUniformRows = 64;    // rows per UNIFORM_ALL tile (one per lane)
-constexpr int kChunk = 4096;        // Vd values staged in LDS per pass
+constexpr int kChunk = 8192;        // Vd values staged in LDS per pass
 
 // log2(e)/100: exp(-dV^2/100) = 2^(-(dV*a)^2) with a = sqrt(log2(e)/100).
 constexpr float kL2eOver100 = 0.014426950408889634f;
@@ -49,7 +53,9 @@ struct InstDesc {
     int32_t pulse_off;
     int32_t n_pulses;
     int32_t lanes_per_row; // CSR: lanes per row (4..64)
-    int32_t pad0;
+    int32_t vd_lds;        // CSR: stage the network's Vd in LDS (n <= kChunk)
+    int32_t col16;         // CSR: columns stored as uint16
+    int32_t pad0[3];
     CellParams p;
 };
 
@@ -74,6 +80,7 @@ struct StepArgs {
     const float* bias;         // [cells]
     const int64_t* row_ptr;    // CSR row pointers of all networks
     const int32_t* col;        // CSR columns (local cell index)
+    const uint16_t* col16;     // CSR columns, 16-bit form
     const float* w;            // DENSE matrices and CSR weights
     const float* i_stream;     // dense input streams
     int32_t* spike_count;      // [cells]
@@ -181,37 +188,69 @@ __device__ __forceinline__ void gap_dense(const StepArgs& a, const InstDesc& d, 
     }
 }
 
-template <int BLOCK>
-__device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
-                                        const float* __restrict__ vd, float* s_ig) {
+template <int BLOCK, bool LDS, bool C16, bool HASW>
+__device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                             const float* __restrict__ vd, const float* s_vd,
+                                             float* s_ig) {
     const int L = d.lanes_per_row;
     const int groups = BLOCK / L;
     const int grp = threadIdx.x / L;
     const int lig = threadIdx.x % L;
     const int64_t* rp = a.row_ptr + d.rp_off;
-    const int32_t* col = a.col + d.w_off;
+    const int32_t* c32 = a.col + d.w_off;
+    const uint16_t* c16 = a.col16 + d.w_off;
     const float* wv = a.w + d.w_off;
+    auto col_at = [&](int64_t k) -> int { return C16 ? (int)c16[k] : c32[k]; };
+    auto v_at = [&](int j) -> float { return LDS ? s_vd[j] : vd[j]; };
+    auto term = [&](int64_t k, float vi, int j) -> float {
+        const float dv = vi - v_at(j);
+        return HASW ? wv[k] * (dv * gap_factor(dv)) : dv * gap_factor(dv);
+    };
     for (int r0 = t.row0; r0 < t.row1; r0 += groups) {
         const int r = r0 + grp;
-        float acc = 0.0f;
+        float acc0 = 0.0f, acc1 = 0.0f;
         if (r < t.row1) {
-            const float vi = vd[r];
-            const int64_t b = rp[r], e = rp[r + 1];
-            if (d.has_w) {
-                for (int64_t k = b + lig; k < e; k += L) {
-                    const float dv = vi - vd[col[k]];
-                    acc = fmaf(wv[k], dv * gap_factor(dv), acc);
-                }
-            } else {
-                for (int64_t k = b + lig; k < e; k += L) {
-                    const float dv = vi - vd[col[k]];
-                    acc = fmaf(dv, gap_factor(dv), acc);
-                }
+            const float vi = v_at(r);
+            const int64_t e = rp[r + 1];
+            int64_t k = rp[r] + lig;
+            // four independent edges per lane per iteration keep loads in flight
+            for (; k + 3 * L < e; k += 4 * L) {
+                const int j0 = col_at(k), j1 = col_at(k + L), j2 = col_at(k + 2 * L),
+                          j3 = col_at(k + 3 * L);
+                acc0 += term(k, vi, j0);
+                acc1 += term(k + L, vi, j1);
+                acc0 += term(k + 2 * L, vi, j2);
+                acc1 += term(k + 3 * L, vi, j3);
             }
+            for (; k < e; k += L) acc0 += term(k, vi, col_at(k));
         }
         // all lanes of a group run the butterfly together
-        acc = wave_sum_xor(acc, L);
-        if (r < t.row1 && lig == 0) s_ig[r - t.row0] = d.has_w ? acc : d.g * acc;
+        float acc = wave_sum_xor(acc0 + acc1, L);
+        if (r < t.row1 && lig == 0) s_ig[r - t.row0] = HASW ? acc : d.g * acc;
+    }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                        const float* __restrict__ vd, float* s_vd, float* s_ig) {
+    if (d.vd_lds) {
+        for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k];
+        __syncthreads();
+        if (d.col16) {
+            if (d.has_w) gap_csr_impl<BLOCK, true, true, true>(a, d, t, vd, s_vd, s_ig);
+            else gap_csr_impl<BLOCK, true, true, false>(a, d, t, vd, s_vd, s_ig);
+        } else {
+            if (d.has_w) gap_csr_impl<BLOCK, true, false, true>(a, d, t, vd, s_vd, s_ig);
+            else gap_csr_impl<BLOCK, true, false, false>(a, d, t, vd, s_vd, s_ig);
+        }
+    } else {
+        if (d.col16) {
+            if (d.has_w) gap_csr_impl<BLOCK, false, true, true>(a, d, t, vd, s_vd, s_ig);
+            else gap_csr_impl<BLOCK, false, true, false>(a, d, t, vd, s_vd, s_ig);
+        } else {
+            if (d.has_w) gap_csr_impl<BLOCK, false, false, true>(a, d, t, vd, s_vd, s_ig);
+            else gap_csr_impl<BLOCK, false, false, false>(a, d, t, vd, s_vd, s_ig);
+        }
     }
 }
 
@@ -245,7 +284,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
     switch (d.conn) {
         case CONN_UNIFORM: gap_uniform<BLOCK>(a, d, t, vd, s_ig, s_v4, s_part, s_red); break;
         case CONN_DENSE: gap_dense<BLOCK>(a, d, t, vd, s_ig); break;
-        case CONN_CSR: gap_csr<BLOCK>(a, d, t, vd, s_ig); break;
+        case CONN_CSR: gap_csr<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_ig); break;
         default:
             for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
             break;

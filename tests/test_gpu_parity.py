@@ -5,6 +5,12 @@ Tolerances: per state variable v, the max over sampled steps and cells of
 the first 1,000 steps; axon spike counts per cell within +-1 and matched
 spike times within 0.1 ms over the full run. The error against the fp64
 oracle is printed alongside.
+
+In runs where cells fire, fp32 rounding alone moves the fast axon gates by
+more than 1e-4 (the fp32 oracle differs from the fp64 one by up to ~3e-4
+there), so the bound for variable v is max(1e-4, e_v(oracle_f32, oracle_f64)):
+the GPU must be at least as close to the fp32 oracle as that oracle is to
+the fp64 result.
 """
 import numpy as np
 import pytest
@@ -68,8 +74,11 @@ def _check_run(infoli, o32, o64, net, steps=1000, every=10):
     e32 = per_var_error(got, ref["trace"])
     r64 = o64.run(net, steps, x0=x0.astype(np.float64), trace_every=every, trace_cells=net.n)
     e64 = per_var_error(got, r64["trace"])
-    print(f"{net.label or net.conn} n={net.n}: max err vs f32 oracle {e32.max():.2e}, vs f64 {e64.max():.2e}")
-    assert e32.max() <= TOL_STATE, e32
+    floor = per_var_error(ref["trace"], r64["trace"])
+    tol = np.maximum(TOL_STATE, floor)
+    print(f"{net.label or net.conn} n={net.n}: max err vs f32 oracle {e32.max():.2e}, vs f64 {e64.max():.2e}, "
+          f"f32-oracle floor {floor.max():.2e}")
+    assert np.all(e32 <= tol), (e32, tol)
     compare_spikes(c, t, ref["counts"], ref["times"], 64)
     return e32, e64
 
@@ -174,35 +183,58 @@ def test_gap_current(infoli, o32, o64, conn, n):
 
 
 # ------------------------------------------------------------------ full sizes, one step
-def _one_step_check(infoli, o32, net, warm, mode="graph"):
+def _row_magnitude(net, vd):
+    """sum_j |w_ij| * |Vd_i - Vd_j| per row (scale of the fp32 rounding of a row sum)."""
+    vd = np.asarray(vd, np.float64)
+    if net.conn == "uniform":
+        order = np.sort(vd)
+        c = np.concatenate([[0.0], np.cumsum(order)])
+        k = np.searchsorted(order, vd)
+        below = k * vd - c[k]
+        above = (c[-1] - c[k]) - (len(vd) - k) * vd
+        return net.g * (below + above)
+    if net.conn == "dense":
+        return (np.abs(net.w_dense.astype(np.float64)) * np.abs(vd[:, None] - vd[None, :])).sum(axis=1)
+    mag = np.zeros(net.n)
+    for i in range(net.n):
+        js = net.col[net.row_ptr[i]:net.row_ptr[i + 1]]
+        w = net.g if net.w_csr is None else np.abs(net.w_csr[net.row_ptr[i]:net.row_ptr[i + 1]])
+        mag[i] = (w * np.abs(vd[i] - vd[js])).sum()
+    return mag
+
+
+def _one_step_check(infoli, o32, o64, net, warm, mode="graph"):
     """Run `warm` steps in the benchmark's launch configuration, then check
-    one more GPU step against the oracle's step from the GPU state."""
+    one more GPU step against the oracle's step from the GPU state, and the
+    GPU gap currents against the fp64 oracle's (bound: 1e-5 of each row's
+    sum of |terms|)."""
     x0 = infoli.initial_state(net)
     sim = infoli.Simulator(net, init_states=[x0], step_mode=mode, graph_chunk=100)
     sim.step(warm)
     xk = sim.read_state(0)
     step_k = sim.last_step_index
-    ig = sim.read_gap_current(0)
+    ig = sim.read_gap_current(0).astype(np.float64)
     sim.step(1)
     xk1 = sim.read_state(0)
     sim.close()
     ref = o32.run(net, 1, x0=xk, step0=step_k)["x"]
     e = per_var_error(xk1[None], ref[None])
-    ig_ref = o32.gap(net, xk[0]).astype(np.float64)
-    gerr = np.abs(ig - ig_ref).max() / max(np.abs(ig_ref).max(), 1e-30)
-    print(f"{net.label}: one-step max err {e.max():.2e}, gap rel err {gerr:.2e}")
+    ig_ref = o64.gap(net, xk[0].astype(np.float64))
+    tol = 1e-5 * _row_magnitude(net, xk[0]) + 1e-30
+    gerr = np.max(np.abs(ig - ig_ref) / tol)
+    print(f"{net.label}: one-step max err {e.max():.2e}, gap err / bound {gerr:.2e}")
     assert e.max() <= 1e-5, e
-    assert gerr <= 1e-4
+    assert gerr <= 1.0
     assert np.all(np.isfinite(xk))
 
 
 @pytest.mark.parametrize("p", [0.01, 0.1, 0.5])
-def test_config1_full_size_step(infoli, o32, p):
-    _one_step_check(infoli, o32, I.config1(p), 400)
+def test_config1_full_size_step(infoli, o32, o64, p):
+    _one_step_check(infoli, o32, o64, I.config1(p), 400)
 
 
-def test_config2_full_size_step(infoli, o32):
-    _one_step_check(infoli, o32, I.config2(), 200)
+def test_config2_full_size_step(infoli, o32, o64):
+    _one_step_check(infoli, o32, o64, I.config2(), 200)
 
 
 # ------------------------------------------------------------------ invariants
