@@ -123,7 +123,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="csr4096", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="graph", choices=["graph", "launch", "auto"])
+    ap.add_argument("--mode", default="auto", choices=["graph", "launch", "auto", "persistent"])
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)

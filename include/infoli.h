@@ -138,7 +138,7 @@ typedef struct infoli_options {
     int32_t graph_chunk;         /* steps per captured graph (GRAPH mode), >= 2, even      */
     int32_t max_spikes_per_cell; /* spike times kept per cell (ring); 0 => counts only     */
     int32_t tile_rows;           /* 0 => tuned; else rows per workgroup tile               */
-    int32_t lanes_per_row;       /* 0 => tuned; CSR/dense lanes per row: 4..64, power of 2 */
+    int32_t lanes_per_row;       /* 0 => tuned; CSR lanes per row: 4..256, power of 2     */
     int32_t check_finite;        /* 1 => a NaN/Inf state makes infoli_sync fail            */
 } infoli_options;
 

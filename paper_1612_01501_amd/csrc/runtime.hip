@@ -16,6 +16,7 @@
 #include "../../include/infoli.h"
 #include "cell_model.hpp"
 #include "step_kernel.hpp"
+#include "persist_kernel.hpp"
 
 using namespace infoli;
 
@@ -131,6 +132,7 @@ struct infoli_ctx {
     int64_t pairs_per_step = 0;
     float dt = 0.05f;
     int block = 256;
+    int persist_cpt = 1;            // cells per thread of the persistent kernel
 
     // device memory
     std::vector<void*> allocs;
@@ -273,12 +275,12 @@ void validate_spec(const infoli_network_spec& s, int k) {
     }
 }
 
-int pick_lanes(double mean_degree) {
-    if (mean_degree >= 48) return 64;
-    if (mean_degree >= 24) return 32;
-    if (mean_degree >= 12) return 16;
-    if (mean_degree >= 6) return 8;
-    return 4;
+// Lanes per CSR row: about eight edges per lane, so that one batch of
+// independent loads covers most rows.
+int pick_lanes(double mean_degree, int block) {
+    int L = 4;
+    while (L < block && L * 8 < mean_degree) L *= 2;
+    return L;
 }
 
 void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t ninst,
@@ -288,16 +290,14 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     if (opt) c->opt = *opt;
     if (c->opt.step_mode < 0 || c->opt.step_mode > INFOLI_MODE_PERSISTENT)
         fail(INFOLI_E_INVALID_ARG, "unknown step_mode %d", c->opt.step_mode);
-    if (c->opt.step_mode == INFOLI_MODE_PERSISTENT)
-        fail(INFOLI_E_UNSUPPORTED, "PERSISTENT step mode is not available in this build");
     if (c->opt.graph_chunk < 2 || (c->opt.graph_chunk & 1))
         fail(INFOLI_E_INVALID_ARG, "graph_chunk must be even and >= 2");
     if (c->opt.max_spikes_per_cell < 0 || c->opt.max_spikes_per_cell > 4096)
         fail(INFOLI_E_INVALID_ARG, "max_spikes_per_cell must be in [0, 4096]");
     if (c->opt.lanes_per_row != 0 &&
-        (c->opt.lanes_per_row < 4 || c->opt.lanes_per_row > 64 ||
+        (c->opt.lanes_per_row < 4 || c->opt.lanes_per_row > 256 ||
          (c->opt.lanes_per_row & (c->opt.lanes_per_row - 1))))
-        fail(INFOLI_E_INVALID_ARG, "lanes_per_row must be 0 or a power of two in [4, 64]");
+        fail(INFOLI_E_INVALID_ARG, "lanes_per_row must be 0 or a power of two in [4, 256]");
     if (c->opt.tile_rows < 0 || c->opt.tile_rows > kMaxTileRows)
         fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
     for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
@@ -316,7 +316,11 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->n_inst = ninst;
     c->dt = specs[0].dt_ms;
     c->step = specs[0].step0;
+    // 1024-thread workgroups when all-to-all rows dominate (16 waves share the
+    // sender range of a 64-row tile); 256 otherwise
     c->block = 256;
+    for (int k = 0; k < ninst; ++k)
+        if (specs[k].conn == INFOLI_CONN_UNIFORM_ALL && specs[k].n_cells >= 2048) c->block = 1024;
 
     // ---- layout of the flattened networks
     int64_t cells = 0, rp_total = 0, w_total = 0, col_total = 0, stream_total = 0;
@@ -344,7 +348,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
             col_total += s.nnz;
             d.has_w = s.w_csr ? 1 : 0;
             const double deg = (double)s.nnz / s.n_cells;
-            d.lanes_per_row = c->opt.lanes_per_row ? c->opt.lanes_per_row : pick_lanes(deg);
+            d.lanes_per_row = std::min(c->block, c->opt.lanes_per_row ? c->opt.lanes_per_row : pick_lanes(deg, c->block));
             c->pairs_per_step += s.nnz;
         } else if (s.conn == INFOLI_CONN_UNIFORM_ALL) {
             c->pairs_per_step += (int64_t)s.n_cells * (s.n_cells - 1);
@@ -360,6 +364,15 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     }
     if (w_total > 0 && col_total > 0)
         fail(INFOLI_E_UNSUPPORTED, "a batch may not mix DENSE and CSR networks");
+    int32_t max_n = 0;
+    for (int k = 0; k < ninst; ++k) max_n = std::max(max_n, specs[k].n_cells);
+    if (c->opt.step_mode == INFOLI_MODE_PERSISTENT && max_n > kPersistCells)
+        fail(INFOLI_E_UNSUPPORTED, "PERSISTENT mode holds networks of at most %d cells (largest: %d)",
+             kPersistCells, max_n);
+    if (c->opt.step_mode == INFOLI_MODE_AUTO && ninst == 1 && max_n <= 1024)
+        c->opt.step_mode = INFOLI_MODE_PERSISTENT;   // real-time sized network: one workgroup
+    c->persist_cpt = 1;
+    while (c->persist_cpt * kPersistBlock < max_n) c->persist_cpt *= 2;
     c->total_cells = cells;
     c->stride = (cells + 63) & ~int64_t(63);
 
@@ -376,11 +389,9 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
             case CONN_DENSE: rows = c->opt.tile_rows ? c->opt.tile_rows : 16; break;
             case CONN_CSR: {
                 const double deg = (double)specs[k].nnz / d.n;
-                const int per_pass = c->block / d.lanes_per_row;
-                // about 16k edges per tile, whole passes of row groups
-                int r = deg > 0 ? (int)(16384.0 / deg) : kMaxTileRows;
-                r = std::max(per_pass, std::min(kMaxTileRows, (r / per_pass) * per_pass));
-                rows = c->opt.tile_rows ? c->opt.tile_rows : r;
+                // one pass of row groups per tile: short dependent-load chains
+                const int per_pass = std::max(1, c->block / d.lanes_per_row);
+                rows = c->opt.tile_rows ? c->opt.tile_rows : std::min(kMaxTileRows, per_pass);
                 d.col16 = col16 ? 1 : 0;
                 d.vd_lds = (d.n <= kChunk && (double)rows * deg >= 2.0 * d.n) ? 1 : 0;
                 break;
@@ -528,8 +539,12 @@ StepArgs make_args(const infoli_ctx* c, bool device_step) {
 
 void launch_step(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
                  int32_t off) {
-    hipLaunchKernelGGL(k_step<256>, dim3((unsigned)c->tiles.size()), dim3(256), 0, st, a,
-                       c->state[from], c->state[from ^ 1], step_arg, off);
+    if (c->block == 1024)
+        hipLaunchKernelGGL(k_step<1024>, dim3((unsigned)c->tiles.size()), dim3(1024), 0, st, a,
+                           c->state[from], c->state[from ^ 1], step_arg, off);
+    else
+        hipLaunchKernelGGL(k_step<256>, dim3((unsigned)c->tiles.size()), dim3(256), 0, st, a,
+                           c->state[from], c->state[from ^ 1], step_arg, off);
 }
 
 hipGraphExec_t get_graph(infoli_ctx* c, int parity) {
@@ -552,11 +567,30 @@ hipGraphExec_t get_graph(infoli_ctx* c, int parity) {
     return ex;
 }
 
+void launch_persistent(infoli_ctx* c, int64_t n_steps) {
+    const StepArgs a = make_args(c, false);
+    const dim3 grid((unsigned)c->n_inst), block(kPersistBlock);
+    const float* xin = c->state[c->cur];
+    float* xout = c->state[c->cur ^ 1];
+    switch (c->persist_cpt) {
+        case 1: hipLaunchKernelGGL(k_persist<1>, grid, block, 0, c->stream, a, xin, xout, c->step, n_steps); break;
+        case 2: hipLaunchKernelGGL(k_persist<2>, grid, block, 0, c->stream, a, xin, xout, c->step, n_steps); break;
+        case 4: hipLaunchKernelGGL(k_persist<4>, grid, block, 0, c->stream, a, xin, xout, c->step, n_steps); break;
+        default: hipLaunchKernelGGL(k_persist<8>, grid, block, 0, c->stream, a, xin, xout, c->step, n_steps); break;
+    }
+    c->cur ^= 1;
+    c->step += n_steps;
+}
+
 void run_steps(infoli_ctx* c, int64_t n_steps) {
     if (n_steps < 0) fail(INFOLI_E_INVALID_ARG, "n_steps must be >= 0");
     HIPX(hipEventRecord(c->ev0, c->stream));
     int64_t left = n_steps;
     const int mode = c->opt.step_mode;
+    if (mode == INFOLI_MODE_PERSISTENT) {
+        if (left > 0) launch_persistent(c, left);
+        left = 0;
+    }
     const int64_t chunk = c->opt.graph_chunk;
     const bool use_graph = (mode == INFOLI_MODE_GRAPH) || (mode == INFOLI_MODE_AUTO && n_steps >= 2 * chunk);
     if (use_graph) {

@@ -30,7 +30,7 @@ namespace infoli {
 
 enum : int { CONN_NONE = 0, CONN_UNIFORM = 1, CONN_DENSE = 2, CONN_CSR = 3 };
 
-constexpr int kMaxTileRows = 256;   // rows (cells) per tile, any layout
+constexpr int kMaxTileRows = 256;   // rows (cells) per tile, any layout (<= BLOCK)
 constexpr int kUniformRows = 64;    // rows per UNIFORM_ALL tile (one per lane)
 constexpr int kChunk = 8192;        // Vd values staged in LDS per pass
 
@@ -191,7 +191,9 @@ __device__ __forceinline__ void gap_dense(const StepArgs& a, const InstDesc& d, 
 template <int BLOCK, bool LDS, bool C16, bool HASW>
 __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& d, const Tile& t,
                                              const float* __restrict__ vd, const float* s_vd,
-                                             float* s_ig) {
+                                             float* s_part, float* s_ig) {
+    // L lanes per row (4..BLOCK, power of two); a row wider than a wave
+    // spans L/64 consecutive waves and is reduced through LDS.
     const int L = d.lanes_per_row;
     const int groups = BLOCK / L;
     const int grp = threadIdx.x / L;
@@ -202,9 +204,9 @@ __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& 
     const float* wv = a.w + d.w_off;
     auto col_at = [&](int64_t k) -> int { return C16 ? (int)c16[k] : c32[k]; };
     auto v_at = [&](int j) -> float { return LDS ? s_vd[j] : vd[j]; };
-    auto term = [&](int64_t k, float vi, int j) -> float {
-        const float dv = vi - v_at(j);
-        return HASW ? wv[k] * (dv * gap_factor(dv)) : dv * gap_factor(dv);
+    auto term = [&](float w, float vi, float vj) -> float {
+        const float dv = vi - vj;
+        return HASW ? w * (dv * gap_factor(dv)) : dv * gap_factor(dv);
     };
     for (int r0 = t.row0; r0 < t.row1; r0 += groups) {
         const int r = r0 + grp;
@@ -213,43 +215,66 @@ __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& 
             const float vi = v_at(r);
             const int64_t e = rp[r + 1];
             int64_t k = rp[r] + lig;
-            // four independent edges per lane per iteration keep loads in flight
-            for (; k + 3 * L < e; k += 4 * L) {
-                const int j0 = col_at(k), j1 = col_at(k + L), j2 = col_at(k + 2 * L),
-                          j3 = col_at(k + 3 * L);
-                acc0 += term(k, vi, j0);
-                acc1 += term(k + L, vi, j1);
-                acc0 += term(k + 2 * L, vi, j2);
-                acc1 += term(k + 3 * L, vi, j3);
+            // batches of eight independent edges: all loads issue before use
+            for (; k + 7 * L < e; k += 8 * L) {
+                int j[8];
+                float w[8], v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    j[u] = col_at(k + u * L);
+                    w[u] = HASW ? wv[k + u * L] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = v_at(j[u]);
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    acc0 += term(w[u], vi, v[u]);
+                    acc1 += term(w[u + 1], vi, v[u + 1]);
+                }
             }
-            for (; k < e; k += L) acc0 += term(k, vi, col_at(k));
+            for (; k < e; k += L) acc0 += term(HASW ? wv[k] : 0.0f, vi, v_at(col_at(k)));
         }
-        // all lanes of a group run the butterfly together
-        float acc = wave_sum_xor(acc0 + acc1, L);
-        if (r < t.row1 && lig == 0) s_ig[r - t.row0] = HASW ? acc : d.g * acc;
+        float acc = acc0 + acc1;
+        if (L <= 64) {
+            // all lanes of a group run the butterfly together
+            acc = wave_sum_xor(acc, L);
+            if (r < t.row1 && lig == 0) s_ig[r - t.row0] = HASW ? acc : d.g * acc;
+        } else {
+            acc = wave_sum_xor(acc, 64);
+            const int wave = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0) s_part[wave] = acc;
+            __syncthreads();
+            if (lig == 0 && r < t.row1) {
+                float tot = 0.0f;
+                for (int w = 0; w < L / 64; ++w) tot += s_part[wave + w];
+                s_ig[r - t.row0] = HASW ? tot : d.g * tot;
+            }
+            __syncthreads();
+        }
     }
 }
 
 template <int BLOCK>
 __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
-                                        const float* __restrict__ vd, float* s_vd, float* s_ig) {
+                                        const float* __restrict__ vd, float* s_vd, float* s_part,
+                                        float* s_ig) {
     if (d.vd_lds) {
         for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k];
         __syncthreads();
         if (d.col16) {
-            if (d.has_w) gap_csr_impl<BLOCK, true, true, true>(a, d, t, vd, s_vd, s_ig);
-            else gap_csr_impl<BLOCK, true, true, false>(a, d, t, vd, s_vd, s_ig);
+            if (d.has_w) gap_csr_impl<BLOCK, true, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, true, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
         } else {
-            if (d.has_w) gap_csr_impl<BLOCK, true, false, true>(a, d, t, vd, s_vd, s_ig);
-            else gap_csr_impl<BLOCK, true, false, false>(a, d, t, vd, s_vd, s_ig);
+            if (d.has_w) gap_csr_impl<BLOCK, true, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, true, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
         }
     } else {
         if (d.col16) {
-            if (d.has_w) gap_csr_impl<BLOCK, false, true, true>(a, d, t, vd, s_vd, s_ig);
-            else gap_csr_impl<BLOCK, false, true, false>(a, d, t, vd, s_vd, s_ig);
+            if (d.has_w) gap_csr_impl<BLOCK, false, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, false, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
         } else {
-            if (d.has_w) gap_csr_impl<BLOCK, false, false, true>(a, d, t, vd, s_vd, s_ig);
-            else gap_csr_impl<BLOCK, false, false, false>(a, d, t, vd, s_vd, s_ig);
+            if (d.has_w) gap_csr_impl<BLOCK, false, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, false, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
         }
     }
 }
@@ -281,28 +306,36 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
     const float* vd = xin + (int64_t)SV_VD * a.stride + d.cell_off;
     const int nrows = t.row1 - t.row0;
 
+    // Thread k < nrows owns cell row0 + k for the compartment update; its
+    // state loads are issued first so their latency overlaps the gap work.
+    const bool own = (int)threadIdx.x < nrows && !a.gap_only;
+    const int li = t.row0 + threadIdx.x;
+    const int64_t cell = d.cell_off + li;
+    float x[NSV];
+    float iapp = 0.0f;
+    if (own) {
+#pragma unroll
+        for (int v = 0; v < NSV; ++v) x[v] = xin[v * a.stride + cell];
+        iapp = evoked_input(a, d, step, li, cell);
+    }
+
     switch (d.conn) {
         case CONN_UNIFORM: gap_uniform<BLOCK>(a, d, t, vd, s_ig, s_v4, s_part, s_red); break;
         case CONN_DENSE: gap_dense<BLOCK>(a, d, t, vd, s_ig); break;
-        case CONN_CSR: gap_csr<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_ig); break;
+        case CONN_CSR: gap_csr<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig); break;
         default:
             for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
             break;
     }
     __syncthreads();
 
-    for (int k = threadIdx.x; k < nrows; k += BLOCK) {
-        const int li = t.row0 + k;
-        const int64_t cell = d.cell_off + li;
-        if (a.gap_only) {
-            a.igap_out[cell] = s_ig[k];
-            continue;
-        }
-        float x[NSV], y[NSV];
-#pragma unroll
-        for (int v = 0; v < NSV; ++v) x[v] = xin[v * a.stride + cell];
-        const float iapp = evoked_input(a, d, step, li, cell);
-        cell_step(d.p, x, s_ig[k], iapp, a.dt, y);
+    if (a.gap_only) {
+        for (int k = threadIdx.x; k < nrows; k += BLOCK) a.igap_out[d.cell_off + t.row0 + k] = s_ig[k];
+        return;
+    }
+    if (own) {
+        float y[NSV];
+        cell_step(d.p, x, s_ig[threadIdx.x], iapp, a.dt, y);
         float chk = 0.0f;
 #pragma unroll
         for (int v = 0; v < NSV; ++v) {

@@ -363,3 +363,66 @@ def test_torch_stream_and_device_readback(infoli):
     sim.step(300)
     np.testing.assert_array_equal(sim.read_state(0), a)
     sim.close()
+
+
+# ------------------------------------------------------------------ persistent mode
+def test_persistent_batch_parity(infoli, o32, o64):
+    """One workgroup per network, all steps in one launch: a batch of small
+    networks of every layout against the oracle, and against the per-step
+    kernel within the same bound."""
+    nets = [
+        I.Network(n=300, conn="uniform", g=0.04, jitter=I.voltage_jitter(300, 1),
+                  pulses=[I.Pulse(100, 600, 6.0)], label="p_uniform300"),
+        I.config1(0.1, seed=9, n=513),
+        I.Network(n=50, conn="none", jitter=I.voltage_jitter(50, 2), bias=I.input_bias(50, 3)),
+        I.config1(0.02, seed=10, n=2048),
+    ]
+    x0s = [infoli.initial_state(n) for n in nets]
+    res = {}
+    for mode in ("persistent", "graph"):
+        sim = infoli.Simulator(nets, init_states=x0s, step_mode=mode, graph_chunk=50)
+        tr = [[] for _ in nets]
+        for _ in range(10):
+            sim.step(100)
+            for k in range(len(nets)):
+                tr[k].append(sim.read_state(k))
+        res[mode] = [np.stack(t) for t in tr]
+        sim.close()
+    for k, net in enumerate(nets):
+        ref = o32.run(net, 1000, x0=x0s[k], trace_every=100, trace_cells=net.n)["trace"]
+        r64 = o64.run(net, 1000, x0=x0s[k].astype(np.float64), trace_every=100, trace_cells=net.n)["trace"]
+        tol = np.maximum(TOL_STATE, per_var_error(ref, r64))
+        for mode in ("persistent", "graph"):
+            e = per_var_error(res[mode][k], ref)
+            assert np.all(e <= tol), (net.label, mode, e)
+
+
+def test_persistent_dense_and_resume(infoli, o32):
+    n = 128
+    w = I.rng(5).uniform(0, 0.04, (n, n)).astype(np.float32)
+    net = I.Network(n=n, conn="dense", w_dense=w, jitter=I.voltage_jitter(n, 6),
+                    pulses=[I.Pulse(100, 600, 6.0)])
+    x0 = infoli.initial_state(net)
+    sim = infoli.Simulator(net, init_states=[x0], step_mode="persistent")
+    sim.step(400)
+    sim.step(400)
+    a = sim.read_state(0)
+    ca, ta = sim.read_spikes(0)
+    sim.close()
+    sim = infoli.Simulator(net, init_states=[x0], step_mode="persistent")
+    sim.step(800)
+    b = sim.read_state(0)
+    cb, tb = sim.read_spikes(0)
+    sim.close()
+    np.testing.assert_array_equal(a, b)          # one launch or two: same bits
+    np.testing.assert_array_equal(ca, cb)
+    ref = o32.run(net, 800, x0=x0)
+    assert per_var_error(a[None], ref["x"][None]).max() <= 1e-3
+    compare_spikes(ca, ta, ref["counts"], ref["times"], 64)
+
+
+def test_persistent_rejects_large_network(infoli):
+    net = I.Network(n=3000, conn="none")
+    with pytest.raises(infoli.InfoliError) as e:
+        infoli.Simulator(net, step_mode="persistent")
+    assert e.value.status == 7
