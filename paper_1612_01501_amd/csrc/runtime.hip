@@ -133,6 +133,7 @@ struct infoli_ctx {
     float dt = 0.05f;
     int block = 256;
     int persist_cpt = 1;            // cells per thread of the persistent kernel
+    size_t lds_bytes = 16;          // dynamic LDS of the step kernel
 
     // device memory
     std::vector<void*> allocs;
@@ -275,11 +276,11 @@ void validate_spec(const infoli_network_spec& s, int k) {
     }
 }
 
-// Lanes per CSR row: about eight edges per lane, so that one batch of
+// Lanes per CSR row: at most kBatch edges per lane, so that one batch of
 // independent loads covers most rows.
 int pick_lanes(double mean_degree, int block) {
     int L = 4;
-    while (L < block && L * 8 < mean_degree) L *= 2;
+    while (L < block && L * kBatch < mean_degree) L *= 2;
     return L;
 }
 
@@ -412,6 +413,17 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
             planned.push_back({cost, Tile{k, r, r1, 0}});
         }
     }
+    // dynamic LDS: Vd staging of the largest all-to-all chunk / staged CSR network
+    {
+        size_t floats = 4;
+        for (int k = 0; k < ninst; ++k) {
+            const InstDesc& d = c->inst[k];
+            if (d.conn == CONN_UNIFORM)
+                floats = std::max(floats, (size_t)std::min(d.n, kChunk) + 8 * (size_t)(c->block / 64));
+            if (d.conn == CONN_CSR && d.vd_lds) floats = std::max(floats, (size_t)d.n);
+        }
+        c->lds_bytes = ((floats + 3) / 4) * sizeof(float4);
+    }
     std::stable_sort(planned.begin(), planned.end(),
                      [](const auto& x, const auto& y) { return x.first > y.first; });
     for (const auto& pt : planned) c->tiles.push_back(pt.second);
@@ -540,10 +552,10 @@ StepArgs make_args(const infoli_ctx* c, bool device_step) {
 void launch_step(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
                  int32_t off) {
     if (c->block == 1024)
-        hipLaunchKernelGGL(k_step<1024>, dim3((unsigned)c->tiles.size()), dim3(1024), 0, st, a,
-                           c->state[from], c->state[from ^ 1], step_arg, off);
+        hipLaunchKernelGGL(k_step<1024>, dim3((unsigned)c->tiles.size()), dim3(1024), c->lds_bytes, st,
+                           a, c->state[from], c->state[from ^ 1], step_arg, off);
     else
-        hipLaunchKernelGGL(k_step<256>, dim3((unsigned)c->tiles.size()), dim3(256), 0, st, a,
+        hipLaunchKernelGGL(k_step<256>, dim3((unsigned)c->tiles.size()), dim3(256), c->lds_bytes, st, a,
                            c->state[from], c->state[from ^ 1], step_arg, off);
 }
 

@@ -33,6 +33,7 @@ enum : int { CONN_NONE = 0, CONN_UNIFORM = 1, CONN_DENSE = 2, CONN_CSR = 3 };
 constexpr int kMaxTileRows = 256;   // rows (cells) per tile, any layout (<= BLOCK)
 constexpr int kUniformRows = 64;    // rows per UNIFORM_ALL tile (one per lane)
 constexpr int kChunk = 8192;        // Vd values staged in LDS per pass
+constexpr int kBatch = 16;          // CSR edges per lane per batch of loads
 
 // log2(e)/100: exp(-dV^2/100) = 2^(-(dV*a)^2) with a = sqrt(log2(e)/100).
 constexpr float kL2eOver100 = 0.014426950408889634f;
@@ -215,19 +216,19 @@ __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& 
             const float vi = v_at(r);
             const int64_t e = rp[r + 1];
             int64_t k = rp[r] + lig;
-            // batches of eight independent edges: all loads issue before use
-            for (; k + 7 * L < e; k += 8 * L) {
-                int j[8];
-                float w[8], v[8];
+            // batches of kBatch independent edges: all loads issue before use
+            for (; k + (kBatch - 1) * L < e; k += kBatch * L) {
+                int j[kBatch];
+                float w[kBatch], v[kBatch];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kBatch; ++u) {
                     j[u] = col_at(k + u * L);
                     w[u] = HASW ? wv[k + u * L] : 0.0f;
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = v_at(j[u]);
+                for (int u = 0; u < kBatch; ++u) v[u] = v_at(j[u]);
 #pragma unroll
-                for (int u = 0; u < 8; u += 2) {
+                for (int u = 0; u < kBatch; u += 2) {
                     acc0 += term(w[u], vi, v[u]);
                     acc1 += term(w[u + 1], vi, v[u + 1]);
                 }
@@ -296,9 +297,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
                                                 float* __restrict__ xout, int64_t step_arg,
                                                 int32_t step_off) {
     __shared__ float s_ig[kMaxTileRows];
-    __shared__ float4 s_v4[(kChunk + 8 * (BLOCK / 64)) / 4];
     __shared__ float s_part[BLOCK];
     __shared__ double s_red[BLOCK / 64];
+    // Vd staging, sized per launch: the largest all-to-all chunk
+    // (min(n, kChunk) + 8 per wave) or the largest LDS-staged CSR network
+    extern __shared__ float4 s_v4[];
 
     const Tile t = a.tiles[blockIdx.x];
     const InstDesc& d = a.inst[t.inst];
