@@ -222,3 +222,27 @@ def config4(seed: int = 0, n: int = 65536, degree: float = 1000.0) -> Network:
                    jitter=voltage_jitter(n, 2000 + seed),
                    bias=input_bias(n, 3000 + seed),
                    pulses=[Pulse(400, 500, 6.0)], label=f"c4_csr_n{n}_deg{degree:g}")
+
+
+# ---------------------------------------------------------------- surrogate MLP
+MLP_K_IN, MLP_HID, MLP_K_OUT = 16, 128, 16
+
+
+def mlp_init_params(seed: int = 5000) -> np.ndarray:
+    """Initial MLP parameters (flat fp32, order W1 b1 W2 b2 W3 b3 with
+    W1 [128][16], W2 [128][128], W3 [16][128]): weights U(-1/sqrt(fan_in),
+    1/sqrt(fan_in)), biases zero."""
+    g = rng(seed)
+    parts = []
+    for rows, cols in ((MLP_HID, MLP_K_IN), (MLP_HID, MLP_HID), (MLP_K_OUT, MLP_HID)):
+        b = 1.0 / np.sqrt(cols)
+        parts.append(g.uniform(-b, b, rows * cols))
+        parts.append(np.zeros(rows))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_batch(n: int, seed: int):
+    """A synthetic training batch: inputs ~ N(0, 1) in R^16, targets ~ N(0, 1)."""
+    g = rng(seed)
+    return (g.normal(0.0, 1.0, (n, MLP_K_IN)).astype(np.float32),
+            g.normal(0.0, 1.0, (n, MLP_K_OUT)).astype(np.float32))
