@@ -13,6 +13,10 @@ Workloads (--workload):
            20-25 ms), stepped together: the default, 20,000 steps
   uni96    96 cells all-to-all (g = 0.04), 2,000 steps
   uni16k   16,384 cells all-to-all (g = 0.04*96/N), 4,000 steps
+  batch256 256 independent networks, N_k ~ U{64..2048}, density ~ U{5, 25,
+           100 %} (100 % all-to-all, else ER CSR), g_k ~ U[0.01, 0.08],
+           pulse amplitude ~ U[2, 10] uA/cm^2, 10,000 steps, one launch per
+           step replayed from a HIP graph
 
 Prints one JSON line (rank 0) with the throughput, a roofline entry for the
 step kernel and the CPU oracle timed on a bounded sample of the same work.
@@ -35,6 +39,7 @@ WORKLOADS = {
     "csr4096": dict(steps=20000, warmup=1000),
     "uni96": dict(steps=2000, warmup=200),
     "uni16k": dict(steps=4000, warmup=100),
+    "batch256": dict(steps=10000, warmup=200),
 }
 
 
@@ -46,6 +51,10 @@ def build_workload(name):
     elif name == "uni96":
         nets = [I.config0()]
         desc = "96 cells all-to-all, g=0.04 mS/cm^2, 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms"
+    elif name == "batch256":
+        nets = I.config3()
+        desc = ("256 networks, N_k ~ U{64..2048}, density ~ U{5,25,100 %} (100 % all-to-all, else ER CSR), "
+                "g_k ~ U[0.01,0.08] mS/cm^2, pulse A_k ~ U[2,10] uA/cm^2 steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms")
     elif name == "uni16k":
         nets = [I.config2()]
         desc = "16,384 cells all-to-all, g=0.04*96/N mS/cm^2, +-1 mV jitter, no input, FP32, dt=0.05 ms"
@@ -82,7 +91,22 @@ def algorithmic_bytes(nets):
     return b
 
 
+# CSR edge: v_sub, v_mul, v_mul, v_exp_f32 (2 slots), v_fma, v_add and two
+# address operations for the 16-bit column gather.
+CSR_SLOTS_PER_EDGE = 9
+
+
 def roofline(nets, launch_s):
+    kinds = {n.conn for n in nets}
+    if len(kinds) > 1:
+        # mixed batch: issue slots of the pair/edge work against the lane-slot peak
+        slots = sum(UNIFORM_SLOTS_PER_PAIR * n.n * n.n if n.conn == "uniform"
+                    else CSR_SLOTS_PER_EDGE * n.pairs_per_step() for n in nets)
+        achieved = slots / launch_s / 1e12
+        peak = LANE_SLOTS_PER_S / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T lane-slots/s",
+                "frac": achieved / peak, "traffic": None, "kernel": "infoli::k_step<256>",
+                "slots_per_launch": slots}
     if all(n.conn == "uniform" for n in nets):
         pairs = sum(n.n * n.n for n in nets)       # the kernel evaluates the diagonal too
         achieved = pairs / launch_s / 1e9

@@ -140,11 +140,15 @@ typedef struct infoli_options {
     int32_t tile_rows;           /* 0 => tuned; else rows per workgroup tile               */
     int32_t lanes_per_row;       /* 0 => tuned; CSR lanes per row: 4..256, power of 2     */
     int32_t check_finite;        /* 1 => a NaN/Inf state makes infoli_sync fail            */
+    int32_t autotune;            /* CSR tile shapes: 0 => built-in rule; 1 => timed on the
+                                    device at init, cached on disk (INFOLI_TUNE_CACHE, else
+                                    ~/.cache/infoli-tune-v1.txt); 2 => timed, cache ignored */
 } infoli_options;
 
 typedef struct infoli_ctx infoli_ctx;
 
-/* Fill *opt with the defaults (AUTO mode, 64 spike times, tuned tiles, checks on). */
+/* Fill *opt with the defaults (AUTO mode, 64 spike times, autotuned tiles,
+ * checks on). */
 infoli_status infoli_default_options(infoli_options *opt);
 
 /* Copy the default cell parameters (see INFOLI_NUM_PARAMS) into out[20]. */
@@ -215,6 +219,8 @@ typedef struct infoli_info {
     int32_t tile_rows;          /* rows per tile of the largest instance               */
     int32_t lanes_per_row;
     int64_t device_bytes;       /* device memory held                                   */
+    int32_t tuned;              /* networks whose tile shapes were timed at init        */
+    int32_t tune_cached;        /* networks whose tile shapes came from the cache       */
 } infoli_info;
 infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
 

@@ -8,8 +8,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
+#include <sys/stat.h>
 #include <string>
 #include <vector>
 
@@ -134,6 +137,10 @@ struct infoli_ctx {
     int block = 256;
     int persist_cpt = 1;            // cells per thread of the persistent kernel
     size_t lds_bytes = 16;          // dynamic LDS of the step kernel
+    std::vector<int> rows_of;       // tile rows per network
+    std::vector<double> deg_of;     // mean gap-junction degree per network
+    int tuned = 0;                  // networks whose tiles came from timing runs
+    int tune_cached = 0;            // networks whose tiles came from the tuning cache
 
     // device memory
     std::vector<void*> allocs;
@@ -284,6 +291,178 @@ int pick_lanes(double mean_degree, int block) {
     return L;
 }
 
+StepArgs make_args(const infoli_ctx* c, bool device_step);
+
+void launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, unsigned ntiles, size_t lds, int from,
+                  int64_t step_arg, int32_t off) {
+    if (c->block == 1024)
+        hipLaunchKernelGGL(k_step<1024>, dim3(ntiles), dim3(1024), lds, st, a, c->state[from],
+                           c->state[from ^ 1], step_arg, off);
+    else
+        hipLaunchKernelGGL(k_step<256>, dim3(ntiles), dim3(256), lds, st, a, c->state[from],
+                           c->state[from ^ 1], step_arg, off);
+}
+
+void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int rows, double deg) {
+    for (int r = 0; r < n; r += rows) {
+        const int r1 = std::min(n, r + rows);
+        out.push_back({(r1 - r) * (deg * 8.0 + 400.0), Tile{k, r, r1, 0}});
+    }
+}
+
+// Tiles of every network, longest (estimated issue slots) first; dynamic LDS
+// for the Vd staging they need; descriptors and tiles to the device.
+void finalize_tiles(infoli_ctx* c) {
+    std::vector<std::pair<double, Tile>> planned;
+    size_t floats = 4;
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstDesc& d = c->inst[k];
+        append_tiles(planned, k, d.n, c->rows_of[k], c->deg_of[k]);
+        if (d.conn == CONN_UNIFORM)
+            floats = std::max(floats, (size_t)std::min(d.n, kChunk) + 8 * (size_t)(c->block / 64));
+        if (d.conn == CONN_CSR && d.vd_lds) floats = std::max(floats, (size_t)d.n);
+    }
+    c->lds_bytes = ((floats + 3) / 4) * sizeof(float4);
+    std::stable_sort(planned.begin(), planned.end(),
+                     [](const auto& x, const auto& y) { return x.first > y.first; });
+    c->tiles.clear();
+    for (const auto& pt : planned) c->tiles.push_back(pt.second);
+    if (c->tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
+    c->d_tiles = c->alloc<Tile>(c->tiles.size());
+    HIPX(hipMemcpy(c->d_tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDesc) * c->n_inst, hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------- autotuner
+// For every class of CSR network (log-spaced size and degree buckets) the
+// candidate tile shapes (lanes per row, rows per tile, LDS staging of Vd) are
+// timed on the network's own device data with dry launches (they write only
+// the next-state buffer) and the fastest is kept, in memory and in an
+// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v1.txt).
+struct TuneChoice {
+    int L, R, lds;
+};
+
+std::string tune_cache_path() {
+    const char* p = std::getenv("INFOLI_TUNE_CACHE");
+    if (p && *p) return p;
+    const char* h = std::getenv("HOME");
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v1.txt";
+    return "";
+}
+
+std::string tune_key(const infoli_ctx* c, const InstDesc& d, double deg) {
+    const int nb = (int)std::ceil(std::log2((double)d.n) * 4.0);
+    const int db = (int)std::ceil(std::log2(deg + 1.0) * 4.0);
+    char buf[128];
+    snprintf(buf, sizeof buf, "gfx950 block%d c16=%d w=%d n%d d%d", c->block, d.col16, d.has_w, nb, db);
+    return buf;
+}
+
+std::map<std::string, TuneChoice> read_tune_cache(const std::string& path) {
+    std::map<std::string, TuneChoice> m;
+    if (path.empty()) return m;
+    std::FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return m;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        char* bar = std::strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        TuneChoice t;
+        if (std::sscanf(bar + 1, "%d %d %d", &t.L, &t.R, &t.lds) == 3 && t.L >= 4 && t.L <= 1024 &&
+            (t.L & (t.L - 1)) == 0 && t.R >= 1 && t.R <= kMaxTileRows && (t.lds == 0 || t.lds == 1))
+            m[line] = t;
+    }
+    std::fclose(f);
+    return m;
+}
+
+void append_tune_cache(const std::string& path, const std::string& key, const TuneChoice& t) {
+    if (path.empty()) return;
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos) mkdir(path.substr(0, slash).c_str(), 0755);
+    std::FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s|%d %d %d\n", key.c_str(), t.L, t.R, t.lds);
+    std::fclose(f);
+}
+
+float time_shape(infoli_ctx* c, int k, const TuneChoice& t, Tile* d_tmp) {
+    InstDesc d = c->inst[k];
+    d.lanes_per_row = t.L;
+    d.vd_lds = t.lds;
+    HIPX(hipMemcpy(c->d_inst + k, &d, sizeof(d), hipMemcpyHostToDevice));
+    std::vector<std::pair<double, Tile>> planned;
+    append_tiles(planned, k, d.n, t.R, 0.0);
+    std::vector<Tile> tl;
+    for (const auto& pt : planned) tl.push_back(pt.second);
+    HIPX(hipMemcpy(d_tmp, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice));
+    StepArgs a = make_args(c, false);
+    a.tiles = d_tmp;
+    a.dry = 1;
+    const size_t lds = t.lds ? ((size_t)(d.n + 3) / 4) * sizeof(float4) : 16;
+    for (int w = 0; w < 2; ++w) launch_tiles(c, c->stream, a, (unsigned)tl.size(), lds, c->cur, c->step, 0);
+    HIPX(hipEventRecord(c->ev0, c->stream));
+    const int reps = 8;
+    for (int w = 0; w < reps; ++w) launch_tiles(c, c->stream, a, (unsigned)tl.size(), lds, c->cur, c->step, 0);
+    HIPX(hipEventRecord(c->ev1, c->stream));
+    HIPX(hipGetLastError());
+    HIPX(hipEventSynchronize(c->ev1));
+    float ms = 0.0f;
+    HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    return ms / reps;
+}
+
+void autotune(infoli_ctx* c) {
+    if (c->opt.lanes_per_row || c->opt.tile_rows) return;   // shapes given by the caller
+    const std::string path = tune_cache_path();
+    std::map<std::string, TuneChoice> cache;
+    if (c->opt.autotune == 1) cache = read_tune_cache(path);
+    std::map<std::string, TuneChoice> decided;
+    Tile* d_tmp = nullptr;
+    for (int k = 0; k < c->n_inst; ++k) {
+        InstDesc& d = c->inst[k];
+        const double deg = c->deg_of[k];
+        if (d.conn != CONN_CSR || deg <= 0.0) continue;
+        const std::string key = tune_key(c, d, deg);
+        TuneChoice best{0, 0, 0};
+        auto hit = decided.find(key);
+        if (hit != decided.end()) {
+            best = hit->second;
+        } else if ((hit = cache.find(key)) != cache.end() && hit->second.L <= c->block) {
+            best = hit->second;
+            decided[key] = best;
+            ++c->tune_cached;
+        } else {
+            if (!d_tmp) d_tmp = c->alloc<Tile>(c->total_cells + 1);
+            float best_ms = 1e30f;
+            for (int L = 4; L <= c->block; L *= 2) {
+                if (L > 4 && L > 2.0 * deg) break;
+                if (deg / L > 256.0) continue;
+                for (int m = 1; m <= 4; m *= 2) {
+                    const int R = std::max(1, c->block / L) * m;
+                    if (R > kMaxTileRows) continue;
+                    for (int lds = 0; lds <= (d.n <= kChunk ? 1 : 0); ++lds) {
+                        const TuneChoice t{L, R, lds};
+                        const float ms = time_shape(c, k, t, d_tmp);
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best = t;
+                        }
+                    }
+                }
+            }
+            decided[key] = best;
+            append_tune_cache(path, key, best);
+            ++c->tuned;
+        }
+        d.lanes_per_row = best.L;
+        c->rows_of[k] = best.R;
+        d.vd_lds = best.lds;
+    }
+}
+
 void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t ninst,
                    const infoli_options* opt) {
     if (!specs || ninst < 1) fail(INFOLI_E_INVALID_ARG, "need at least one network spec");
@@ -299,6 +478,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         (c->opt.lanes_per_row < 4 || c->opt.lanes_per_row > 256 ||
          (c->opt.lanes_per_row & (c->opt.lanes_per_row - 1))))
         fail(INFOLI_E_INVALID_ARG, "lanes_per_row must be 0 or a power of two in [4, 256]");
+    if (c->opt.autotune < 0 || c->opt.autotune > 2)
+        fail(INFOLI_E_INVALID_ARG, "autotune must be 0, 1 or 2");
     if (c->opt.tile_rows < 0 || c->opt.tile_rows > kMaxTileRows)
         fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
     for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
@@ -381,15 +562,17 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     bool col16 = col_total > 0;
     for (int k = 0; k < ninst; ++k)
         if (c->inst[k].conn == CONN_CSR && c->inst[k].n > 65536) col16 = false;
-    std::vector<int> rows_of(ninst);
+    c->rows_of.assign(ninst, kMaxTileRows);
+    c->deg_of.assign(ninst, 0.0);
     for (int k = 0; k < ninst; ++k) {
         InstDesc& d = c->inst[k];
         int rows;
         switch (d.conn) {
-            case CONN_UNIFORM: rows = kUniformRows; break;
-            case CONN_DENSE: rows = c->opt.tile_rows ? c->opt.tile_rows : 16; break;
+            case CONN_UNIFORM: rows = kUniformRows; c->deg_of[k] = d.n; break;
+            case CONN_DENSE: rows = c->opt.tile_rows ? c->opt.tile_rows : 16; c->deg_of[k] = d.n; break;
             case CONN_CSR: {
                 const double deg = (double)specs[k].nnz / d.n;
+                c->deg_of[k] = deg;
                 // one pass of row groups per tile: short dependent-load chains
                 const int per_pass = std::max(1, c->block / d.lanes_per_row);
                 rows = c->opt.tile_rows ? c->opt.tile_rows : std::min(kMaxTileRows, per_pass);
@@ -399,35 +582,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
             }
             default: rows = c->opt.tile_rows ? c->opt.tile_rows : kMaxTileRows; break;
         }
-        rows_of[k] = std::min(rows, kMaxTileRows);
+        c->rows_of[k] = std::min(rows, kMaxTileRows);
     }
-    // estimated cost of a tile (issue slots): the longest tiles go first
-    std::vector<std::pair<double, Tile>> planned;
-    for (int k = 0; k < ninst; ++k) {
-        const InstDesc& d = c->inst[k];
-        const double deg = d.conn == CONN_CSR ? (double)specs[k].nnz / d.n
-                         : (d.conn == CONN_NONE ? 0.0 : (double)d.n);
-        for (int r = 0; r < d.n; r += rows_of[k]) {
-            const int r1 = std::min(d.n, r + rows_of[k]);
-            const double cost = (r1 - r) * (deg * 8.0 + 400.0);
-            planned.push_back({cost, Tile{k, r, r1, 0}});
-        }
-    }
-    // dynamic LDS: Vd staging of the largest all-to-all chunk / staged CSR network
-    {
-        size_t floats = 4;
-        for (int k = 0; k < ninst; ++k) {
-            const InstDesc& d = c->inst[k];
-            if (d.conn == CONN_UNIFORM)
-                floats = std::max(floats, (size_t)std::min(d.n, kChunk) + 8 * (size_t)(c->block / 64));
-            if (d.conn == CONN_CSR && d.vd_lds) floats = std::max(floats, (size_t)d.n);
-        }
-        c->lds_bytes = ((floats + 3) / 4) * sizeof(float4);
-    }
-    std::stable_sort(planned.begin(), planned.end(),
-                     [](const auto& x, const auto& y) { return x.first > y.first; });
-    for (const auto& pt : planned) c->tiles.push_back(pt.second);
-    if (c->tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
 
     // ---- stream
     if (c->opt.hip_stream) {
@@ -486,7 +642,6 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->igap = c->alloc<float>(S);
     c->bias = c->alloc<float>(S);
     c->d_inst = c->alloc<InstDesc>(ninst);
-    c->d_tiles = c->alloc<Tile>(c->tiles.size());
     c->d_pulses = c->alloc<DevPulse>(h_pulses.size());
     c->d_rowptr = c->alloc<int64_t>(h_rp.size());
     if (col16) {
@@ -511,7 +666,6 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     HIPX(hipMemcpy(c->state[1], h_state.data(), sizeof(float) * h_state.size(), hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->bias, h_bias.data(), sizeof(float) * S, hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDesc) * ninst, hipMemcpyHostToDevice));
-    HIPX(hipMemcpy(c->d_tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(), hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->d_pulses, h_pulses.data(), sizeof(DevPulse) * h_pulses.size(), hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->d_rowptr, h_rp.data(), sizeof(int64_t) * h_rp.size(), hipMemcpyHostToDevice));
     if (!col16)
@@ -522,6 +676,9 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     HIPX(hipMemset(c->d_spk_times, 0, sizeof(float) * (size_t)S * std::max(cap, 1)));
     HIPX(hipMemset(c->d_flags, 0, sizeof(int32_t) * 4));
     HIPX(hipMemset(c->igap, 0, sizeof(float) * S));
+    HIPX(hipDeviceSynchronize());
+    if (c->opt.autotune) autotune(c);
+    finalize_tiles(c);
     HIPX(hipDeviceSynchronize());
 }
 
@@ -551,12 +708,7 @@ StepArgs make_args(const infoli_ctx* c, bool device_step) {
 
 void launch_step(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
                  int32_t off) {
-    if (c->block == 1024)
-        hipLaunchKernelGGL(k_step<1024>, dim3((unsigned)c->tiles.size()), dim3(1024), c->lds_bytes, st,
-                           a, c->state[from], c->state[from ^ 1], step_arg, off);
-    else
-        hipLaunchKernelGGL(k_step<256>, dim3((unsigned)c->tiles.size()), dim3(256), c->lds_bytes, st, a,
-                           c->state[from], c->state[from ^ 1], step_arg, off);
+    launch_tiles(c, st, a, (unsigned)c->tiles.size(), c->lds_bytes, from, step_arg, off);
 }
 
 hipGraphExec_t get_graph(infoli_ctx* c, int parity) {
@@ -648,6 +800,7 @@ infoli_status infoli_default_options(infoli_options* opt) {
     opt->tile_rows = 0;
     opt->lanes_per_row = 0;
     opt->check_finite = 1;
+    opt->autotune = 1;
     return INFOLI_OK;
 }
 
@@ -846,6 +999,8 @@ infoli_status infoli_get_info(const infoli_ctx* ctx, infoli_info* info) {
     info->tile_rows = rows;
     info->lanes_per_row = lanes;
     info->device_bytes = (int64_t)ctx->device_bytes;
+    info->tuned = ctx->tuned;
+    info->tune_cached = ctx->tune_cached;
     return INFOLI_OK;
 }
 

@@ -93,7 +93,7 @@ struct StepArgs {
     float dt;
     int32_t spike_cap;
     int32_t gap_only;
-    int32_t pad0;
+    int32_t dry;               // timing runs: write the next state only
 };
 
 __device__ __forceinline__ float wave_sum_xor(float v, int width) {
@@ -345,6 +345,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
             xout[v * a.stride + cell] = y[v];
             chk += y[v];
         }
+        if (a.dry) return;
         if (!isfinite(chk)) atomicOr(a.flags, 1);
         // axon output: upward 0 mV crossing, time interpolated within the step
         if (x[SV_VA] < 0.0f && y[SV_VA] >= 0.0f) {

@@ -65,7 +65,7 @@ class Options(ctypes.Structure):
     _fields_ = [("hip_stream", ctypes.c_void_p), ("step_mode", ctypes.c_int32),
                 ("graph_chunk", ctypes.c_int32), ("max_spikes_per_cell", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -73,7 +73,8 @@ class Info(ctypes.Structure):
                 ("pairs_per_step", ctypes.c_int64), ("step", ctypes.c_int64),
                 ("step_mode", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("tuned", ctypes.c_int32),
+                ("tune_cached", ctypes.c_int32)]
 
 
 _lib = None

@@ -281,18 +281,18 @@ def test_repeat_resume_and_modes_bitwise(infoli):
     x0 = infoli.initial_state(net)
     runs = []
     for mode in ("graph", "graph", "launch"):
-        sim = infoli.Simulator(net, init_states=[x0], step_mode=mode, graph_chunk=50)
+        sim = infoli.Simulator(net, init_states=[x0], step_mode=mode, graph_chunk=50, autotune=0)
         sim.step(600)
         runs.append((sim.read_state(0), sim.read_spikes(0)[0]))
         sim.close()
     np.testing.assert_array_equal(runs[0][0], runs[1][0])
     np.testing.assert_array_equal(runs[0][0], runs[2][0])
     # split run: 250 steps, read, restart from that state at step 250
-    sim = infoli.Simulator(net, init_states=[x0], graph_chunk=50)
+    sim = infoli.Simulator(net, init_states=[x0], graph_chunk=50, autotune=0)
     sim.step(250)
     mid = sim.read_state(0)
     sim.close()
-    sim = infoli.Simulator(net, init_states=[x0], graph_chunk=50)
+    sim = infoli.Simulator(net, init_states=[x0], graph_chunk=50, autotune=0)
     sim.write_state(0, mid, 250)
     sim.step(350)
     end = sim.read_state(0)
@@ -310,13 +310,13 @@ def test_batch_matches_standalone_bitwise(infoli):
         I.Network(n=64, conn="uniform", g=0.02, jitter=I.voltage_jitter(64, 3)),
     ]
     x0s = [infoli.initial_state(n) for n in nets]
-    sim = infoli.Simulator(nets, init_states=x0s, step_mode="graph", graph_chunk=50)
+    sim = infoli.Simulator(nets, init_states=x0s, step_mode="graph", graph_chunk=50, autotune=0)
     sim.step(500)
     batch = [sim.read_state(k) for k in range(len(nets))]
     bspk = [sim.read_spikes(k)[0] for k in range(len(nets))]
     sim.close()
     for k, net in enumerate(nets):
-        s = infoli.Simulator(net, init_states=[x0s[k]], step_mode="graph", graph_chunk=50)
+        s = infoli.Simulator(net, init_states=[x0s[k]], step_mode="graph", graph_chunk=50, autotune=0)
         s.step(500)
         np.testing.assert_array_equal(s.read_state(0), batch[k])
         np.testing.assert_array_equal(s.read_spikes(0)[0], bspk[k])
@@ -360,14 +360,14 @@ def test_torch_stream_and_device_readback(infoli):
     x0 = infoli.initial_state(net)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sim = infoli.Simulator(net, init_states=[x0], stream=stream.cuda_stream)
+        sim = infoli.Simulator(net, init_states=[x0], stream=stream.cuda_stream, autotune=0)
         sim.step(300)
         dev = torch.empty((14, net.n), dtype=torch.float32, device="cuda")
         sim.read_state_device(0, dev.data_ptr())
         stream.synchronize()
         a = dev.cpu().numpy()
         sim.close()
-    sim = infoli.Simulator(net, init_states=[x0])
+    sim = infoli.Simulator(net, init_states=[x0], autotune=0)
     sim.step(300)
     np.testing.assert_array_equal(sim.read_state(0), a)
     sim.close()
@@ -434,3 +434,70 @@ def test_persistent_rejects_large_network(infoli):
     with pytest.raises(infoli.InfoliError) as e:
         infoli.Simulator(net, step_mode="persistent")
     assert e.value.status == 7
+
+
+# ------------------------------------------------------------------ autotuner
+def test_autotuner_times_caches_and_stays_exact(infoli, o32, tmp_path, monkeypatch):
+    """Tile shapes chosen by timing runs give oracle-exact results; a second
+    context reads them from the cache and reproduces the first bitwise."""
+    monkeypatch.setenv("INFOLI_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    nets = [I.config1(0.3, seed=12, n=900), I.config1(0.03, seed=13, n=1500)]
+    x0s = [infoli.initial_state(n) for n in nets]
+    out = []
+    for mode in (2, 1):
+        sim = infoli.Simulator(nets, init_states=x0s, autotune=mode, step_mode="graph", graph_chunk=50)
+        info = sim.info()
+        sim.step(300)
+        out.append([sim.read_state(k) for k in range(2)])
+        sim.close()
+        if mode == 2:
+            assert info["tuned"] == 2 and info["tune_cached"] == 0
+        else:
+            assert info["tuned"] == 0 and info["tune_cached"] == 2
+    lines = (tmp_path / "tune.txt").read_text().strip().splitlines()
+    assert len(lines) == 2 and all("|" in l for l in lines)
+    for k, net in enumerate(nets):
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+        ref = o32.run(net, 300, x0=x0s[k])["x"]
+        assert per_var_error(out[0][k][None], ref[None]).max() <= TOL_STATE
+
+
+# ------------------------------------------------------------------ batches of uneven networks
+def test_uneven_batch_against_oracle(infoli, o32, o64):
+    """The 256-network batch recipe at reduced size: 24 networks of 64-600
+    cells, densities 5/25/100 %, per-network g and pulse amplitude."""
+    nets = I.config3(seed=7, n_instances=24, n_min=64, n_max=600)
+    for n in nets:
+        n.pulses = [I.Pulse(100, 600, n.pulses[0].amplitude)]
+    x0s = [infoli.initial_state(n) for n in nets]
+    for mode in ("graph", "persistent"):
+        sim = infoli.Simulator(nets, init_states=x0s, step_mode=mode, graph_chunk=100)
+        sim.step(1000)
+        got = [sim.read_state(k) for k in range(len(nets))]
+        spk = [sim.read_spikes(k) for k in range(len(nets))]
+        sim.close()
+        for k, net in enumerate(nets):
+            ref = o32.run(net, 1000, x0=x0s[k])
+            r64 = o64.run(net, 1000, x0=x0s[k].astype(np.float64))
+            tol = np.maximum(TOL_STATE, per_var_error(ref["x"][None], r64["x"][None]))
+            e = per_var_error(got[k][None], ref["x"][None])
+            assert np.all(e <= np.maximum(TOL_STATE, 2 * tol)), (mode, net.label, e)
+            compare_spikes(spk[k][0], spk[k][1], ref["counts"], ref["times"], 64)
+
+
+def test_full_batch256_sampled_step(infoli, o32):
+    """All 256 networks in one context (graph mode): after 200 steps, one more
+    GPU step matches the oracle's step from the GPU state on 16 sampled
+    networks."""
+    nets = I.config3()
+    x0s = [infoli.initial_state(n) for n in nets]
+    sim = infoli.Simulator(nets, init_states=x0s, step_mode="graph", graph_chunk=100)
+    sim.step(200)
+    sample = list(range(0, 256, 16))
+    xk = {k: sim.read_state(k) for k in sample}
+    sim.step(1)
+    xk1 = {k: sim.read_state(k) for k in sample}
+    sim.close()
+    for k in sample:
+        ref = o32.run(nets[k], 1, x0=xk[k], step0=200)["x"]
+        assert per_var_error(xk1[k][None], ref[None]).max() <= 1e-5, nets[k].label
