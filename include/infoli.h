@@ -228,6 +228,94 @@ infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
  * call's device work; valid after infoli_sync. */
 infoli_status infoli_last_step_ms(infoli_ctx *ctx, float *ms);
 
+/* ------------------------------------------------------------------ surrogate
+ * A learned surrogate of the cell update: an MLP 16 -> 128 -> 128 -> 16 with
+ * SiLU, BF16 weights on the matrix cores and FP32 accumulation, mapping a
+ * cell's normalised [14 state variables, I_gap, I_app] to its normalised state
+ * increment over a macro step of 4 time steps, during which the gap current
+ * (computed exactly in fp32 at the macro step's start) and the input are held.
+ * The plain method stays the fallback and the judge (drift check). This part
+ * is not in the paper; it serves callers that trade a bounded error for speed.
+ *
+ * Parameters: INFOLI_MLP_PARAMS fp32 values in the order W1[128][16] b1[128]
+ * W2[128][128] b2[128] W3[16][128] b3[16] (W[out][in]). Normalisation: 64
+ * floats in_mean[16] in_rstd[16] out_mean[16] out_std[16] (features: the 14
+ * state variables, I_gap, I_app; outputs: the 14 increments, 2 pads). */
+enum { INFOLI_MLP_PARAMS = 20752 };
+
+typedef struct infoli_train_cfg {
+    int64_t n_transitions;      /* training-set size (rounded up to whole trajectories)   */
+    int32_t n_trajectories;     /* independent cells generating it                        */
+    int32_t burn_in;            /* macro steps per trajectory before recording            */
+    int32_t batch;              /* samples per optimiser step, multiple of 64             */
+    int32_t steps;              /* optimiser steps                                        */
+    float lr, beta1, beta2, eps;/* Adam                                                   */
+    float bias_sd;              /* per-trajectory constant input ~ N(0, bias_sd^2)        */
+    float gap_sd, gap_rho;      /* AR(1) gap current: stationary sd, lag-1 correlation    */
+    float pulse_p;              /* pulse start probability per macro step                 */
+    float pulse_lo, pulse_hi;   /* pulse amplitude ~ U[lo, hi] uA/cm^2                    */
+    int32_t pulse_len;          /* pulse length in macro steps                            */
+    uint64_t seed;              /* counter-based draws of the data and the batches        */
+    const float *init_params;   /* [INFOLI_MLP_PARAMS] initial weights (host), required   */
+} infoli_train_cfg;
+
+typedef struct infoli_train_report {
+    int64_t n_transitions;
+    int32_t steps;
+    float loss_first, loss_last;  /* mean squared error of the normalised increments     */
+    float data_ms, train_ms;      /* device time: data generation, optimisation          */
+} infoli_train_report;
+
+enum { INFOLI_SURROGATE_MLP = 0,        /* MLP with drift check and plain fallback        */
+       INFOLI_SURROGATE_PLAIN_HOLD = 1  /* every cell by the plain method, gap held 4 dt  */ };
+
+typedef struct infoli_drift_cfg {
+    float theta_mv;             /* a checked cell whose MLP voltages differ from the plain
+                                   ones by more than this (mV) is flagged                 */
+    float vs_spiking;           /* Vs above this (mV): the plain method                   */
+    int32_t sample_every;       /* checked cells per macro step: 1 in sample_every; 0 = none */
+    int32_t hold_steps;         /* macro steps a flagged cell stays on the plain method   */
+    int32_t mode;               /* INFOLI_SURROGATE_*                                     */
+} infoli_drift_cfg;
+
+typedef struct infoli_drift_report {
+    int64_t plain_cell_macro_steps;  /* cell macro steps advanced by the plain method     */
+    int64_t checked;                 /* drift checks made                                 */
+    int64_t flagged;                 /* checks past theta                                 */
+    float ms;                        /* device time of the call                           */
+} infoli_drift_report;
+
+infoli_status infoli_default_train_cfg(infoli_train_cfg *cfg);
+infoli_status infoli_default_drift_cfg(infoli_drift_cfg *cfg);
+
+/* Generate the training set on the device (the context's single network's
+ * cell parameters; independent cells under random currents advanced by the
+ * plain method), normalise it, and train the MLP with Adam. loss_hist
+ * (optional, [cfg->steps]) receives the loss of every step. Blocking. */
+infoli_status infoli_surrogate_train(infoli_ctx *ctx, const infoli_train_cfg *cfg,
+                                     infoli_train_report *report, float *loss_hist);
+
+/* Copy out (either pointer may be NULL) or install trained weights and
+ * normalisation (params [INFOLI_MLP_PARAMS], norm [64]; scales > 0). */
+infoli_status infoli_surrogate_get(infoli_ctx *ctx, float *params, float *norm);
+infoli_status infoli_surrogate_set(infoli_ctx *ctx, const float *params, const float *norm);
+
+/* Advance n_macro macro steps of 4 time steps each (single-network contexts).
+ * cfg NULL => defaults (theta 0.5 mV, Vs > -40 mV plain, 1/64 checked per macro
+ * step, 50 macro steps of fallback). report optional (blocking when given). */
+infoli_status infoli_step_surrogate(infoli_ctx *ctx, int64_t n_macro, const infoli_drift_cfg *cfg,
+                                    infoli_drift_report *report);
+
+/* The MLP kernels on host data, blocking: forward y[batch][16] of x[batch][16];
+ * loss (mean over the batch and the first 14 outputs of the squared error) and
+ * its gradient grad[INFOLI_MLP_PARAMS]; one Adam step on params/m/v in place
+ * (bias correction with step t >= 1). batch: multiple of 16. */
+infoli_status infoli_mlp_forward(const float *params, const float *x, int32_t batch, float *y);
+infoli_status infoli_mlp_loss_grad(const float *params, const float *x, const float *t, int32_t batch,
+                                   float *loss, float *grad);
+infoli_status infoli_mlp_adam_step(float *params, float *m, float *v, const float *grad, int64_t t,
+                                   float lr, float beta1, float beta2, float eps);
+
 /* Names of state variables ("Vd", "Ca", ...); NULL when out of range. */
 const char *infoli_state_var_name(int32_t v);
 

@@ -15,10 +15,13 @@ HIPCC_FLAGS = [
 ]
 
 
+SOURCES = ("runtime.hip", "surrogate.hip")
+
+
 def build_library(verbose: bool = False) -> str:
-    """Compile csrc/runtime.hip (which includes the kernels) to libinfoli.so."""
+    """Compile the host runtime and kernels (csrc/*.hip) to libinfoli.so."""
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, os.path.join(CSRC, "runtime.hip")]
+    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp] + [os.path.join(CSRC, f) for f in SOURCES]
     res = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)

@@ -1,0 +1,181 @@
+// Host-side context of the library, shared by the step driver (runtime.hip)
+// and the surrogate (surrogate.hip). Internal: not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/infoli.h"
+#include "cell_model.hpp"
+#include "mlp_kernel.hpp"
+#include "step_kernel.hpp"
+
+namespace infoli_rt {
+
+using namespace infoli;
+
+extern thread_local std::string g_thread_error;
+
+extern const float kDefaultParams[INFOLI_NUM_PARAMS];
+extern const char* const kStateNames[INFOLI_NUM_STATE];
+
+struct Fail {
+    infoli_status code;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(infoli_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    throw Fail{code, buf};
+}
+
+#define HIPX(expr)                                                                   \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            fail(e_ == hipErrorOutOfMemory ? INFOLI_E_OUT_OF_MEMORY : INFOLI_E_DEVICE, \
+                 "%s: %s", #expr, hipGetErrorString(e_));                            \
+    } while (0)
+
+inline bool finite_all(const float* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+void rest_state_host(const float* P, float v0, float* x);
+
+struct SurrogateState {
+    bool ready = false;                 // weights and normalisation present
+    float* params = nullptr;            // [kNumParams] fp32 masters
+    float* m = nullptr;                 // Adam moments
+    float* v = nullptr;
+    float* grad = nullptr;
+    uint16_t* wb = nullptr;             // bf16 copies
+    float norm[64] = {0};               // in_mean[16] in_rstd[16] out_mean[16] out_std[16]
+    int32_t* hold = nullptr;            // [cells]
+    uint32_t* counters = nullptr;       // [4]
+};
+
+}  // namespace infoli_rt
+
+using namespace infoli;
+using infoli_rt::fail;
+
+struct infoli_ctx {
+    infoli_rt::SurrogateState surr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    infoli_options opt{};
+    std::string err;
+
+    int32_t n_inst = 0;
+    std::vector<InstDesc> inst;     // host copies of the descriptors
+    std::vector<Tile> tiles;
+    int64_t total_cells = 0;
+    int64_t stride = 0;
+    int64_t pairs_per_step = 0;
+    float dt = 0.05f;
+    int block = 256;
+    int persist_cpt = 1;            // cells per thread of the persistent kernel
+    size_t lds_bytes = 16;          // dynamic LDS of the step kernel
+    std::vector<int> rows_of;       // tile rows per network
+    std::vector<double> deg_of;     // mean gap-junction degree per network
+    int tuned = 0;                  // networks whose tiles came from timing runs
+    int tune_cached = 0;            // networks whose tiles came from the tuning cache
+
+    // device memory
+    std::vector<void*> allocs;
+    size_t device_bytes = 0;
+    float* state[2] = {nullptr, nullptr};
+    int cur = 0;
+    float* igap = nullptr;
+    float* bias = nullptr;
+    InstDesc* d_inst = nullptr;
+    Tile* d_tiles = nullptr;
+    DevPulse* d_pulses = nullptr;
+    int64_t* d_rowptr = nullptr;
+    int32_t* d_col = nullptr;
+    uint16_t* d_col16 = nullptr;
+    float* d_w = nullptr;
+    float* d_stream = nullptr;
+    int32_t* d_spk_count = nullptr;
+    float* d_spk_times = nullptr;
+    int32_t* d_flags = nullptr;
+    int64_t* d_step = nullptr;
+
+    int64_t step = 0;               // absolute index of the next step to run
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // by starting buffer parity
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+
+    template <typename T>
+    T* alloc(size_t count) {
+        if (count == 0) count = 1;
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess)
+            fail(INFOLI_E_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                 hipGetErrorString(e));
+        allocs.push_back(p);
+        device_bytes += count * sizeof(T);
+        return static_cast<T*>(p);
+    }
+
+    void release() {
+        for (int k = 0; k < 2; ++k)
+            if (graph[k]) (void)hipGraphExecDestroy(graph[k]);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* p : allocs) (void)hipFree(p);
+        allocs.clear();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace infoli_rt {
+
+inline void set_err(infoli_ctx* ctx, const std::string& m) {
+    g_thread_error = m;
+    if (ctx) ctx->err = m;
+}
+
+template <typename F>
+infoli_status guarded(infoli_ctx* ctx, F&& f) {
+    try {
+        f();
+        return INFOLI_OK;
+    } catch (const Fail& e) {
+        set_err(ctx, e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_err(ctx, "host allocation failed");
+        return INFOLI_E_OUT_OF_MEMORY;
+    } catch (...) {
+        set_err(ctx, "unexpected internal error");
+        return INFOLI_E_DEVICE;
+    }
+}
+
+StepArgs make_args(const infoli_ctx* c, bool device_step);
+void launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, unsigned ntiles, size_t lds, int from,
+                  int64_t step_arg, int32_t off);
+void check_instance(const infoli_ctx* c, int32_t k);
+
+}  // namespace infoli_rt

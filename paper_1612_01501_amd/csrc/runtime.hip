@@ -2,33 +2,18 @@
 // device-resident network data (Section 2.4.3: everything the run needs is
 // copied to the device once), tile planning and the step driver (one
 // launch per step, or chunks of steps replayed from a HIP graph).
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <map>
-#include <new>
 #include <sys/stat.h>
-#include <string>
-#include <vector>
 
-#include "../../include/infoli.h"
-#include "cell_model.hpp"
-#include "step_kernel.hpp"
+#include "context.hpp"
 #include "persist_kernel.hpp"
 
-using namespace infoli;
-
-namespace {
+namespace infoli_rt {
 
 thread_local std::string g_thread_error;
 
 // Default cell parameters, in the order of INFOLI_NUM_PARAMS, of the
 // published three-compartment inferior-olive model.
+extern const float kDefaultParams[INFOLI_NUM_PARAMS];
 const float kDefaultParams[INFOLI_NUM_PARAMS] = {
     4.5f,    // g_CaH
     35.0f,   // g_KCa
@@ -52,36 +37,9 @@ const float kDefaultParams[INFOLI_NUM_PARAMS] = {
     10.0f,   // V_L
 };
 
+extern const char* const kStateNames[INFOLI_NUM_STATE];
 const char* const kStateNames[INFOLI_NUM_STATE] = {"Vd", "Ca", "r", "s", "q", "Vs", "k",
                                                    "l",  "h",  "n", "x", "Va", "ha", "xa"};
-
-struct Fail {
-    infoli_status code;
-    std::string msg;
-};
-
-[[noreturn]] void fail(infoli_status code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    throw Fail{code, buf};
-}
-
-#define HIPX(expr)                                                                   \
-    do {                                                                             \
-        hipError_t e_ = (expr);                                                      \
-        if (e_ != hipSuccess)                                                        \
-            fail(e_ == hipErrorOutOfMemory ? INFOLI_E_OUT_OF_MEMORY : INFOLI_E_DEVICE, \
-                 "%s: %s", #expr, hipGetErrorString(e_));                            \
-    } while (0)
-
-bool finite_all(const float* p, int64_t n) {
-    for (int64_t i = 0; i < n; ++i)
-        if (!std::isfinite(p[i])) return false;
-    return true;
-}
 
 // Host copy of one rest-state computation (every voltage at v0, gates and
 // [Ca2+] at their steady state there).
@@ -112,110 +70,11 @@ void rest_state_host(const float* P, float v0, float* x) {
     x[SV_XA] = ax / (ax + bx);
 }
 
-template <typename T>
-struct DevBuf {
-    T* p = nullptr;
-    size_t n = 0;
-};
+}  // namespace infoli_rt
 
-}  // namespace
-
-struct infoli_ctx {
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    hipStream_t cap_stream = nullptr;
-    infoli_options opt{};
-    std::string err;
-
-    int32_t n_inst = 0;
-    std::vector<InstDesc> inst;     // host copies of the descriptors
-    std::vector<Tile> tiles;
-    int64_t total_cells = 0;
-    int64_t stride = 0;
-    int64_t pairs_per_step = 0;
-    float dt = 0.05f;
-    int block = 256;
-    int persist_cpt = 1;            // cells per thread of the persistent kernel
-    size_t lds_bytes = 16;          // dynamic LDS of the step kernel
-    std::vector<int> rows_of;       // tile rows per network
-    std::vector<double> deg_of;     // mean gap-junction degree per network
-    int tuned = 0;                  // networks whose tiles came from timing runs
-    int tune_cached = 0;            // networks whose tiles came from the tuning cache
-
-    // device memory
-    std::vector<void*> allocs;
-    size_t device_bytes = 0;
-    float* state[2] = {nullptr, nullptr};
-    int cur = 0;
-    float* igap = nullptr;
-    float* bias = nullptr;
-    InstDesc* d_inst = nullptr;
-    Tile* d_tiles = nullptr;
-    DevPulse* d_pulses = nullptr;
-    int64_t* d_rowptr = nullptr;
-    int32_t* d_col = nullptr;
-    uint16_t* d_col16 = nullptr;
-    float* d_w = nullptr;
-    float* d_stream = nullptr;
-    int32_t* d_spk_count = nullptr;
-    float* d_spk_times = nullptr;
-    int32_t* d_flags = nullptr;
-    int64_t* d_step = nullptr;
-
-    int64_t step = 0;               // absolute index of the next step to run
-    hipGraphExec_t graph[2] = {nullptr, nullptr};  // by starting buffer parity
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    bool timed = false;
-
-    template <typename T>
-    T* alloc(size_t count) {
-        if (count == 0) count = 1;
-        void* p = nullptr;
-        hipError_t e = hipMalloc(&p, count * sizeof(T));
-        if (e != hipSuccess)
-            fail(INFOLI_E_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
-                 hipGetErrorString(e));
-        allocs.push_back(p);
-        device_bytes += count * sizeof(T);
-        return static_cast<T*>(p);
-    }
-
-    void release() {
-        for (int k = 0; k < 2; ++k)
-            if (graph[k]) (void)hipGraphExecDestroy(graph[k]);
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-        if (stream) (void)hipStreamSynchronize(stream);
-        for (void* p : allocs) (void)hipFree(p);
-        allocs.clear();
-        if (cap_stream) (void)hipStreamDestroy(cap_stream);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
-    }
-};
+using namespace infoli_rt;
 
 namespace {
-
-void set_err(infoli_ctx* ctx, const std::string& m) {
-    g_thread_error = m;
-    if (ctx) ctx->err = m;
-}
-
-template <typename F>
-infoli_status guarded(infoli_ctx* ctx, F&& f) {
-    try {
-        f();
-        return INFOLI_OK;
-    } catch (const Fail& e) {
-        set_err(ctx, e.msg);
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        set_err(ctx, "host allocation failed");
-        return INFOLI_E_OUT_OF_MEMORY;
-    } catch (...) {
-        set_err(ctx, "unexpected internal error");
-        return INFOLI_E_DEVICE;
-    }
-}
 
 void validate_spec(const infoli_network_spec& s, int k) {
     if (s.n_cells < 1) fail(INFOLI_E_INVALID_ARG, "network %d: n_cells must be >= 1", k);
@@ -291,9 +150,9 @@ int pick_lanes(double mean_degree, int block) {
     return L;
 }
 
-StepArgs make_args(const infoli_ctx* c, bool device_step);
+}  // namespace
 
-void launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, unsigned ntiles, size_t lds, int from,
+void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, unsigned ntiles, size_t lds, int from,
                   int64_t step_arg, int32_t off) {
     if (c->block == 1024)
         hipLaunchKernelGGL(k_step<1024>, dim3(ntiles), dim3(1024), lds, st, a, c->state[from],
@@ -302,6 +161,8 @@ void launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, unsigned nti
         hipLaunchKernelGGL(k_step<256>, dim3(ntiles), dim3(256), lds, st, a, c->state[from],
                            c->state[from ^ 1], step_arg, off);
 }
+
+namespace {
 
 void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int rows, double deg) {
     for (int r = 0; r < n; r += rows) {
@@ -682,7 +543,9 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     HIPX(hipDeviceSynchronize());
 }
 
-StepArgs make_args(const infoli_ctx* c, bool device_step) {
+}  // namespace
+
+StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.inst = c->d_inst;
@@ -705,6 +568,8 @@ StepArgs make_args(const infoli_ctx* c, bool device_step) {
     a.gap_only = 0;
     return a;
 }
+
+namespace {
 
 void launch_step(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
                  int32_t off) {
@@ -779,11 +644,12 @@ void run_steps(infoli_ctx* c, int64_t n_steps) {
     c->timed = true;
 }
 
-void check_instance(const infoli_ctx* c, int32_t k) {
+}  // namespace
+
+void infoli_rt::check_instance(const infoli_ctx* c, int32_t k) {
     if (k < 0 || k >= c->n_inst) fail(INFOLI_E_INVALID_ARG, "instance %d out of range", k);
 }
 
-}  // namespace
 
 extern "C" {
 

@@ -359,7 +359,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
     }
 }
 
-__global__ void k_set_step(int64_t* d_step, int64_t value) {
+static __global__ void k_set_step(int64_t* d_step, int64_t value) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *d_step = value;
 }
 

@@ -1,0 +1,289 @@
+// Surrogate macro step (four time steps of dt) and its training data.
+//
+// A macro step holds each cell's gap current (computed exactly, in fp32, from
+// the Vd at the macro step's start) and evoked input for its four steps; the
+// MLP maps the normalised [state, I_gap, I_app] to the normalised state
+// increment. The plain method stays the judge and the fallback: cells in the
+// spiking regime (Vs above a threshold), cells flagged by an earlier drift
+// check, and a rotating sample of cells re-checked this macro step are
+// advanced by four plain forward-Euler steps; a checked cell whose MLP result
+// differs from the plain one by more than theta in any voltage is flagged for
+// a number of macro steps. Every cell advanced by the plain method takes the
+// plain result.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cell_model.hpp"
+#include "mlp_kernel.hpp"
+#include "step_kernel.hpp"
+
+namespace infoli {
+
+// Normalisation: 16 input features (14 states, I_gap, I_app) and 16 outputs
+// (14 state increments over the macro step, two pads).
+struct NormStats {
+    float in_mean[16], in_rstd[16];
+    float out_mean[16], out_std[16];
+};
+
+struct SurrArgs {
+    const float* params;        // fp32 masters (biases)
+    const uint16_t* wb;         // bf16 weights
+    NormStats norm;
+    const float* igap;          // [cells] held gap currents
+    int32_t* hold;              // [cells] macro steps left on the plain method
+    uint32_t* counters;         // [0] cells on plain, [1] checked, [2] newly flagged
+    float theta_mv;             // drift threshold on Vd, Vs, Va
+    float vs_spiking;           // Vs above this: plain method
+    int32_t sample_every;       // check cells with (cell + macro) % sample_every == 0; 0 = never
+    int32_t hold_steps;         // macro steps a flagged cell stays on the plain method
+    int32_t mode;               // 0 surrogate, 1 plain for every cell (gap held 4 steps)
+    int64_t macro_index;
+};
+
+constexpr int kMacro = 4;
+
+// One wave = 16 cells; four lanes per cell (feature groups of four).
+static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrArgs s, const float* __restrict__ xin,
+                                                        float* __restrict__ xout, int64_t step0,
+                                                        int64_t n_cells_total) {
+    __shared__ uint16_t s_w[kMlpLdsElems];
+    const MlpSmem sm = mlp_smem(s_w);
+    if (s.mode == 0) {
+        load_weights_lds(s.wb, sm);
+        __syncthreads();
+    }
+    const int l = threadIdx.x & 63;
+    const int g = l >> 4;
+    const int waves = blockDim.x >> 6;
+    for (int64_t base = ((int64_t)blockIdx.x * waves + (threadIdx.x >> 6)) * 16; base < n_cells_total;
+         base += (int64_t)gridDim.x * waves * 16) {
+        const int64_t cell = base + (l & 15);
+        const bool live = cell < n_cells_total;
+        const int64_t c = live ? cell : n_cells_total - 1;
+        const InstDesc& d = a.inst[0];      // surrogate contexts hold one network
+        const int li = (int)(c - d.cell_off);
+        const float ig = s.igap[c];
+        const float ia0 = evoked_input(a, d, step0, li, c);
+
+        // decide plain vs MLP (lanes of group 0 look at the cell's soma voltage)
+        const float vs0 = xin[SV_VS * a.stride + c];
+        int hold = s.hold[c];
+        const bool check = s.sample_every > 0 &&
+                           ((c + s.macro_index) % s.sample_every) == 0;
+        const bool plain = s.mode == 1 || hold > 0 || vs0 > s.vs_spiking || check;
+
+        // MLP on every lane (the matrix cores need the whole wave)
+        f32x4 y = {0.0f, 0.0f, 0.0f, 0.0f};
+        f32x4 xg;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int v = 4 * g + e;
+            xg[e] = v < NSV ? xin[v * a.stride + c] : 0.0f;
+        }
+        if (s.mode == 0) {
+            f32x4 xnv;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int v = 4 * g + e;
+                const float raw = v < NSV ? xg[e] : (v == 14 ? ig : ia0);
+                xnv[e] = (raw - s.norm.in_mean[v]) * s.norm.in_rstd[v];
+            }
+            y = mlp_forward(sm, s.params, pack_bf16(xnv), nullptr, nullptr);
+        }
+        // MLP candidate: x + denormalised increment (lane holds 4 variables)
+        f32x4 xm;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int v = 4 * g + e;
+            xm[e] = xg[e] + (y[e] * s.norm.out_std[v] + s.norm.out_mean[v]);
+        }
+        // voltages of the MLP candidate, gathered to the cell's group-0 lane
+        const float mvd = __shfl(xm[0], (l & 15), 64);           // v = 0  (g 0, e 0)
+        const float mvs = __shfl(xm[1], (l & 15) + 16, 64);      // v = 5  (g 1, e 1)
+        const float mva = __shfl(xm[3], (l & 15) + 32, 64);      // v = 11 (g 2, e 3)
+
+        if (!plain) {
+            if (live)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int v = 4 * g + e;
+                    if (v < NSV) xout[v * a.stride + c] = xm[e];
+                }
+            // spike of an MLP cell: Va crossing 0 mV within the macro step
+            if (g == 0 && live) {
+                const float va0 = xin[SV_VA * a.stride + c];
+                if (va0 < 0.0f && mva >= 0.0f) {
+                    const int cnt = a.spike_count[c];
+                    if (a.spike_cap > 0) {
+                        const float frac = (0.0f - va0) / (mva - va0);
+                        a.spike_times[c * a.spike_cap + (cnt % a.spike_cap)] =
+                            ((float)step0 + kMacro * frac) * a.dt;
+                    }
+                    a.spike_count[c] = cnt + 1;
+                }
+            }
+        } else if (g == 0 && live) {
+            // plain method: four forward-Euler steps with the gap current held
+            float x[NSV], yv[NSV];
+#pragma unroll
+            for (int v = 0; v < NSV; ++v) x[v] = xin[v * a.stride + c];
+            int cnt = a.spike_count[c];
+            for (int k = 0; k < kMacro; ++k) {
+                const int64_t st = step0 + k;
+                cell_step(d.p, x, ig, evoked_input(a, d, st, li, c), a.dt, yv);
+                if (x[SV_VA] < 0.0f && yv[SV_VA] >= 0.0f) {
+                    if (a.spike_cap > 0) {
+                        const float frac = (0.0f - x[SV_VA]) / (yv[SV_VA] - x[SV_VA]);
+                        a.spike_times[c * a.spike_cap + (cnt % a.spike_cap)] = ((float)st + frac) * a.dt;
+                    }
+                    ++cnt;
+                }
+#pragma unroll
+                for (int v = 0; v < NSV; ++v) x[v] = yv[v];
+            }
+            a.spike_count[c] = cnt;
+            float chk = 0.0f;
+#pragma unroll
+            for (int v = 0; v < NSV; ++v) {
+                xout[v * a.stride + c] = x[v];
+                chk += x[v];
+            }
+            if (!isfinite(chk)) atomicOr(a.flags, 1);
+            int new_hold = hold > 0 ? hold - 1 : 0;
+            if (s.mode == 0 && check) {
+                atomicAdd(&s.counters[1], 1u);
+                const float dev = fmaxf(fabsf(mvd - x[SV_VD]), fmaxf(fabsf(mvs - x[SV_VS]), fabsf(mva - x[SV_VA])));
+                if (!(dev <= s.theta_mv)) {
+                    new_hold = s.hold_steps;
+                    atomicAdd(&s.counters[2], 1u);
+                }
+            }
+            if (new_hold != hold) s.hold[c] = new_hold;
+            atomicAdd(&s.counters[0], 1u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- training data
+// Independent cells driven by random currents, advanced by the plain method:
+// each macro step records (state, I_gap, I_app) and the state increment over
+// four steps with both currents held. Per trajectory: a constant bias
+// N(0, bias_sd); a gap current following an AR(1) process with stationary
+// standard deviation gap_sd and lag-one correlation gap_rho per macro step;
+// pulses of amplitude U[pulse_lo, pulse_hi] lasting pulse_len macro steps,
+// starting with probability pulse_p per macro step. Initial state: rest plus
+// U[-1, 1] mV on the three voltages. Random numbers: SplitMix64 finaliser of
+// (seed, trajectory, macro step, stream), uniform in (0, 1) from 24 bits.
+struct DataGenArgs {
+    CellParams p;
+    float rest[NSV];
+    float dt;
+    float bias_sd, gap_sd, gap_rho, pulse_p, pulse_lo, pulse_hi;
+    int32_t pulse_len;
+    int32_t burn_in;          // macro steps not recorded
+    int32_t per_traj;         // recorded macro steps per trajectory
+    int32_t n_traj;
+    uint64_t seed;
+    float* x_raw;             // [N][16] state, I_gap, I_app
+    float* d_raw;             // [N][16] increments (pads zero)
+};
+
+__device__ __forceinline__ float u01(uint64_t seed, uint64_t traj, uint64_t m, uint64_t stream) {
+    const uint64_t h = mix64(seed ^ mix64(traj * 0x100000001b3ull + (m << 8) + stream));
+    return ((float)(h >> 40) + 0.5f) * (1.0f / 16777216.0f);
+}
+__device__ __forceinline__ float normal01(uint64_t seed, uint64_t traj, uint64_t m, uint64_t stream) {
+    // Box-Muller
+    const float u1 = u01(seed, traj, m, stream), u2 = u01(seed, traj, m, stream + 1);
+    return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
+static __global__ void k_surrogate_data(DataGenArgs g) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.n_traj) return;
+    float x[NSV], y[NSV];
+#pragma unroll
+    for (int v = 0; v < NSV; ++v) x[v] = g.rest[v];
+    x[SV_VD] += 2.0f * u01(g.seed, t, 0, 10) - 1.0f;
+    x[SV_VS] += 2.0f * u01(g.seed, t, 0, 11) - 1.0f;
+    x[SV_VA] += 2.0f * u01(g.seed, t, 0, 12) - 1.0f;
+    const float bias = g.bias_sd * normal01(g.seed, t, 0, 20);
+    float gap = g.gap_sd * normal01(g.seed, t, 0, 30);
+    int pulse_left = 0;
+    float pulse_amp = 0.0f;
+    const float innov = g.gap_sd * sqrtf(1.0f - g.gap_rho * g.gap_rho);
+    for (int m = 1; m <= g.burn_in + g.per_traj; ++m) {
+        gap = g.gap_rho * gap + innov * normal01(g.seed, t, m, 40);
+        if (pulse_left == 0 && u01(g.seed, t, m, 50) < g.pulse_p) {
+            pulse_left = g.pulse_len;
+            pulse_amp = g.pulse_lo + (g.pulse_hi - g.pulse_lo) * u01(g.seed, t, m, 51);
+        }
+        const float iapp = bias + (pulse_left > 0 ? pulse_amp : 0.0f);
+        if (pulse_left > 0) --pulse_left;
+        float x0[NSV];
+#pragma unroll
+        for (int v = 0; v < NSV; ++v) x0[v] = x[v];
+        for (int k = 0; k < kMacro; ++k) {
+            cell_step(g.p, x, gap, iapp, g.dt, y);
+#pragma unroll
+            for (int v = 0; v < NSV; ++v) x[v] = y[v];
+        }
+        if (m > g.burn_in) {
+            const int64_t r = (int64_t)(m - g.burn_in - 1) * g.n_traj + t;
+            float* xr = g.x_raw + r * 16;
+            float* dr = g.d_raw + r * 16;
+#pragma unroll
+            for (int v = 0; v < NSV; ++v) {
+                xr[v] = x0[v];
+                dr[v] = x[v] - x0[v];
+            }
+            xr[14] = gap;
+            xr[15] = iapp;
+            dr[14] = 0.0f;
+            dr[15] = 0.0f;
+        }
+    }
+}
+
+// Per-feature mean and standard deviation of a [N][16] array: one workgroup
+// per feature, fixed-order fp64 reduction.
+static __global__ __launch_bounds__(256) void k_feature_stats(const float* __restrict__ a, int64_t n,
+                                                       double* __restrict__ out /* [16][2] */) {
+    __shared__ double s1[256], s2[256];
+    const int f = blockIdx.x;
+    double m = 0.0, q = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+        const double v = a[r * 16 + f];
+        m += v;
+        q += v * v;
+    }
+    s1[threadIdx.x] = m;
+    s2[threadIdx.x] = q;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+            s2[threadIdx.x] += s2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mean = s1[0] / (double)n;
+        const double var = s2[0] / (double)n - mean * mean;
+        out[2 * f] = mean;
+        out[2 * f + 1] = var > 0.0 ? sqrt(var) : 0.0;
+    }
+}
+
+// In-place normalisation of inputs and targets.
+static __global__ void k_normalize(float* __restrict__ x, float* __restrict__ t, int64_t n, NormStats ns) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * 16) return;
+    const int f = (int)(e % 16);
+    x[e] = (x[e] - ns.in_mean[f]) * ns.in_rstd[f];
+    t[e] = f < kTargets ? (t[e] - ns.out_mean[f]) / ns.out_std[f] : 0.0f;
+}
+
+}  // namespace infoli
