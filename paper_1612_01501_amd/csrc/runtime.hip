@@ -359,11 +359,11 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->n_inst = ninst;
     c->dt = specs[0].dt_ms;
     c->step = specs[0].step0;
-    // 1024-thread workgroups when all-to-all rows dominate (16 waves share the
+    // 1024-thread workgroups for large all-to-all networks (16 waves share the
     // sender range of a 64-row tile); 256 otherwise
     c->block = 256;
     for (int k = 0; k < ninst; ++k)
-        if (specs[k].conn == INFOLI_CONN_UNIFORM_ALL && specs[k].n_cells >= 2048) c->block = 1024;
+        if (specs[k].conn == INFOLI_CONN_UNIFORM_ALL && specs[k].n_cells >= 8192) c->block = 1024;
 
     // ---- layout of the flattened networks
     int64_t cells = 0, rp_total = 0, w_total = 0, col_total = 0, stream_total = 0;

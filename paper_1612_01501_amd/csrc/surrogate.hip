@@ -93,8 +93,13 @@ void launch_macro(infoli_ctx* c, hipStream_t st, const infoli_drift_cfg& dc, int
     g.gap_only = 1;
     launch_tiles(c, st, g, (unsigned)c->tiles.size(), c->lds_bytes, from, step0, 0);
     const StepArgs a = make_args(c, false);
-    const SurrArgs s = surr_args(c, dc, step0 / kMacro);
     const int64_t cells = c->total_cells;
+    if (dc.mode == INFOLI_SURROGATE_PLAIN_HOLD) {
+        hipLaunchKernelGGL(k_hold4, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, a, c->igap,
+                           c->state[from], c->state[from ^ 1], step0, cells);
+        return;
+    }
+    const SurrArgs s = surr_args(c, dc, step0 / kMacro);
     const unsigned blocks = (unsigned)std::min<int64_t>((cells + 63) / 64, 1024);
     hipLaunchKernelGGL(k_surrogate_step, dim3(blocks), dim3(256), 0, st, a, s, c->state[from],
                        c->state[from ^ 1], step0, cells);

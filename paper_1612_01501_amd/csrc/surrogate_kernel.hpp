@@ -166,6 +166,44 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
     }
 }
 
+// Four plain forward-Euler steps per cell with the macro step's gap current
+// held (the surrogate's ablation without the MLP): one thread per cell.
+static __global__ __launch_bounds__(256) void k_hold4(StepArgs a, const float* __restrict__ igap,
+                                                      const float* __restrict__ xin, float* __restrict__ xout,
+                                                      int64_t step0, int64_t n_cells_total) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells_total) return;
+    const InstDesc& d = a.inst[0];
+    const int li = (int)(c - d.cell_off);
+    const float ig = igap[c];
+    float x[NSV], y[NSV];
+#pragma unroll
+    for (int v = 0; v < NSV; ++v) x[v] = xin[v * a.stride + c];
+    int cnt = a.spike_count[c];
+    const int cnt0 = cnt;
+    for (int k = 0; k < kMacro; ++k) {
+        const int64_t st = step0 + k;
+        cell_step(d.p, x, ig, evoked_input(a, d, st, li, c), a.dt, y);
+        if (x[SV_VA] < 0.0f && y[SV_VA] >= 0.0f) {
+            if (a.spike_cap > 0) {
+                const float frac = (0.0f - x[SV_VA]) / (y[SV_VA] - x[SV_VA]);
+                a.spike_times[c * a.spike_cap + (cnt % a.spike_cap)] = ((float)st + frac) * a.dt;
+            }
+            ++cnt;
+        }
+#pragma unroll
+        for (int v = 0; v < NSV; ++v) x[v] = y[v];
+    }
+    if (cnt != cnt0) a.spike_count[c] = cnt;
+    float chk = 0.0f;
+#pragma unroll
+    for (int v = 0; v < NSV; ++v) {
+        xout[v * a.stride + c] = x[v];
+        chk += x[v];
+    }
+    if (!isfinite(chk)) atomicOr(a.flags, 1);
+}
+
 // ---------------------------------------------------------------- training data
 // Independent cells driven by random currents, advanced by the plain method:
 // each macro step records (state, I_gap, I_app) and the state increment over

@@ -32,7 +32,12 @@ EXPORTS = (
     "infoli_read_state_device", "infoli_write_state", "infoli_read_gap_current",
     "infoli_read_spikes", "infoli_clear_spikes", "infoli_get_info", "infoli_last_step_ms",
     "infoli_state_var_name", "infoli_last_error", "infoli_destroy",
+    "infoli_default_train_cfg", "infoli_default_drift_cfg", "infoli_surrogate_train",
+    "infoli_surrogate_get", "infoli_surrogate_set", "infoli_step_surrogate",
+    "infoli_mlp_forward", "infoli_mlp_loss_grad", "infoli_mlp_adam_step",
 )
+MLP_PARAMS = 20752
+SURROGATE_MODE = {"mlp": 0, "plain_hold": 1}
 
 
 class InfoliError(RuntimeError):
@@ -77,6 +82,33 @@ class Info(ctypes.Structure):
                 ("tune_cached", ctypes.c_int32)]
 
 
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("n_transitions", ctypes.c_int64), ("n_trajectories", ctypes.c_int32),
+                ("burn_in", ctypes.c_int32), ("batch", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("bias_sd", ctypes.c_float), ("gap_sd", ctypes.c_float),
+                ("gap_rho", ctypes.c_float), ("pulse_p", ctypes.c_float), ("pulse_lo", ctypes.c_float),
+                ("pulse_hi", ctypes.c_float), ("pulse_len", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("init_params", _PF)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("n_transitions", ctypes.c_int64), ("steps", ctypes.c_int32),
+                ("loss_first", ctypes.c_float), ("loss_last", ctypes.c_float),
+                ("data_ms", ctypes.c_float), ("train_ms", ctypes.c_float)]
+
+
+class DriftCfg(ctypes.Structure):
+    _fields_ = [("theta_mv", ctypes.c_float), ("vs_spiking", ctypes.c_float),
+                ("sample_every", ctypes.c_int32), ("hold_steps", ctypes.c_int32),
+                ("mode", ctypes.c_int32)]
+
+
+class DriftReport(ctypes.Structure):
+    _fields_ = [("plain_cell_macro_steps", ctypes.c_int64), ("checked", ctypes.c_int64),
+                ("flagged", ctypes.c_int64), ("ms", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -112,6 +144,17 @@ def lib():
     L.infoli_last_error.restype = ctypes.c_char_p
     L.infoli_destroy.argtypes = [vp]
     L.infoli_destroy.restype = None
+    L.infoli_default_train_cfg.argtypes = [ctypes.POINTER(TrainCfg)]
+    L.infoli_default_drift_cfg.argtypes = [ctypes.POINTER(DriftCfg)]
+    L.infoli_surrogate_train.argtypes = [vp, ctypes.POINTER(TrainCfg), ctypes.POINTER(TrainReport), _PF]
+    L.infoli_surrogate_get.argtypes = [vp, _PF, _PF]
+    L.infoli_surrogate_set.argtypes = [vp, _PF, _PF]
+    L.infoli_step_surrogate.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(DriftCfg),
+                                        ctypes.POINTER(DriftReport)]
+    L.infoli_mlp_forward.argtypes = [_PF, _PF, ctypes.c_int32, _PF]
+    L.infoli_mlp_loss_grad.argtypes = [_PF, _PF, _PF, ctypes.c_int32, _PF, _PF]
+    L.infoli_mlp_adam_step.argtypes = [_PF, _PF, _PF, _PF, ctypes.c_int64, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_float]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("infoli_state_var_name", "infoli_last_error", "infoli_destroy"):
@@ -161,6 +204,55 @@ def initial_state(net: "_inputs.Network", v0: float = _inputs.REST_MV) -> np.nda
         for row, v in enumerate((_inputs.IDX_VD, _inputs.IDX_VS, _inputs.IDX_VA)):
             x[v] += net.jitter[row]
     return np.ascontiguousarray(x.astype(np.float32))
+
+
+def default_train_cfg(**kw) -> TrainCfg:
+    c = TrainCfg()
+    _check(lib().infoli_default_train_cfg(ctypes.byref(c)))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def default_drift_cfg(**kw) -> DriftCfg:
+    c = DriftCfg()
+    _check(lib().infoli_default_drift_cfg(ctypes.byref(c)))
+    for k, v in kw.items():
+        if k == "mode" and isinstance(v, str):
+            v = SURROGATE_MODE[v]
+        setattr(c, k, v)
+    return c
+
+
+def _f32(a, n=None):
+    a = np.ascontiguousarray(a, np.float32)
+    if n is not None:
+        assert a.size == n, (a.size, n)
+    return a
+
+
+def mlp_forward(params, x) -> np.ndarray:
+    """The library's MLP forward kernel on a host batch x [B][16] (B % 16 == 0)."""
+    p, xx = _f32(params, MLP_PARAMS), _f32(x)
+    y = np.zeros_like(xx)
+    _check(lib().infoli_mlp_forward(_fptr(p), _fptr(xx), xx.shape[0], _fptr(y)))
+    return y
+
+
+def mlp_loss_grad(params, x, t):
+    """Loss and gradient from the library's forward/backward kernels."""
+    p, xx, tt = _f32(params, MLP_PARAMS), _f32(x), _f32(t)
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(lib().infoli_mlp_loss_grad(_fptr(p), _fptr(xx), _fptr(tt), xx.shape[0], _fptr(loss), _fptr(g)))
+    return float(loss[0]), g
+
+
+def mlp_adam_step(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    p, mm, vv = _f32(params, MLP_PARAMS).copy(), _f32(m, MLP_PARAMS).copy(), _f32(v, MLP_PARAMS).copy()
+    g = _f32(grad, MLP_PARAMS)
+    _check(lib().infoli_mlp_adam_step(_fptr(p), _fptr(mm), _fptr(vv), _fptr(g), int(t), lr, beta1, beta2, eps))
+    return p, mm, vv
 
 
 class _SpecHolder:
@@ -283,6 +375,36 @@ class Simulator:
         i = Info()
         _check(lib().infoli_get_info(self._ctx, ctypes.byref(i)), self._ctx)
         return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    # ----------------------------------------------------------- surrogate
+    def surrogate_train(self, init_params, cfg: Optional[TrainCfg] = None, **kw):
+        """Train the MLP surrogate on device-generated transitions; returns
+        (report dict, per-step loss array)."""
+        c = cfg if cfg is not None else default_train_cfg(**kw)
+        p = _f32(init_params, MLP_PARAMS)
+        c.init_params = _fptr(p)
+        rep = TrainReport()
+        hist = np.zeros(max(c.steps, 1), np.float32)
+        _check(lib().infoli_surrogate_train(self._ctx, ctypes.byref(c), ctypes.byref(rep), _fptr(hist)),
+               self._ctx)
+        return {f: getattr(rep, f) for f, _ in TrainReport._fields_}, hist[:c.steps]
+
+    def surrogate_get(self):
+        p = np.zeros(MLP_PARAMS, np.float32)
+        n = np.zeros(64, np.float32)
+        _check(lib().infoli_surrogate_get(self._ctx, _fptr(p), _fptr(n)), self._ctx)
+        return p, n
+
+    def surrogate_set(self, params, norm):
+        p, n = _f32(params, MLP_PARAMS), _f32(norm, 64)
+        _check(lib().infoli_surrogate_set(self._ctx, _fptr(p), _fptr(n)), self._ctx)
+
+    def step_surrogate(self, n_macro: int, cfg: Optional[DriftCfg] = None, report: bool = True, **kw):
+        c = cfg if cfg is not None else default_drift_cfg(**kw)
+        rep = DriftReport()
+        _check(lib().infoli_step_surrogate(self._ctx, int(n_macro), ctypes.byref(c),
+                                           ctypes.byref(rep) if report else None), self._ctx)
+        return {f: getattr(rep, f) for f, _ in DriftReport._fields_} if report else None
 
     def close(self):
         if getattr(self, "_ctx", None):

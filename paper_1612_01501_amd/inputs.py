@@ -123,8 +123,12 @@ def erdos_renyi_csr(n: int, p: float, seed: int):
     """Symmetric Erdos-Renyi graph without self-loops as sorted CSR.
 
     Every unordered pair i < j is present independently with probability p;
-    a present pair adds the directed edges (i, j) and (j, i).
+    a present pair adds the directed edges (i, j) and (j, i). Networks above
+    16,384 cells draw the present pairs by geometric skips over the upper
+    triangle instead of one uniform per pair (same distribution).
     """
+    if n > 16384 and 0.0 < p < 1.0:
+        return _erdos_renyi_skip(n, p, seed)
     g = rng(seed)
     rows, cols = [], []
     block = max(1, int(4_000_000 // max(n, 1)))
@@ -146,6 +150,44 @@ def erdos_renyi_csr(n: int, p: float, seed: int):
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
     return row_ptr, dst.astype(np.int32)
+
+
+def _erdos_renyi_skip(n: int, p: float, seed: int):
+    g = rng(seed)
+    total = n * (n - 1) // 2                      # pairs i < j, row-major over i
+    chunks, pos = [], -1
+    while True:
+        k = int(max(1024, (total - pos) * p * 1.05 + 10 * np.sqrt(total * p) + 1024))
+        gaps = g.geometric(p, size=k).astype(np.int64)
+        loc = pos + np.cumsum(gaps)
+        inside = loc[loc < total]
+        chunks.append(inside)
+        if len(inside) < len(loc):
+            break
+        pos = int(loc[-1])
+    t = np.concatenate(chunks)
+    # pair index -> (i, j): t = i*(2n-i-1)/2 + (j - i - 1)
+    i = (n - 2 - np.floor(np.sqrt(-8.0 * t + 4.0 * n * (n - 1) - 7.0) / 2.0 - 0.5)).astype(np.int64)
+    first = i * (2 * n - i - 1) // 2
+    i = np.where(first > t, i - 1, i)
+    first = i * (2 * n - i - 1) // 2
+    nxt = (i + 1) * (2 * n - i - 2) // 2
+    i = np.where(nxt <= t, i + 1, i)
+    first = i * (2 * n - i - 1) // 2
+    j = t - first + i + 1
+    # forward edges (i, j) are sorted by (i, j); reverse edges (j, i) by (j, i)
+    order = np.argsort(j * n + i, kind="stable")
+    rr, rc = j[order], i[order]
+    cnt_f = np.bincount(i, minlength=n)
+    cnt_r = np.bincount(rr, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(cnt_f + cnt_r, out=row_ptr[1:])
+    col = np.empty(int(row_ptr[-1]), dtype=np.int32)
+    off_r = np.concatenate([[0], np.cumsum(cnt_r)[:-1]])
+    off_f = np.concatenate([[0], np.cumsum(cnt_f)[:-1]])
+    col[row_ptr[:-1][rr] + (np.arange(len(rr)) - off_r[rr])] = rc
+    col[row_ptr[:-1][i] + cnt_r[i] + (np.arange(len(i)) - off_f[i])] = j
+    return row_ptr, col
 
 
 def complete_csr(n: int):

@@ -1,0 +1,196 @@
+"""The learned surrogate on the GPU: its MLP kernels against the numpy oracle
+(emulated BF16 at the same rounding points), the drift check and plain
+fallback, the held-gap plain macro step against the CPU oracle, and the
+trained surrogate against the plain method (accuracy and speed)."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_1612_01501_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+VD, VS, VA = 0, 5, 11
+
+
+@pytest.fixture(scope="module")
+def infoli():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1612_01501_amd import infoli as mod
+    mod.lib()
+    return mod
+
+
+def _params(seed):
+    w = I.mlp_init_params(seed).astype(np.float64)
+    w += I.rng(seed + 1).normal(0.0, 0.02, w.shape)          # non-zero biases
+    return w.astype(np.float32)
+
+
+# ------------------------------------------------------------------ kernels vs oracle
+@pytest.mark.parametrize("batch", [16, 64, 1024])
+def test_mlp_forward_matches_oracle(infoli, batch):
+    w = _params(3)
+    x, _ = I.mlp_batch(batch, 4)
+    y = infoli.mlp_forward(w, x).astype(np.float64)
+    ref, _ = M.forward(w.astype(np.float64), x, bf16=True)
+    err = np.abs(y - ref) / (1.0 + np.abs(ref))
+    print(f"forward B={batch}: max scaled error {err.max():.2e}")
+    assert err.max() <= 2e-3
+
+
+@pytest.mark.parametrize("batch", [64, 4096])
+def test_mlp_gradients_match_oracle(infoli, batch):
+    """GPU loss and gradients against the emulated-BF16 oracle: relative error
+    (2-norm over each parameter block) <= 1e-3."""
+    w = _params(5)
+    x, t = I.mlp_batch(batch, 6)
+    loss, g = infoli.mlp_loss_grad(w, x, t)
+    rl, rg = M.loss_and_grad(w.astype(np.float64), x, t, bf16=True)
+    assert loss == pytest.approx(rl, rel=1e-4)
+    gp, rp = M.unpack(g.astype(np.float64)), M.unpack(rg)
+    worst = 0.0
+    for name, _ in M.SHAPES:
+        a, b = gp[name][:14] if name in ("W3", "b3") else gp[name], rp[name][:14] if name in ("W3", "b3") else rp[name]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        worst = max(worst, rel)
+        assert rel <= 1e-3, (name, rel)
+    assert np.all(gp["W3"][14:] == 0) and np.all(gp["b3"][14:] == 0)
+    print(f"gradients B={batch}: worst block relative error {worst:.2e}")
+
+
+def test_adam_step_matches_oracle(infoli):
+    rs = I.rng(9)
+    w = rs.normal(0, 0.1, M.N_PARAMS).astype(np.float32)
+    m = rs.normal(0, 0.01, M.N_PARAMS).astype(np.float32)
+    v = np.abs(rs.normal(0, 0.001, M.N_PARAMS)).astype(np.float32)
+    g = rs.normal(0, 0.05, M.N_PARAMS).astype(np.float32)
+    w1, m1, v1 = infoli.mlp_adam_step(w, m, v, g, 7, lr=2e-3)
+    rw, rm, rv = M.adam_step(w.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                             g.astype(np.float64), 7, lr=2e-3)
+    np.testing.assert_allclose(m1, rm, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(v1, rv, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(w1, rw, rtol=1e-5, atol=2e-7)
+
+
+# ------------------------------------------------------------------ held-gap macro step
+def test_plain_hold_matches_oracle(infoli, o32):
+    """Macro steps without the MLP: the gap current from the macro step's
+    starting Vd held for four plain steps; compared with the same scheme built
+    from the oracle's gap and right-hand-side functions."""
+    net = I.Network(n=64, conn="uniform", g=0.04, jitter=I.voltage_jitter(64, 21),
+                    bias=I.input_bias(64, 22), pulses=[I.Pulse(40, 140, 6.0)])
+    x0 = infoli.initial_state(net)
+    sim = infoli.Simulator(net, init_states=[x0], step_mode="graph")
+    sim.step_surrogate(50, mode="plain_hold")
+    got = sim.read_state(0)
+    sim.close()
+    x = x0.copy()
+    P = net.params
+    for m in range(50):
+        ig = o32.gap(net, x[VD])
+        for k in range(4):
+            ia = o32.iapp(net, 4 * m + k)
+            for i in range(net.n):
+                x[:, i] = x[:, i] + np.float32(net.dt) * o32.rhs(x[:, i], ig[i], ia[i], P)
+    scale = np.abs(x).max(axis=1)
+    err = (np.abs(got.astype(np.float64) - x) .max(axis=1) / scale).max()
+    assert err <= 1e-4, err
+
+
+# ------------------------------------------------------------------ drift check and fallback
+def _trained(infoli, net, x0, steps=1500, n_transitions=400_000):
+    sim = infoli.Simulator(net, init_states=[x0], step_mode="graph")
+    rep, hist = sim.surrogate_train(I.mlp_init_params(5000), steps=steps, n_transitions=n_transitions)
+    return sim, rep, hist
+
+
+def test_forced_fallback(infoli):
+    """theta = 0: every checked cell is flagged and held on the plain method;
+    checking every cell with theta = inf gives exactly the plain result."""
+    net = I.config4(seed=2, n=4096, degree=200)
+    x0 = infoli.initial_state(net)
+    sim, rep, _ = _trained(infoli, net, x0, steps=200, n_transitions=100_000)
+    params, norm = sim.surrogate_get()
+    r1 = sim.step_surrogate(1, theta_mv=0.0, sample_every=64, hold_steps=3)
+    expected = sum(1 for c in range(net.n) if (c + sim.info()["step"] // 4 - 1) % 64 == 0)
+    assert r1["checked"] == expected and r1["flagged"] == expected
+    r2 = sim.step_surrogate(1, theta_mv=0.0, sample_every=64, hold_steps=3)
+    assert r2["plain_cell_macro_steps"] >= expected + r2["checked"]
+    sim.close()
+    out = []
+    for mode, kw in (("mlp", dict(theta_mv=1e30, sample_every=1)), ("plain_hold", {})):
+        s = infoli.Simulator(net, init_states=[x0], step_mode="graph")
+        s.surrogate_set(params, norm)
+        r = s.step_surrogate(10, mode=mode, **kw)
+        out.append(s.read_state(0))
+        s.close()
+        if mode == "mlp":
+            assert r["checked"] == 10 * net.n and r["flagged"] == 0
+    np.testing.assert_array_equal(out[0], out[1])
+
+
+def test_surrogate_set_get_roundtrip_and_errors(infoli):
+    net = I.Network(n=100, conn="none")
+    sim = infoli.Simulator(net)
+    with pytest.raises(infoli.InfoliError) as e:
+        sim.step_surrogate(1)
+    assert e.value.status == 6                     # no surrogate yet
+    w = _params(1)
+    norm = np.concatenate([np.zeros(16), np.ones(16), np.zeros(16), np.ones(16)]).astype(np.float32)
+    bad = norm.copy()
+    bad[20] = 0.0
+    with pytest.raises(infoli.InfoliError):
+        sim.surrogate_set(w, bad)
+    sim.surrogate_set(w, norm)
+    w2, n2 = sim.surrogate_get()
+    np.testing.assert_array_equal(w2, w)
+    np.testing.assert_array_equal(n2, norm)
+    sim.close()
+
+
+# ------------------------------------------------------------------ trained surrogate vs plain
+def test_trained_surrogate_accuracy_and_gain(infoli):
+    """The 65,536-cell recipe at 8,192 cells (mean degree 1,000, g = 3.84e-3,
+    bias, pulse, jitter): after training on device-generated transitions the
+    surrogate run stays within 1 mV RMSE of the plain run over 2,000 steps,
+    spikes (if any) within 0.5 ms, and it is faster than the plain method."""
+    net = I.config4(seed=1, n=8192)
+    x0 = infoli.initial_state(net)
+    sim, rep, hist = _trained(infoli, net, x0, steps=3000, n_transitions=1_000_000)
+    print(f"training: {rep['n_transitions']} transitions, loss {rep['loss_first']:.3e} -> "
+          f"{rep['loss_last']:.3e}, data {rep['data_ms']:.1f} ms, train {rep['train_ms']:.1f} ms")
+    assert rep["loss_last"] < 0.05 * rep["loss_first"]
+    params, norm = sim.surrogate_get()
+    sim.close()
+
+    plain = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
+    surr = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
+    surr.surrogate_set(params, norm)
+    t_plain = t_surr = 0.0
+    sq, cnt = 0.0, 0
+    for _ in range(10):
+        plain.step(200)
+        plain.sync()
+        t_plain += plain.last_step_ms()
+        r = surr.step_surrogate(50)
+        t_surr += r["ms"]
+        a, b = plain.read_state(0), surr.read_state(0)
+        d = (a[[VD, VS, VA]] - b[[VD, VS, VA]]).astype(np.float64)
+        sq += float((d * d).sum())
+        cnt += d.size
+    rmse = np.sqrt(sq / cnt)
+    ca, ta = plain.read_spikes(0)
+    cb, tb = surr.read_spikes(0)
+    plain.close()
+    surr.close()
+    print(f"surrogate vs plain over 2,000 steps: voltage RMSE {rmse:.3f} mV, "
+          f"plain {t_plain:.2f} ms, surrogate {t_surr:.2f} ms, speedup {t_plain / t_surr:.2f}x, "
+          f"spikes plain {ca.sum()} surrogate {cb.sum()}")
+    assert rmse <= 1.0
+    assert np.all(np.abs(ca.astype(np.int64) - cb) <= 1)
+    for i in np.nonzero((ca > 0) & (cb > 0))[0][:200]:
+        k = min(ca[i], cb[i], ta.shape[1])
+        assert np.max(np.abs(np.sort(ta[i, :k]) - np.sort(tb[i, :k]))) <= 0.5
+    assert t_surr < t_plain

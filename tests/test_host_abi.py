@@ -33,7 +33,9 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     exe = tmp_path / "sz"
     checks = {"infoli_pulse": infoli.Pulse, "infoli_network_spec": infoli.NetworkSpec,
-              "infoli_options": infoli.Options, "infoli_info": infoli.Info}
+              "infoli_options": infoli.Options, "infoli_info": infoli.Info,
+              "infoli_train_cfg": infoli.TrainCfg, "infoli_train_report": infoli.TrainReport,
+              "infoli_drift_cfg": infoli.DriftCfg, "infoli_drift_report": infoli.DriftReport}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in checks.items():
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
@@ -151,3 +153,22 @@ def test_bad_options_rejected():
         st = infoli.lib().infoli_init(ctypes.byref(h.spec), ctypes.byref(opt), ctypes.byref(ctx))
         assert st in (1, 7), kw
         assert ctx.value is None
+
+
+def test_mlp_entry_points_validate_arguments():
+    L = infoli.lib()
+    p = np.zeros(infoli.MLP_PARAMS, np.float32)
+    x = np.zeros((10, 16), np.float32)
+    y = np.zeros((10, 16), np.float32)
+    PF = ctypes.POINTER(ctypes.c_float)
+    assert L.infoli_mlp_forward(p.ctypes.data_as(PF), x.ctypes.data_as(PF), 10, y.ctypes.data_as(PF)) == 1
+    p[3] = np.nan
+    assert L.infoli_mlp_forward(p.ctypes.data_as(PF), x.ctypes.data_as(PF), 16, y.ctypes.data_as(PF)) == 1
+    assert L.infoli_mlp_adam_step(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8) == 1
+
+
+def test_default_train_and_drift_cfg():
+    c = infoli.default_train_cfg()
+    assert c.batch % 64 == 0 and c.n_transitions >= 1_000_000 and c.lr > 0
+    d = infoli.default_drift_cfg()
+    assert d.theta_mv == 0.5 and d.sample_every == 64 and d.hold_steps == 50 and d.vs_spiking == -40.0
