@@ -13,6 +13,11 @@ Workloads (--workload):
            20-25 ms), stepped together: the default, 20,000 steps
   uni96    96 cells all-to-all (g = 0.04), 2,000 steps
   uni16k   16,384 cells all-to-all (g = 0.04*96/N), 4,000 steps
+  surr65k  65,536 cells, symmetric ER graph of mean degree 1,000 (CSR,
+           g = 3.84e-3), bias, pulse, jitter: the plain method for 10,000
+           steps against the trained MLP surrogate for 2,500 macro steps of
+           4 dt (drift check 1/64 cells, theta 0.5 mV), with the two
+           ablations (held gap without MLP; MLP without fallback)
   batch256 256 independent networks, N_k ~ U{64..2048}, density ~ U{5, 25,
            100 %} (100 % all-to-all, else ER CSR), g_k ~ U[0.01, 0.08],
            pulse amplitude ~ U[2, 10] uA/cm^2, 10,000 steps, one launch per
@@ -40,6 +45,7 @@ WORKLOADS = {
     "uni96": dict(steps=2000, warmup=200),
     "uni16k": dict(steps=4000, warmup=100),
     "batch256": dict(steps=10000, warmup=200),
+    "surr65k": dict(steps=10000, warmup=100),
 }
 
 
@@ -55,6 +61,11 @@ def build_workload(name):
         nets = I.config3()
         desc = ("256 networks, N_k ~ U{64..2048}, density ~ U{5,25,100 %} (100 % all-to-all, else ER CSR), "
                 "g_k ~ U[0.01,0.08] mS/cm^2, pulse A_k ~ U[2,10] uA/cm^2 steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms")
+    elif name == "surr65k":
+        nets = [I.config4()]
+        desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR), g=3.84e-3 mS/cm^2, "
+                "bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms; "
+                "MLP 16-128-128-16 BF16 on MFMA, 4 dt per macro step")
     elif name == "uni16k":
         nets = [I.config2()]
         desc = "16,384 cells all-to-all, g=0.04*96/N mS/cm^2, +-1 mV jitter, no input, FP32, dt=0.05 ms"
@@ -142,6 +153,100 @@ def cpu_baseline(nets, budget_s=15.0):
             "sample": f"{steps} steps of the same {len(nets)} network(s) ({cells} cells) from the initial state, fp32 oracle, OpenMP over cells"}
 
 
+def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
+    """Plain run vs trained surrogate on the same network and initial state."""
+    net = nets[0]
+    x0 = infoli.initial_state(net)
+    V = [I.IDX_VD, I.IDX_VS, I.IDX_VA]
+    macro = steps // 4
+    samples = 25
+    every = macro // samples
+    # plain method
+    plain = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
+    info = plain.info()
+    ref, t_plain = [], 0.0
+    for _ in range(samples):
+        plain.step(4 * every)
+        plain.sync()
+        t_plain += plain.last_step_ms()
+        ref.append(plain.read_state(0)[V])
+    ca, ta = plain.read_spikes(0)
+    plain.close()
+    # training
+    sim = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
+    t0 = time.perf_counter()
+    rep, hist = sim.surrogate_train(I.mlp_init_params(5000))
+    train_wall = time.perf_counter() - t0
+    params, norm = sim.surrogate_get()
+    sim.close()
+
+    def surrogate_run(**drift):
+        s = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
+        s.surrogate_set(params, norm)
+        sq, n, ms, checked, flagged, plain_cells = 0.0, 0, 0.0, 0, 0, 0
+        for k in range(samples):
+            r = s.step_surrogate(every, **drift)
+            ms += r["ms"]
+            checked += r["checked"]
+            flagged += r["flagged"]
+            plain_cells += r["plain_cell_macro_steps"]
+            d = (s.read_state(0)[V] - ref[k]).astype(np.float64)
+            sq += float((d * d).sum())
+            n += d.size
+        cb, tb = s.read_spikes(0)
+        s.close()
+        worst = 0.0
+        for i in np.nonzero((ca > 0) & (cb > 0))[0]:
+            m = min(ca[i], cb[i], ta.shape[1])
+            worst = max(worst, float(np.max(np.abs(np.sort(ta[i, :m]) - np.sort(tb[i, :m])))))
+        return {"ms": ms, "rmse_mv": float(np.sqrt(sq / n)), "spikes": int(cb.sum()),
+                "spike_count_max_diff": int(np.max(np.abs(ca.astype(np.int64) - cb))),
+                "spike_time_err_ms": worst, "checked": checked, "flagged": flagged,
+                "plain_cell_macro_steps": plain_cells}
+
+    surr = surrogate_run()
+    hold = surrogate_run(mode="plain_hold")
+    nofb = surrogate_run(sample_every=0, vs_spiking=1e30)
+    cells = net.n
+    total_steps = 4 * every * samples
+    out = {
+        "metric": "surrogate vs plain speedup at voltage RMSE <= 1 mV (cell-steps/s of the surrogate path)",
+        "value": cells * total_steps / (surr["ms"] * 1e-3),
+        "unit": "cell-steps/s",
+        "n_gpus": 1, "steps": total_steps, "warmup": 0,
+        "ms_per_step": surr["ms"] / total_steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"surr65k: {desc}", "cells": cells, "gap_pairs_per_step": net.pairs_per_step(),
+                   "tiles": info["n_tiles"], "lanes_per_row": info["lanes_per_row"]},
+        "plain_cell_steps_per_s": cells * total_steps / (t_plain * 1e-3),
+        "plain_ms_per_step": t_plain / total_steps,
+        "speedup": t_plain / surr["ms"],
+        "rmse_mv": surr["rmse_mv"], "spike_time_err_ms": surr["spike_time_err_ms"],
+        "spikes_plain": int(ca.sum()), "spikes_surrogate": surr["spikes"],
+        "drift": {k: surr[k] for k in ("checked", "flagged", "plain_cell_macro_steps")},
+        "ablation_held_gap_no_mlp": {"speedup": t_plain / hold["ms"], "rmse_mv": hold["rmse_mv"]},
+        "ablation_mlp_no_fallback": {"speedup": t_plain / nofb["ms"], "rmse_mv": nofb["rmse_mv"],
+                                     "spike_time_err_ms": nofb["spike_time_err_ms"]},
+        "training": {**rep, "wall_s": train_wall},
+        "roofline": roofline(nets, t_plain * 1e-3 / total_steps),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def copy_probe(mb, torch):
+    """A plain device copy of known size (counter calibration for rocprofv3)."""
+    n = int(mb * 1024 * 1024 // 4)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +257,8 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mb", type=float, default=0.0,
+                    help="only run a device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -164,7 +271,13 @@ def main():
     from paper_1612_01501_amd import infoli
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe_mb > 0:
+        copy_probe(args.copy_probe_mb, torch)
+        return
     nets, desc = build_workload(args.workload)
+    if args.workload == "surr65k":
+        run_surrogate(nets, desc, steps, warmup, args, torch, infoli)
+        return
     x0s = [infoli.initial_state(n) for n in nets]
     stream = torch.cuda.current_stream().cuda_stream
     sim = infoli.Simulator(nets, init_states=x0s, stream=stream, step_mode=args.mode,

@@ -111,6 +111,7 @@ struct infoli_ctx {
     int64_t* d_rowptr = nullptr;
     int32_t* d_col = nullptr;
     uint16_t* d_col16 = nullptr;
+    uint32_t* d_bits = nullptr;
     float* d_w = nullptr;
     float* d_stream = nullptr;
     int32_t* d_spk_count = nullptr;

@@ -164,6 +164,11 @@ void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, u
 
 namespace {
 
+size_t bitmap_lds_floats(int n) {
+    const int groups = (n + kBitGroup - 1) / kBitGroup;
+    return (size_t)std::min(groups, kBitChunkGroups) * 4 * kBitStride;
+}
+
 void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int rows, double deg) {
     for (int r = 0; r < n; r += rows) {
         const int r1 = std::min(n, r + rows);
@@ -181,7 +186,8 @@ void finalize_tiles(infoli_ctx* c) {
         append_tiles(planned, k, d.n, c->rows_of[k], c->deg_of[k]);
         if (d.conn == CONN_UNIFORM)
             floats = std::max(floats, (size_t)std::min(d.n, kChunk) + 8 * (size_t)(c->block / 64));
-        if (d.conn == CONN_CSR && d.vd_lds) floats = std::max(floats, (size_t)d.n);
+        if (d.conn == CONN_CSR && d.vd_lds && !d.bitmap) floats = std::max(floats, (size_t)d.n);
+        if (d.conn == CONN_CSR && d.bitmap) floats = std::max(floats, bitmap_lds_floats(d.n));
     }
     c->lds_bytes = ((floats + 3) / 4) * sizeof(float4);
     std::stable_sort(planned.begin(), planned.end(),
@@ -194,6 +200,39 @@ void finalize_tiles(infoli_ctx* c) {
     HIPX(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDesc) * c->n_inst, hipMemcpyHostToDevice));
 }
 
+// Coupling bitmaps of CSR networks with one weight g (the pattern as one bit
+// per pair), for networks of at most 16,384 cells while the bitmaps take at
+// most 1 GiB together; the tuner decides whether the step uses them.
+void build_bitmaps(infoli_ctx* c, const infoli_network_spec* specs) {
+    int64_t words = 0;
+    for (int k = 0; k < c->n_inst; ++k) {
+        InstDesc& d = c->inst[k];
+        d.bits_off = -1;
+        if (d.conn != CONN_CSR || d.has_w || d.n > 16384 || specs[k].nnz == 0) continue;
+        const int64_t groups = (d.n + kBitGroup - 1) / kBitGroup;
+        const int64_t w = groups * bitmap_rows_pad(d.n) * 4;
+        if ((words + w) * 4 > ((int64_t)1 << 30)) continue;
+        d.bits_off = words;
+        words += w;
+    }
+    if (words == 0) return;
+    std::vector<uint32_t> h((size_t)words, 0u);
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstDesc& d = c->inst[k];
+        if (d.bits_off < 0) continue;
+        const int npad = bitmap_rows_pad(d.n);
+        const infoli_network_spec& s = specs[k];
+        for (int i = 0; i < d.n; ++i)
+            for (int64_t e = s.row_ptr[i]; e < s.row_ptr[i + 1]; ++e) {
+                const int j = s.col[e];
+                const int64_t g = j / kBitGroup, p = (j % kBitGroup) / 32, t = j % 32;
+                h[(size_t)(d.bits_off + (g * npad + i) * 4 + p)] |= 1u << t;
+            }
+    }
+    c->d_bits = c->alloc<uint32_t>((size_t)words);
+    HIPX(hipMemcpy(c->d_bits, h.data(), sizeof(uint32_t) * words, hipMemcpyHostToDevice));
+}
+
 // ---------------------------------------------------------------- autotuner
 // For every class of CSR network (log-spaced size and degree buckets) the
 // candidate tile shapes (lanes per row, rows per tile, LDS staging of Vd) are
@@ -201,14 +240,14 @@ void finalize_tiles(infoli_ctx* c) {
 // the next-state buffer) and the fastest is kept, in memory and in an
 // on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v1.txt).
 struct TuneChoice {
-    int L, R, lds;
+    int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS, bitmap path
 };
 
 std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v1.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v2.txt";
     return "";
 }
 
@@ -231,8 +270,9 @@ std::map<std::string, TuneChoice> read_tune_cache(const std::string& path) {
         if (!bar) continue;
         *bar = 0;
         TuneChoice t;
-        if (std::sscanf(bar + 1, "%d %d %d", &t.L, &t.R, &t.lds) == 3 && t.L >= 4 && t.L <= 1024 &&
-            (t.L & (t.L - 1)) == 0 && t.R >= 1 && t.R <= kMaxTileRows && (t.lds == 0 || t.lds == 1))
+        if (std::sscanf(bar + 1, "%d %d %d %d", &t.L, &t.R, &t.lds, &t.bm) == 4 && t.L >= 4 && t.L <= 1024 &&
+            (t.L & (t.L - 1)) == 0 && t.R >= 1 && t.R <= kMaxTileRows && (t.lds == 0 || t.lds == 1) &&
+            (t.bm == 0 || t.bm == 1))
             m[line] = t;
     }
     std::fclose(f);
@@ -245,24 +285,31 @@ void append_tune_cache(const std::string& path, const std::string& key, const Tu
     if (slash != std::string::npos) mkdir(path.substr(0, slash).c_str(), 0755);
     std::FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s|%d %d %d\n", key.c_str(), t.L, t.R, t.lds);
+    std::fprintf(f, "%s|%d %d %d %d\n", key.c_str(), t.L, t.R, t.lds, t.bm);
     std::fclose(f);
 }
 
-float time_shape(infoli_ctx* c, int k, const TuneChoice& t, Tile* d_tmp) {
-    InstDesc d = c->inst[k];
-    d.lanes_per_row = t.L;
-    d.vd_lds = t.lds;
-    HIPX(hipMemcpy(c->d_inst + k, &d, sizeof(d), hipMemcpyHostToDevice));
+// Average duration of a dry launch of the tiles of networks `ks` (one size
+// and degree class) shaped by t.
+float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t, Tile* d_tmp) {
     std::vector<std::pair<double, Tile>> planned;
-    append_tiles(planned, k, d.n, t.R, 0.0);
+    size_t lds = 16;
+    for (int k : ks) {
+        InstDesc d = c->inst[k];
+        d.lanes_per_row = t.L;
+        d.vd_lds = t.lds;
+        d.bitmap = t.bm;
+        HIPX(hipMemcpy(c->d_inst + k, &d, sizeof(d), hipMemcpyHostToDevice));
+        append_tiles(planned, k, d.n, t.R, 0.0);
+        if (t.bm) lds = std::max(lds, ((bitmap_lds_floats(d.n) + 3) / 4) * sizeof(float4));
+        else if (t.lds) lds = std::max(lds, ((size_t)(d.n + 3) / 4) * sizeof(float4));
+    }
     std::vector<Tile> tl;
     for (const auto& pt : planned) tl.push_back(pt.second);
     HIPX(hipMemcpy(d_tmp, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice));
     StepArgs a = make_args(c, false);
     a.tiles = d_tmp;
     a.dry = 1;
-    const size_t lds = t.lds ? ((size_t)(d.n + 3) / 4) * sizeof(float4) : 16;
     for (int w = 0; w < 2; ++w) launch_tiles(c, c->stream, a, (unsigned)tl.size(), lds, c->cur, c->step, 0);
     HIPX(hipEventRecord(c->ev0, c->stream));
     const int reps = 8;
@@ -280,23 +327,31 @@ void autotune(infoli_ctx* c) {
     const std::string path = tune_cache_path();
     std::map<std::string, TuneChoice> cache;
     if (c->opt.autotune == 1) cache = read_tune_cache(path);
-    std::map<std::string, TuneChoice> decided;
-    Tile* d_tmp = nullptr;
+    // classes of CSR networks
+    std::map<std::string, std::vector<int>> classes;
     for (int k = 0; k < c->n_inst; ++k) {
-        InstDesc& d = c->inst[k];
-        const double deg = c->deg_of[k];
-        if (d.conn != CONN_CSR || deg <= 0.0) continue;
-        const std::string key = tune_key(c, d, deg);
-        TuneChoice best{0, 0, 0};
-        auto hit = decided.find(key);
-        if (hit != decided.end()) {
+        const InstDesc& d = c->inst[k];
+        if (d.conn != CONN_CSR || c->deg_of[k] <= 0.0) continue;
+        classes[tune_key(c, d, c->deg_of[k])].push_back(k);
+    }
+    Tile* d_tmp = nullptr;
+    for (const auto& kv : classes) {
+        const std::string& key = kv.first;
+        const std::vector<int>& ks = kv.second;
+        TuneChoice best{0, 0, 0, 0};
+        auto hit = cache.find(key);
+        if (hit != cache.end() && hit->second.L <= c->block) {
             best = hit->second;
-        } else if ((hit = cache.find(key)) != cache.end() && hit->second.L <= c->block) {
-            best = hit->second;
-            decided[key] = best;
-            ++c->tune_cached;
+            c->tune_cached += (int)ks.size();
         } else {
             if (!d_tmp) d_tmp = c->alloc<Tile>(c->total_cells + 1);
+            // representative size and degree of the class
+            int n = 0;
+            double deg = 0.0;
+            for (int k : ks) {
+                n = std::max(n, c->inst[k].n);
+                deg = std::max(deg, c->deg_of[k]);
+            }
             float best_ms = 1e30f;
             for (int L = 4; L <= c->block; L *= 2) {
                 if (L > 4 && L > 2.0 * deg) break;
@@ -304,9 +359,9 @@ void autotune(infoli_ctx* c) {
                 for (int m = 1; m <= 4; m *= 2) {
                     const int R = std::max(1, c->block / L) * m;
                     if (R > kMaxTileRows) continue;
-                    for (int lds = 0; lds <= (d.n <= kChunk ? 1 : 0); ++lds) {
-                        const TuneChoice t{L, R, lds};
-                        const float ms = time_shape(c, k, t, d_tmp);
+                    for (int lds = 0; lds <= (n <= kChunk ? 1 : 0); ++lds) {
+                        const TuneChoice t{L, R, lds, 0};
+                        const float ms = time_shape(c, ks, t, d_tmp);
                         if (ms < best_ms) {
                             best_ms = ms;
                             best = t;
@@ -314,13 +369,30 @@ void autotune(infoli_ctx* c) {
                     }
                 }
             }
-            decided[key] = best;
+            // the bitmap path, when every network of the class has one
+            bool all_bits = c->d_bits != nullptr;
+            for (int k : ks) all_bits = all_bits && c->inst[k].bits_off >= 0;
+            if (all_bits) {
+                const TuneChoice t{best.L, kBitRows, 0, 1};
+                const float ms = time_shape(c, ks, t, d_tmp);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
             append_tune_cache(path, key, best);
-            ++c->tuned;
+            c->tuned += (int)ks.size();
         }
-        d.lanes_per_row = best.L;
-        c->rows_of[k] = best.R;
-        d.vd_lds = best.lds;
+        if (best.bm) {
+            for (int k : ks)
+                if (c->inst[k].bits_off < 0) best = TuneChoice{best.L, std::max(1, c->block / best.L), 0, 0};
+        }
+        for (int k : ks) {
+            c->inst[k].lanes_per_row = best.L;
+            c->inst[k].vd_lds = best.lds;
+            c->inst[k].bitmap = best.bm;
+            c->rows_of[k] = best.R;
+        }
     }
 }
 
@@ -341,6 +413,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         fail(INFOLI_E_INVALID_ARG, "lanes_per_row must be 0 or a power of two in [4, 256]");
     if (c->opt.autotune < 0 || c->opt.autotune > 2)
         fail(INFOLI_E_INVALID_ARG, "autotune must be 0, 1 or 2");
+    if (c->opt.csr_path < 0 || c->opt.csr_path > 2)
+        fail(INFOLI_E_INVALID_ARG, "csr_path must be 0, 1 or 2");
     if (c->opt.tile_rows < 0 || c->opt.tile_rows > kMaxTileRows)
         fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
     for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
@@ -538,7 +612,14 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     HIPX(hipMemset(c->d_flags, 0, sizeof(int32_t) * 4));
     HIPX(hipMemset(c->igap, 0, sizeof(float) * S));
     HIPX(hipDeviceSynchronize());
-    if (c->opt.autotune) autotune(c);
+    build_bitmaps(c, specs);
+    if (c->opt.autotune && c->opt.csr_path == 0) autotune(c);
+    if (c->opt.csr_path == 2)
+        for (int k = 0; k < ninst; ++k)
+            if (c->inst[k].bits_off >= 0) {
+                c->inst[k].bitmap = 1;
+                c->rows_of[k] = kBitRows;
+            }
     finalize_tiles(c);
     HIPX(hipDeviceSynchronize());
 }
@@ -555,6 +636,7 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     a.row_ptr = c->d_rowptr;
     a.col = c->d_col;
     a.col16 = c->d_col16;
+    a.bits = c->d_bits;
     a.w = c->d_w;
     a.i_stream = c->d_stream;
     a.spike_count = c->d_spk_count;

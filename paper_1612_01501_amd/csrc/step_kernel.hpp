@@ -13,6 +13,11 @@
 //                taken in closed form, 0.2*(n*Vd_i - sum_j Vd_j), in fp64.
 //   DENSE        lanes = sending cells j of one row (coalesced weight rows),
 //                one row per wave at a time, butterfly reduction.
+//   BITMAP       (CSR networks with one weight g, when faster) the coupling
+//                pattern as one bit per pair: 16 receiving cells per wave,
+//                four lane groups per cell take interleaved 32-sender blocks
+//                of a 128-sender group (conflict-free LDS rows), waves split
+//                the groups; every pair is evaluated and masked.
 //   CSR          groups of L lanes per row stride over the row's edges and
 //                gather Vd of the neighbours, from a copy of the network's
 //                Vd staged in LDS when the tile's edges outnumber the cells,
@@ -56,7 +61,9 @@ struct InstDesc {
     int32_t lanes_per_row; // CSR: lanes per row (4..64)
     int32_t vd_lds;        // CSR: stage the network's Vd in LDS (n <= kChunk)
     int32_t col16;         // CSR: columns stored as uint16
-    int32_t pad0[3];
+    int32_t bitmap;        // CSR with uniform g: gap from the coupling bitmap
+    int32_t pad0[2];
+    int64_t bits_off;      // bitmap: offset of the network's first word
     CellParams p;
 };
 
@@ -82,6 +89,7 @@ struct StepArgs {
     const int64_t* row_ptr;    // CSR row pointers of all networks
     const int32_t* col;        // CSR columns (local cell index)
     const uint16_t* col16;     // CSR columns, 16-bit form
+    const uint32_t* bits;      // coupling bitmaps
     const float* w;            // DENSE matrices and CSR weights
     const float* i_stream;     // dense input streams
     int32_t* spike_count;      // [cells]
@@ -280,6 +288,78 @@ __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, co
     }
 }
 
+// Bitmap words of a network: group gr (128 senders), row r (padded to a
+// multiple of 16 rows), block p (senders gr*128 + 32p .. +31): word
+// (gr * n_pad16 + r) * 4 + p, bit t = sender gr*128 + 32p + t. LDS holds a
+// chunk of prescaled Vd with each 32-sender block at a stride of 36 floats.
+constexpr int kBitGroup = 128;
+constexpr int kBitRows = 16;
+constexpr int kBitStride = 36;
+constexpr int kBitChunkGroups = kChunk / kBitGroup;            // 64 groups per LDS chunk
+
+__host__ __device__ __forceinline__ int bitmap_rows_pad(int n) { return (n + kBitRows - 1) / kBitRows * kBitRows; }
+
+template <int BLOCK>
+__device__ __forceinline__ void gap_bitmap(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                           const float* __restrict__ vd, float* s_v, float* s_part,
+                                           float* s_ig) {
+    constexpr int W = BLOCK / 64;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int p = lane >> 4;                   // 32-sender block within a group
+    const int r = lane & 15;                   // row within the tile
+    const int row = t.row0 + r;
+    const bool valid = row < t.row1;
+    const int n = d.n;
+    const int npad = bitmap_rows_pad(n);
+    const int groups = (n + kBitGroup - 1) / kBitGroup;
+    const uint32_t* bits = a.bits + d.bits_off;
+    const float vis = valid ? vd[row] * kPreScale : 0.0f;
+    float acc0 = 0.0f, acc1 = 0.0f;
+    for (int g0 = 0; g0 < groups; g0 += kBitChunkGroups) {
+        const int gc = min(kBitChunkGroups, groups - g0);
+        __syncthreads();
+        // stage the chunk's senders, prescaled, 32-sender blocks at stride 36
+        for (int k = threadIdx.x; k < gc * kBitGroup; k += BLOCK) {
+            const int j = g0 * kBitGroup + k;
+            s_v[(k >> 5) * kBitStride + (k & 31)] = j < n ? vd[j] * kPreScale : kSentinel;
+        }
+        __syncthreads();
+        const int per = (gc + W - 1) / W;
+        const int gb = wave * per, ge = min(gc, gb + per);
+        for (int gl = gb; gl < ge; ++gl) {
+            const uint32_t wbits = valid ? bits[((int64_t)(g0 + gl) * npad + row) * 4 + p] : 0u;
+            const float4* sv = reinterpret_cast<const float4*>(s_v + (gl * 4 + p) * kBitStride);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float4 v4 = sv[q];
+                const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int tb = 4 * q + e;
+                    const float dv = vis - vv[e];
+                    const float f = fmaf(0.8f, __builtin_amdgcn_exp2f(-(dv * dv)), 0.2f);
+                    // all ones when the bit is set, else zero
+                    const int m = (int)(wbits << (31 - tb)) >> 31;
+                    const float dm = __int_as_float(__float_as_int(dv) & m);
+                    if (e & 1) acc1 = fmaf(dm, f, acc1);
+                    else acc0 = fmaf(dm, f, acc0);
+                }
+            }
+        }
+    }
+    float acc = acc0 + acc1;
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (p == 0) s_part[wave * 16 + r] = acc;
+    __syncthreads();
+    if (threadIdx.x < 16 && t.row0 + (int)threadIdx.x < t.row1) {
+        float tot = 0.0f;
+        for (int w = 0; w < W; ++w) tot += s_part[w * 16 + threadIdx.x];
+        s_ig[threadIdx.x] = d.g * (tot * kInvPreScale);
+    }
+}
+
 __device__ __forceinline__ float evoked_input(const StepArgs& a, const InstDesc& d, int64_t step,
                                               int li, int64_t cell) {
     float iapp = a.bias[cell];
@@ -325,7 +405,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
     switch (d.conn) {
         case CONN_UNIFORM: gap_uniform<BLOCK>(a, d, t, vd, s_ig, s_v4, s_part, s_red); break;
         case CONN_DENSE: gap_dense<BLOCK>(a, d, t, vd, s_ig); break;
-        case CONN_CSR: gap_csr<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig); break;
+        case CONN_CSR:
+            if (d.bitmap) gap_bitmap<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
+            else gap_csr<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
+            break;
         default:
             for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
             break;

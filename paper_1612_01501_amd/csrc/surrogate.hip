@@ -125,11 +125,11 @@ infoli_status infoli_default_train_cfg(infoli_train_cfg* cfg) {
     cfg->beta2 = 0.999f;
     cfg->eps = 1e-8f;
     cfg->bias_sd = 0.7f;
-    cfg->gap_sd = 2.0f;
+    cfg->gap_sd = 1.5f;
     cfg->gap_rho = 0.9f;
     cfg->pulse_p = 0.005f;
     cfg->pulse_lo = 2.0f;
-    cfg->pulse_hi = 10.0f;
+    cfg->pulse_hi = 8.0f;
     cfg->pulse_len = 25;
     cfg->seed = 5001;
     cfg->init_params = nullptr;

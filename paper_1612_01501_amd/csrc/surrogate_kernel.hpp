@@ -261,12 +261,30 @@ static __global__ void k_surrogate_data(DataGenArgs g) {
         const float iapp = bias + (pulse_left > 0 ? pulse_amp : 0.0f);
         if (pulse_left > 0) --pulse_left;
         float x0[NSV];
+        float used_iapp = iapp;
 #pragma unroll
         for (int v = 0; v < NSV; ++v) x0[v] = x[v];
         for (int k = 0; k < kMacro; ++k) {
             cell_step(g.p, x, gap, iapp, g.dt, y);
 #pragma unroll
             for (int v = 0; v < NSV; ++v) x[v] = y[v];
+        }
+        // a trajectory driven out of the model's range (forward Euler loses
+        // stability for very large currents) restarts from the rest state
+        float chk = 0.0f;
+#pragma unroll
+        for (int v = 0; v < NSV; ++v) chk += x[v];
+        if (!isfinite(chk) || fabsf(x[SV_VD]) > 150.0f || fabsf(x[SV_VS]) > 150.0f || fabsf(x[SV_VA]) > 150.0f) {
+#pragma unroll
+            for (int v = 0; v < NSV; ++v) x[v] = x0[v] = g.rest[v];
+            gap = 0.0f;
+            pulse_left = 0;
+            used_iapp = bias;
+            for (int k = 0; k < kMacro; ++k) {
+                cell_step(g.p, x, gap, bias, g.dt, y);
+#pragma unroll
+                for (int v = 0; v < NSV; ++v) x[v] = y[v];
+            }
         }
         if (m > g.burn_in) {
             const int64_t r = (int64_t)(m - g.burn_in - 1) * g.n_traj + t;
@@ -278,7 +296,7 @@ static __global__ void k_surrogate_data(DataGenArgs g) {
                 dr[v] = x[v] - x0[v];
             }
             xr[14] = gap;
-            xr[15] = iapp;
+            xr[15] = used_iapp;
             dr[14] = 0.0f;
             dr[15] = 0.0f;
         }

@@ -70,7 +70,8 @@ class Options(ctypes.Structure):
     _fields_ = [("hip_stream", ctypes.c_void_p), ("step_mode", ctypes.c_int32),
                 ("graph_chunk", ctypes.c_int32), ("max_spikes_per_cell", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("csr_path", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -501,3 +501,36 @@ def test_full_batch256_sampled_step(infoli, o32):
     for k in sample:
         ref = o32.run(nets[k], 1, x0=xk[k], step0=200)["x"]
         assert per_var_error(xk1[k][None], ref[None]).max() <= 1e-5, nets[k].label
+
+
+# ------------------------------------------------------------------ bitmap path
+@pytest.mark.parametrize("p", [0.05, 0.3])
+def test_bitmap_path_against_oracle(infoli, o32, o64, p):
+    """CSR networks with one weight g run through the coupling bitmap: ragged
+    sizes (not multiples of the 16-row tile or the 128-sender group)."""
+    net = I.config1(p, seed=15, n=1000)
+    net.pulses = [I.Pulse(100, 600, 6.0)]
+    x0 = infoli.initial_state(net)
+    got, c, t = gpu_trace(infoli, net, 1000, 50, x0, csr_path=2, step_mode="graph", graph_chunk=50)
+    ref = o32.run(net, 1000, x0=x0, trace_every=50, trace_cells=net.n)
+    r64 = o64.run(net, 1000, x0=x0.astype(np.float64), trace_every=50, trace_cells=net.n)
+    tol = np.maximum(TOL_STATE, per_var_error(ref["trace"], r64["trace"]))
+    e = per_var_error(got, ref["trace"])
+    assert np.all(e <= tol), (e, tol)
+    compare_spikes(c, t, ref["counts"], ref["times"], 64)
+
+
+@pytest.mark.parametrize("n", [1, 17, 129, 4100])
+def test_bitmap_gap_current(infoli, o64, n):
+    rs = I.rng(n + 3)
+    rp, col = I.erdos_renyi_csr(n, 0.4, n + 4)
+    net = I.Network(n=n, conn="csr", g=0.03, row_ptr=rp, col=col, jitter=rs.uniform(-15, 15, (3, n)))
+    x0 = infoli.initial_state(net)
+    if len(col) == 0:
+        return
+    sim = infoli.Simulator(net, init_states=[x0], csr_path=2)
+    got = sim.read_gap_current(0).astype(np.float64)
+    sim.close()
+    ref = o64.gap(net, x0[0].astype(np.float64))
+    tol = gap_bound(net, x0[0])
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)

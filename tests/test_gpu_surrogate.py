@@ -69,7 +69,7 @@ def test_adam_step_matches_oracle(infoli):
     w1, m1, v1 = infoli.mlp_adam_step(w, m, v, g, 7, lr=2e-3)
     rw, rm, rv = M.adam_step(w.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
                              g.astype(np.float64), 7, lr=2e-3)
-    np.testing.assert_allclose(m1, rm, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(m1, rm, rtol=1e-5, atol=2e-8)
     np.testing.assert_allclose(v1, rv, rtol=1e-5, atol=1e-12)
     np.testing.assert_allclose(w1, rw, rtol=1e-5, atol=2e-7)
 
