@@ -252,7 +252,11 @@ typedef struct infoli_train_cfg {
     int32_t burn_in;            /* macro steps per trajectory before recording            */
     int32_t batch;              /* samples per optimiser step, multiple of 64             */
     int32_t steps;              /* optimiser steps                                        */
-    float lr, beta1, beta2, eps;/* Adam                                                   */
+    float lr, beta1, beta2, eps;/* Adam; the rate decays from lr to lr_min (cosine)        */
+    float lr_min;
+    float vs_max;               /* a trajectory whose Vs exceeds this (mV) restarts from
+                                   rest: the MLP learns the subthreshold regime only (the
+                                   plain method advances spiking cells)                    */
     float bias_sd;              /* per-trajectory constant input ~ N(0, bias_sd^2)        */
     float gap_sd, gap_rho;      /* AR(1) gap current: stationary sd, lag-1 correlation    */
     float pulse_p;              /* pulse start probability per macro step                 */

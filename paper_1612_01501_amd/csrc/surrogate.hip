@@ -100,7 +100,7 @@ void launch_macro(infoli_ctx* c, hipStream_t st, const infoli_drift_cfg& dc, int
         return;
     }
     const SurrArgs s = surr_args(c, dc, step0 / kMacro);
-    const unsigned blocks = (unsigned)std::min<int64_t>((cells + 63) / 64, 1024);
+    const unsigned blocks = (unsigned)std::min<int64_t>((cells + 63) / 64, 256);
     hipLaunchKernelGGL(k_surrogate_step, dim3(blocks), dim3(256), 0, st, a, s, c->state[from],
                        c->state[from ^ 1], step0, cells);
 }
@@ -119,8 +119,10 @@ infoli_status infoli_default_train_cfg(infoli_train_cfg* cfg) {
     cfg->n_trajectories = 16384;
     cfg->burn_in = 50;
     cfg->batch = 4096;
-    cfg->steps = 3000;
+    cfg->steps = 20000;
     cfg->lr = 1e-3f;
+    cfg->lr_min = 1e-5f;
+    cfg->vs_max = -40.0f;
     cfg->beta1 = 0.9f;
     cfg->beta2 = 0.999f;
     cfg->eps = 1e-8f;
@@ -161,7 +163,8 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
         if (cfg->batch < 16 || cfg->batch % 64 != 0 || cfg->batch > (1 << 20))
             fail(INFOLI_E_INVALID_ARG, "batch must be a positive multiple of 64 up to 2^20");
         if (cfg->steps < 0 || cfg->n_trajectories < 1 || cfg->n_transitions < cfg->batch ||
-            cfg->burn_in < 0 || cfg->pulse_len < 0 || !(cfg->lr > 0.0f) ||
+            cfg->burn_in < 0 || cfg->pulse_len < 0 || !(cfg->lr > 0.0f) || !(cfg->lr_min >= 0.0f) ||
+            !(cfg->lr_min <= cfg->lr) || !std::isfinite(cfg->vs_max) ||
             !(cfg->gap_rho >= 0.0f && cfg->gap_rho < 1.0f))
             fail(INFOLI_E_INVALID_ARG, "bad training configuration");
         check_params(cfg->init_params, kNumParams);
@@ -194,6 +197,7 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
         g.pulse_lo = cfg->pulse_lo;
         g.pulse_hi = cfg->pulse_hi;
         g.pulse_len = cfg->pulse_len;
+        g.vs_max = cfg->vs_max;
         g.burn_in = cfg->burn_in;
         g.per_traj = (int32_t)per_traj;
         g.n_traj = cfg->n_trajectories;
@@ -247,8 +251,11 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
             hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles), dim3(64), 0, st, tb, B, s.grad, dloss + (t - 1));
             c1 *= cfg->beta1;
             c2 *= cfg->beta2;
+            // cosine decay of the learning rate from lr to lr_min
+            const double frac = cfg->steps > 1 ? (double)(t - 1) / (double)(cfg->steps - 1) : 0.0;
+            const float lr_t = (float)(cfg->lr_min + 0.5 * (cfg->lr - cfg->lr_min) * (1.0 + std::cos(M_PI * frac)));
             hipLaunchKernelGGL(k_adam, dim3((kNumParams + 255) / 256), dim3(256), 0, st, s.params, s.m, s.v, s.grad,
-                               s.wb, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, (float)(1.0 - c1), (float)(1.0 - c2));
+                               s.wb, lr_t, cfg->beta1, cfg->beta2, cfg->eps, (float)(1.0 - c1), (float)(1.0 - c2));
         }
         HIPX(hipGetLastError());
         HIPX(hipEventRecord(e2, st));

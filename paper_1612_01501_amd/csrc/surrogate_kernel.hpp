@@ -207,7 +207,9 @@ static __global__ __launch_bounds__(256) void k_hold4(StepArgs a, const float* _
 // ---------------------------------------------------------------- training data
 // Independent cells driven by random currents, advanced by the plain method:
 // each macro step records (state, I_gap, I_app) and the state increment over
-// four steps with both currents held. Per trajectory: a constant bias
+// four steps with both currents held. A trajectory whose soma voltage exceeds
+// vs_max restarts from the (jittered) rest state, so every recorded
+// transition starts in the subthreshold regime the surrogate serves. Per trajectory: a constant bias
 // N(0, bias_sd); a gap current following an AR(1) process with stationary
 // standard deviation gap_sd and lag-one correlation gap_rho per macro step;
 // pulses of amplitude U[pulse_lo, pulse_hi] lasting pulse_len macro steps,
@@ -219,6 +221,7 @@ struct DataGenArgs {
     float rest[NSV];
     float dt;
     float bias_sd, gap_sd, gap_rho, pulse_p, pulse_lo, pulse_hi;
+    float vs_max;             // restart when the soma voltage exceeds this
     int32_t pulse_len;
     int32_t burn_in;          // macro steps not recorded
     int32_t per_traj;         // recorded macro steps per trajectory
@@ -253,6 +256,16 @@ static __global__ void k_surrogate_data(DataGenArgs g) {
     float pulse_amp = 0.0f;
     const float innov = g.gap_sd * sqrtf(1.0f - g.gap_rho * g.gap_rho);
     for (int m = 1; m <= g.burn_in + g.per_traj; ++m) {
+        if (x[SV_VS] > g.vs_max) {
+            // spiking regime: the surrogate leaves it to the plain method
+#pragma unroll
+            for (int v = 0; v < NSV; ++v) x[v] = g.rest[v];
+            x[SV_VD] += 2.0f * u01(g.seed, t, m, 13) - 1.0f;
+            x[SV_VS] += 2.0f * u01(g.seed, t, m, 14) - 1.0f;
+            x[SV_VA] += 2.0f * u01(g.seed, t, m, 15) - 1.0f;
+            gap = 0.0f;
+            pulse_left = 0;
+        }
         gap = g.gap_rho * gap + innov * normal01(g.seed, t, m, 40);
         if (pulse_left == 0 && u01(g.seed, t, m, 50) < g.pulse_p) {
             pulse_left = g.pulse_len;

@@ -87,7 +87,8 @@ class TrainCfg(ctypes.Structure):
     _fields_ = [("n_transitions", ctypes.c_int64), ("n_trajectories", ctypes.c_int32),
                 ("burn_in", ctypes.c_int32), ("batch", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float), ("bias_sd", ctypes.c_float), ("gap_sd", ctypes.c_float),
+                ("eps", ctypes.c_float), ("lr_min", ctypes.c_float), ("vs_max", ctypes.c_float),
+                ("bias_sd", ctypes.c_float), ("gap_sd", ctypes.c_float),
                 ("gap_rho", ctypes.c_float), ("pulse_p", ctypes.c_float), ("pulse_lo", ctypes.c_float),
                 ("pulse_hi", ctypes.c_float), ("pulse_len", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("init_params", _PF)]

@@ -8,9 +8,10 @@ oracle is printed alongside.
 
 In runs where cells fire, fp32 rounding alone moves the fast axon gates by
 more than 1e-4 (the fp32 oracle differs from the fp64 one by up to ~3e-4
-there), so the bound for variable v is max(1e-4, e_v(oracle_f32, oracle_f64)):
-the GPU must be at least as close to the fp32 oracle as that oracle is to
-the fp64 result.
+there). An fp32 implementation as accurate as the fp32 oracle (distance D
+from the fp64 result) lies within 2D of the fp32 oracle (triangle
+inequality), so the bound for variable v is max(1e-4, 2 e_v(oracle_f32,
+oracle_f64)).
 """
 import numpy as np
 import pytest
@@ -75,7 +76,7 @@ def _check_run(infoli, o32, o64, net, steps=1000, every=10):
     r64 = o64.run(net, steps, x0=x0.astype(np.float64), trace_every=every, trace_cells=net.n)
     e64 = per_var_error(got, r64["trace"])
     floor = per_var_error(ref["trace"], r64["trace"])
-    tol = np.maximum(TOL_STATE, floor)
+    tol = np.maximum(TOL_STATE, 2 * floor)
     print(f"{net.label or net.conn} n={net.n}: max err vs f32 oracle {e32.max():.2e}, vs f64 {e64.max():.2e}, "
           f"f32-oracle floor {floor.max():.2e}")
     assert np.all(e32 <= tol), (e32, tol)
@@ -399,7 +400,7 @@ def test_persistent_batch_parity(infoli, o32, o64):
     for k, net in enumerate(nets):
         ref = o32.run(net, 1000, x0=x0s[k], trace_every=100, trace_cells=net.n)["trace"]
         r64 = o64.run(net, 1000, x0=x0s[k].astype(np.float64), trace_every=100, trace_cells=net.n)["trace"]
-        tol = np.maximum(TOL_STATE, per_var_error(ref, r64))
+        tol = np.maximum(TOL_STATE, 2 * per_var_error(ref, r64))
         for mode in ("persistent", "graph"):
             e = per_var_error(res[mode][k], ref)
             assert np.all(e <= tol), (net.label, mode, e)
@@ -479,9 +480,9 @@ def test_uneven_batch_against_oracle(infoli, o32, o64):
         for k, net in enumerate(nets):
             ref = o32.run(net, 1000, x0=x0s[k])
             r64 = o64.run(net, 1000, x0=x0s[k].astype(np.float64))
-            tol = np.maximum(TOL_STATE, per_var_error(ref["x"][None], r64["x"][None]))
+            tol = np.maximum(TOL_STATE, 2 * per_var_error(ref["x"][None], r64["x"][None]))
             e = per_var_error(got[k][None], ref["x"][None])
-            assert np.all(e <= np.maximum(TOL_STATE, 2 * tol)), (mode, net.label, e)
+            assert np.all(e <= tol), (mode, net.label, e)
             compare_spikes(spk[k][0], spk[k][1], ref["counts"], ref["times"], 64)
 
 
@@ -514,7 +515,7 @@ def test_bitmap_path_against_oracle(infoli, o32, o64, p):
     got, c, t = gpu_trace(infoli, net, 1000, 50, x0, csr_path=2, step_mode="graph", graph_chunk=50)
     ref = o32.run(net, 1000, x0=x0, trace_every=50, trace_cells=net.n)
     r64 = o64.run(net, 1000, x0=x0.astype(np.float64), trace_every=50, trace_cells=net.n)
-    tol = np.maximum(TOL_STATE, per_var_error(ref["trace"], r64["trace"]))
+    tol = np.maximum(TOL_STATE, 2 * per_var_error(ref["trace"], r64["trace"]))
     e = per_var_error(got, ref["trace"])
     assert np.all(e <= tol), (e, tol)
     compare_spikes(c, t, ref["counts"], ref["times"], 64)

@@ -70,7 +70,7 @@ def test_adam_step_matches_oracle(infoli):
     rw, rm, rv = M.adam_step(w.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
                              g.astype(np.float64), 7, lr=2e-3)
     np.testing.assert_allclose(m1, rm, rtol=1e-5, atol=2e-8)
-    np.testing.assert_allclose(v1, rv, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(v1, rv, rtol=3e-5, atol=1e-12)
     np.testing.assert_allclose(w1, rw, rtol=1e-5, atol=2e-7)
 
 
@@ -100,9 +100,9 @@ def test_plain_hold_matches_oracle(infoli, o32):
 
 
 # ------------------------------------------------------------------ drift check and fallback
-def _trained(infoli, net, x0, steps=1500, n_transitions=400_000):
+def _trained(infoli, net, x0, **cfg):
     sim = infoli.Simulator(net, init_states=[x0], step_mode="graph")
-    rep, hist = sim.surrogate_train(I.mlp_init_params(5000), steps=steps, n_transitions=n_transitions)
+    rep, hist = sim.surrogate_train(I.mlp_init_params(5000), **cfg)
     return sim, rep, hist
 
 
@@ -158,10 +158,10 @@ def test_trained_surrogate_accuracy_and_gain(infoli):
     spikes (if any) within 0.5 ms, and it is faster than the plain method."""
     net = I.config4(seed=1, n=8192)
     x0 = infoli.initial_state(net)
-    sim, rep, hist = _trained(infoli, net, x0, steps=3000, n_transitions=1_000_000)
+    sim, rep, hist = _trained(infoli, net, x0)        # defaults: 10^6 transitions, 20,000 steps
     print(f"training: {rep['n_transitions']} transitions, loss {rep['loss_first']:.3e} -> "
           f"{rep['loss_last']:.3e}, data {rep['data_ms']:.1f} ms, train {rep['train_ms']:.1f} ms")
-    assert rep["loss_last"] < 0.05 * rep["loss_first"]
+    assert rep["loss_last"] < 0.01 * rep["loss_first"]
     params, norm = sim.surrogate_get()
     sim.close()
 
