@@ -249,7 +249,8 @@ enum { INFOLI_MLP_PARAMS = 20752 };
 typedef struct infoli_train_cfg {
     int64_t n_transitions;      /* training-set size (rounded up to whole trajectories)   */
     int32_t n_trajectories;     /* independent cells generating it                        */
-    int32_t burn_in;            /* macro steps per trajectory before recording            */
+    int32_t burn_in;            /* unrecorded macro steps per trajectory: uniform in
+                                   [0, burn_in] (covers the slow variables' excursion)     */
     int32_t batch;              /* samples per optimiser step, multiple of 64             */
     int32_t steps;              /* optimiser steps                                        */
     float lr, beta1, beta2, eps;/* Adam; the rate decays from lr to lr_min (cosine)        */

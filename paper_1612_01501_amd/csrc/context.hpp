@@ -58,6 +58,13 @@ inline bool finite_all(const float* p, int64_t n) {
 
 void rest_state_host(const float* P, float v0, float* x);
 
+struct TileGroup {
+    int block = 256;
+    std::vector<Tile> tiles;
+    Tile* d_tiles = nullptr;
+    size_t lds = 16;                // dynamic LDS bytes of the launch
+};
+
 struct SurrogateState {
     bool ready = false;                 // weights and normalisation present
     float* params = nullptr;            // [kNumParams] fp32 masters
@@ -80,19 +87,23 @@ struct infoli_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
+    hipStream_t side_stream = nullptr;  // second branch of captured steps
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     infoli_options opt{};
     std::string err;
 
     int32_t n_inst = 0;
     std::vector<InstDesc> inst;     // host copies of the descriptors
-    std::vector<Tile> tiles;
     int64_t total_cells = 0;
     int64_t stride = 0;
     int64_t pairs_per_step = 0;
     float dt = 0.05f;
-    int block = 256;
     int persist_cpt = 1;            // cells per thread of the persistent kernel
-    size_t lds_bytes = 16;          // dynamic LDS of the step kernel
+    // tiles of one step, in two launches: [0] 256-thread workgroups (edge
+    // gathers, small networks), [1] 1024-thread workgroups (bitmaps, large
+    // all-to-all networks); captured as two parallel graph branches
+    infoli_rt::TileGroup grp[2];
+    std::vector<int> group_of;      // launch group of each network
     std::vector<int> rows_of;       // tile rows per network
     std::vector<double> deg_of;     // mean gap-junction degree per network
     int tuned = 0;                  // networks whose tiles came from timing runs
@@ -106,7 +117,6 @@ struct infoli_ctx {
     float* igap = nullptr;
     float* bias = nullptr;
     InstDesc* d_inst = nullptr;
-    Tile* d_tiles = nullptr;
     DevPulse* d_pulses = nullptr;
     int64_t* d_rowptr = nullptr;
     int32_t* d_col = nullptr;
@@ -145,7 +155,10 @@ struct infoli_ctx {
         if (stream) (void)hipStreamSynchronize(stream);
         for (void* p : allocs) (void)hipFree(p);
         allocs.clear();
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (side_stream) (void)hipStreamDestroy(side_stream);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -175,8 +188,13 @@ infoli_status guarded(infoli_ctx* ctx, F&& f) {
 }
 
 StepArgs make_args(const infoli_ctx* c, bool device_step);
-void launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, unsigned ntiles, size_t lds, int from,
-                  int64_t step_arg, int32_t off);
+void launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, int block, unsigned ntiles, size_t lds,
+                  int from, int64_t step_arg, int32_t off);
+// Both tile groups of one step (sequential on st, or forked onto the side
+// stream when `fork` and both groups have tiles).
+void launch_groups(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg, int32_t off,
+                   bool fork);
+int64_t tile_count(const infoli_ctx* c);
 void check_instance(const infoli_ctx* c, int32_t k);
 
 }  // namespace infoli_rt

@@ -152,14 +152,39 @@ int pick_lanes(double mean_degree, int block) {
 
 }  // namespace
 
-void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, unsigned ntiles, size_t lds, int from,
-                  int64_t step_arg, int32_t off) {
-    if (c->block == 1024)
+void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, int block, unsigned ntiles,
+                             size_t lds, int from, int64_t step_arg, int32_t off) {
+    if (ntiles == 0) return;
+    if (block == 1024)
         hipLaunchKernelGGL(k_step<1024>, dim3(ntiles), dim3(1024), lds, st, a, c->state[from],
                            c->state[from ^ 1], step_arg, off);
     else
         hipLaunchKernelGGL(k_step<256>, dim3(ntiles), dim3(256), lds, st, a, c->state[from],
                            c->state[from ^ 1], step_arg, off);
+}
+
+void infoli_rt::launch_groups(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
+                              int32_t off, bool fork) {
+    const bool both = !c->grp[0].tiles.empty() && !c->grp[1].tiles.empty();
+    if (fork && both) {
+        HIPX(hipEventRecord(c->fork_ev, st));
+        HIPX(hipStreamWaitEvent(c->side_stream, c->fork_ev, 0));
+    }
+    for (int g = 1; g >= 0; --g) {
+        const TileGroup& tg = c->grp[g];
+        StepArgs ag = a;
+        ag.tiles = tg.d_tiles;
+        hipStream_t s = (fork && both && g == 1) ? c->side_stream : st;
+        launch_tiles(c, s, ag, tg.block, (unsigned)tg.tiles.size(), tg.lds, from, step_arg, off);
+    }
+    if (fork && both) {
+        HIPX(hipEventRecord(c->join_ev, c->side_stream));
+        HIPX(hipStreamWaitEvent(st, c->join_ev, 0));
+    }
+}
+
+int64_t infoli_rt::tile_count(const infoli_ctx* c) {
+    return (int64_t)c->grp[0].tiles.size() + (int64_t)c->grp[1].tiles.size();
 }
 
 namespace {
@@ -176,27 +201,47 @@ void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int r
     }
 }
 
-// Tiles of every network, longest (estimated issue slots) first; dynamic LDS
-// for the Vd staging they need; descriptors and tiles to the device.
+// Launch group of a network: 1024-thread workgroups for bitmap tiles and
+// large all-to-all networks, 256-thread workgroups otherwise.
+int group_for(const InstDesc& d) {
+    if (d.conn == CONN_CSR && d.bitmap) return 1;
+    if (d.conn == CONN_UNIFORM && d.n >= 4096) return 1;
+    return 0;
+}
+
+size_t lds_floats_for(const InstDesc& d, int block) {
+    if (d.conn == CONN_UNIFORM) return (size_t)std::min(d.n, kChunk) + 8 * (size_t)(block / 64);
+    if (d.conn == CONN_CSR && d.bitmap) return bitmap_lds_floats(d.n);
+    if (d.conn == CONN_CSR && d.vd_lds) return (size_t)d.n;
+    return 4;
+}
+
+// Tiles of every network in their launch group, longest (estimated issue
+// slots) first; dynamic LDS per group; descriptors and tiles to the device.
 void finalize_tiles(infoli_ctx* c) {
-    std::vector<std::pair<double, Tile>> planned;
-    size_t floats = 4;
+    std::vector<std::pair<double, Tile>> planned[2];
+    size_t floats[2] = {4, 4};
+    c->group_of.assign(c->n_inst, 0);
     for (int k = 0; k < c->n_inst; ++k) {
         const InstDesc& d = c->inst[k];
-        append_tiles(planned, k, d.n, c->rows_of[k], c->deg_of[k]);
-        if (d.conn == CONN_UNIFORM)
-            floats = std::max(floats, (size_t)std::min(d.n, kChunk) + 8 * (size_t)(c->block / 64));
-        if (d.conn == CONN_CSR && d.vd_lds && !d.bitmap) floats = std::max(floats, (size_t)d.n);
-        if (d.conn == CONN_CSR && d.bitmap) floats = std::max(floats, bitmap_lds_floats(d.n));
+        const int g = group_for(d);
+        c->group_of[k] = g;
+        append_tiles(planned[g], k, d.n, c->rows_of[k], c->deg_of[k]);
+        floats[g] = std::max(floats[g], lds_floats_for(d, c->grp[g].block));
     }
-    c->lds_bytes = ((floats + 3) / 4) * sizeof(float4);
-    std::stable_sort(planned.begin(), planned.end(),
-                     [](const auto& x, const auto& y) { return x.first > y.first; });
-    c->tiles.clear();
-    for (const auto& pt : planned) c->tiles.push_back(pt.second);
-    if (c->tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
-    c->d_tiles = c->alloc<Tile>(c->tiles.size());
-    HIPX(hipMemcpy(c->d_tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(), hipMemcpyHostToDevice));
+    for (int g = 0; g < 2; ++g) {
+        TileGroup& tg = c->grp[g];
+        tg.lds = ((floats[g] + 3) / 4) * sizeof(float4);
+        std::stable_sort(planned[g].begin(), planned[g].end(),
+                         [](const auto& x, const auto& y) { return x.first > y.first; });
+        tg.tiles.clear();
+        for (const auto& pt : planned[g]) tg.tiles.push_back(pt.second);
+        if (tg.tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
+        if (!tg.tiles.empty()) {
+            tg.d_tiles = c->alloc<Tile>(tg.tiles.size());
+            HIPX(hipMemcpy(tg.d_tiles, tg.tiles.data(), sizeof(Tile) * tg.tiles.size(), hipMemcpyHostToDevice));
+        }
+    }
     HIPX(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDesc) * c->n_inst, hipMemcpyHostToDevice));
 }
 
@@ -247,7 +292,7 @@ std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v2.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v3.txt";
     return "";
 }
 
@@ -255,7 +300,8 @@ std::string tune_key(const infoli_ctx* c, const InstDesc& d, double deg) {
     const int nb = (int)std::ceil(std::log2((double)d.n) * 4.0);
     const int db = (int)std::ceil(std::log2(deg + 1.0) * 4.0);
     char buf[128];
-    snprintf(buf, sizeof buf, "gfx950 block%d c16=%d w=%d n%d d%d", c->block, d.col16, d.has_w, nb, db);
+    snprintf(buf, sizeof buf, "gfx950 groups2 c16=%d w=%d bits=%d n%d d%d", d.col16, d.has_w,
+             d.bits_off >= 0 ? 1 : 0, nb, db);
     return buf;
 }
 
@@ -310,10 +356,12 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
     StepArgs a = make_args(c, false);
     a.tiles = d_tmp;
     a.dry = 1;
-    for (int w = 0; w < 2; ++w) launch_tiles(c, c->stream, a, (unsigned)tl.size(), lds, c->cur, c->step, 0);
+    const int block = t.bm ? 1024 : 256;
+    for (int w = 0; w < 2; ++w) launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0);
     HIPX(hipEventRecord(c->ev0, c->stream));
     const int reps = 8;
-    for (int w = 0; w < reps; ++w) launch_tiles(c, c->stream, a, (unsigned)tl.size(), lds, c->cur, c->step, 0);
+    for (int w = 0; w < reps; ++w)
+        launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0);
     HIPX(hipEventRecord(c->ev1, c->stream));
     HIPX(hipGetLastError());
     HIPX(hipEventSynchronize(c->ev1));
@@ -340,7 +388,7 @@ void autotune(infoli_ctx* c) {
         const std::vector<int>& ks = kv.second;
         TuneChoice best{0, 0, 0, 0};
         auto hit = cache.find(key);
-        if (hit != cache.end() && hit->second.L <= c->block) {
+        if (hit != cache.end() && hit->second.L <= 256) {
             best = hit->second;
             c->tune_cached += (int)ks.size();
         } else {
@@ -353,11 +401,11 @@ void autotune(infoli_ctx* c) {
                 deg = std::max(deg, c->deg_of[k]);
             }
             float best_ms = 1e30f;
-            for (int L = 4; L <= c->block; L *= 2) {
+            for (int L = 4; L <= 256; L *= 2) {
                 if (L > 4 && L > 2.0 * deg) break;
                 if (deg / L > 256.0) continue;
                 for (int m = 1; m <= 4; m *= 2) {
-                    const int R = std::max(1, c->block / L) * m;
+                    const int R = std::max(1, 256 / L) * m;
                     if (R > kMaxTileRows) continue;
                     for (int lds = 0; lds <= (n <= kChunk ? 1 : 0); ++lds) {
                         const TuneChoice t{L, R, lds, 0};
@@ -385,7 +433,7 @@ void autotune(infoli_ctx* c) {
         }
         if (best.bm) {
             for (int k : ks)
-                if (c->inst[k].bits_off < 0) best = TuneChoice{best.L, std::max(1, c->block / best.L), 0, 0};
+                if (c->inst[k].bits_off < 0) best = TuneChoice{best.L, std::max(1, 256 / best.L), 0, 0};
         }
         for (int k : ks) {
             c->inst[k].lanes_per_row = best.L;
@@ -433,11 +481,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->n_inst = ninst;
     c->dt = specs[0].dt_ms;
     c->step = specs[0].step0;
-    // 1024-thread workgroups for large all-to-all networks (16 waves share the
-    // sender range of a 64-row tile); 256 otherwise
-    c->block = 256;
-    for (int k = 0; k < ninst; ++k)
-        if (specs[k].conn == INFOLI_CONN_UNIFORM_ALL && specs[k].n_cells >= 8192) c->block = 1024;
+    c->grp[0].block = 256;
+    c->grp[1].block = 1024;
 
     // ---- layout of the flattened networks
     int64_t cells = 0, rp_total = 0, w_total = 0, col_total = 0, stream_total = 0;
@@ -465,7 +510,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
             col_total += s.nnz;
             d.has_w = s.w_csr ? 1 : 0;
             const double deg = (double)s.nnz / s.n_cells;
-            d.lanes_per_row = std::min(c->block, c->opt.lanes_per_row ? c->opt.lanes_per_row : pick_lanes(deg, c->block));
+            d.lanes_per_row = std::min(256, c->opt.lanes_per_row ? c->opt.lanes_per_row : pick_lanes(deg, 256));
             c->pairs_per_step += s.nnz;
         } else if (s.conn == INFOLI_CONN_UNIFORM_ALL) {
             c->pairs_per_step += (int64_t)s.n_cells * (s.n_cells - 1);
@@ -509,7 +554,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
                 const double deg = (double)specs[k].nnz / d.n;
                 c->deg_of[k] = deg;
                 // one pass of row groups per tile: short dependent-load chains
-                const int per_pass = std::max(1, c->block / d.lanes_per_row);
+                const int per_pass = std::max(1, 256 / d.lanes_per_row);
                 rows = c->opt.tile_rows ? c->opt.tile_rows : std::min(kMaxTileRows, per_pass);
                 d.col16 = col16 ? 1 : 0;
                 d.vd_lds = (d.n <= kChunk && (double)rows * deg >= 2.0 * d.n) ? 1 : 0;
@@ -528,6 +573,9 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         c->own_stream = true;
     }
     HIPX(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPX(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+    HIPX(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
     HIPX(hipEventCreate(&c->ev0));
     HIPX(hipEventCreate(&c->ev1));
 
@@ -630,7 +678,7 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.inst = c->d_inst;
-    a.tiles = c->d_tiles;
+    a.tiles = c->grp[0].d_tiles;
     a.pulses = c->d_pulses;
     a.bias = c->bias;
     a.row_ptr = c->d_rowptr;
@@ -653,11 +701,6 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
 
 namespace {
 
-void launch_step(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
-                 int32_t off) {
-    launch_tiles(c, st, a, (unsigned)c->tiles.size(), c->lds_bytes, from, step_arg, off);
-}
-
 hipGraphExec_t get_graph(infoli_ctx* c, int parity) {
     if (c->graph[parity]) return c->graph[parity];
     const StepArgs a = make_args(c, true);
@@ -665,7 +708,7 @@ hipGraphExec_t get_graph(infoli_ctx* c, int parity) {
     HIPX(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int from = parity;
     for (int k = 0; k < c->opt.graph_chunk; ++k) {
-        launch_step(c, c->cap_stream, a, from, 0, k);
+        launch_groups(c, c->cap_stream, a, from, 0, k, true);
         from ^= 1;
     }
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -716,7 +759,7 @@ void run_steps(infoli_ctx* c, int64_t n_steps) {
     if (left > 0) {
         const StepArgs a = make_args(c, false);
         for (int64_t k = 0; k < left; ++k) {
-            launch_step(c, c->stream, a, c->cur, c->step, 0);
+            launch_groups(c, c->stream, a, c->cur, c->step, 0, false);
             c->cur ^= 1;
             c->step += 1;
         }
@@ -887,7 +930,7 @@ infoli_status infoli_read_gap_current(infoli_ctx* ctx, int32_t instance, float* 
         if (cap < d.n) fail(INFOLI_E_INVALID_ARG, "capacity %lld < %d", (long long)cap, d.n);
         StepArgs a = make_args(ctx, false);
         a.gap_only = 1;
-        launch_step(ctx, ctx->stream, a, ctx->cur, ctx->step, 0);
+        launch_groups(ctx, ctx->stream, a, ctx->cur, ctx->step, 0, false);
         HIPX(hipGetLastError());
         HIPX(hipStreamSynchronize(ctx->stream));
         HIPX(hipMemcpy(host, ctx->igap + d.cell_off, sizeof(float) * d.n, hipMemcpyDeviceToHost));
@@ -940,9 +983,10 @@ infoli_status infoli_get_info(const infoli_ctx* ctx, infoli_info* info) {
     info->pairs_per_step = ctx->pairs_per_step;
     info->step = ctx->step;
     info->step_mode = ctx->opt.step_mode;
-    info->n_tiles = (int32_t)ctx->tiles.size();
+    info->n_tiles = (int32_t)tile_count(ctx);
     int32_t rows = 0, lanes = 0;
-    for (const Tile& t : ctx->tiles) rows = std::max(rows, t.row1 - t.row0);
+    for (int g = 0; g < 2; ++g)
+        for (const Tile& t : ctx->grp[g].tiles) rows = std::max(rows, t.row1 - t.row0);
     for (const InstDesc& d : ctx->inst) lanes = std::max(lanes, d.lanes_per_row);
     info->tile_rows = rows;
     info->lanes_per_row = lanes;

@@ -91,7 +91,7 @@ SurrArgs surr_args(infoli_ctx* c, const infoli_drift_cfg& dc, int64_t macro_inde
 void launch_macro(infoli_ctx* c, hipStream_t st, const infoli_drift_cfg& dc, int from, int64_t step0) {
     StepArgs g = make_args(c, false);
     g.gap_only = 1;
-    launch_tiles(c, st, g, (unsigned)c->tiles.size(), c->lds_bytes, from, step0, 0);
+    launch_groups(c, st, g, from, step0, 0, false);
     const StepArgs a = make_args(c, false);
     const int64_t cells = c->total_cells;
     if (dc.mode == INFOLI_SURROGATE_PLAIN_HOLD) {
@@ -116,8 +116,8 @@ infoli_status infoli_default_train_cfg(infoli_train_cfg* cfg) {
     }
     std::memset(cfg, 0, sizeof(*cfg));
     cfg->n_transitions = 1000000;
-    cfg->n_trajectories = 16384;
-    cfg->burn_in = 50;
+    cfg->n_trajectories = 4096;
+    cfg->burn_in = 2500;
     cfg->batch = 4096;
     cfg->steps = 20000;
     cfg->lr = 1e-3f;

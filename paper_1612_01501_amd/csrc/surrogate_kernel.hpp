@@ -213,7 +213,8 @@ static __global__ __launch_bounds__(256) void k_hold4(StepArgs a, const float* _
 // N(0, bias_sd); a gap current following an AR(1) process with stationary
 // standard deviation gap_sd and lag-one correlation gap_rho per macro step;
 // pulses of amplitude U[pulse_lo, pulse_hi] lasting pulse_len macro steps,
-// starting with probability pulse_p per macro step. Initial state: rest plus
+// starting with probability pulse_p per macro step; a burn-in drawn uniformly
+// from [0, burn_in] macro steps before recording. Initial state: rest plus
 // U[-1, 1] mV on the three voltages. Random numbers: SplitMix64 finaliser of
 // (seed, trajectory, macro step, stream), uniform in (0, 1) from 24 bits.
 struct DataGenArgs {
@@ -223,7 +224,7 @@ struct DataGenArgs {
     float bias_sd, gap_sd, gap_rho, pulse_p, pulse_lo, pulse_hi;
     float vs_max;             // restart when the soma voltage exceeds this
     int32_t pulse_len;
-    int32_t burn_in;          // macro steps not recorded
+    int32_t burn_in;          // largest number of unrecorded macro steps
     int32_t per_traj;         // recorded macro steps per trajectory
     int32_t n_traj;
     uint64_t seed;
@@ -255,7 +256,10 @@ static __global__ void k_surrogate_data(DataGenArgs g) {
     int pulse_left = 0;
     float pulse_amp = 0.0f;
     const float innov = g.gap_sd * sqrtf(1.0f - g.gap_rho * g.gap_rho);
-    for (int m = 1; m <= g.burn_in + g.per_traj; ++m) {
+    // burn-in of this trajectory: uniform in [0, burn_in] macro steps, so the
+    // recorded states cover the slow variables' whole excursion
+    const int burn = (int)(u01(g.seed, t, 0, 60) * (float)(g.burn_in + 1));
+    for (int m = 1; m <= burn + g.per_traj; ++m) {
         if (x[SV_VS] > g.vs_max) {
             // spiking regime: the surrogate leaves it to the plain method
 #pragma unroll
@@ -299,8 +303,8 @@ static __global__ void k_surrogate_data(DataGenArgs g) {
                 for (int v = 0; v < NSV; ++v) x[v] = y[v];
             }
         }
-        if (m > g.burn_in) {
-            const int64_t r = (int64_t)(m - g.burn_in - 1) * g.n_traj + t;
+        if (m > burn) {
+            const int64_t r = (int64_t)(m - burn - 1) * g.n_traj + t;
             float* xr = g.x_raw + r * 16;
             float* dr = g.d_raw + r * 16;
 #pragma unroll
