@@ -27,6 +27,7 @@ Prints one JSON line (rank 0) with the throughput, a roofline entry for the
 step kernel and the CPU oracle timed on a bounded sample of the same work.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +41,34 @@ import numpy as np  # noqa: E402
 from paper_1612_01501_amd import inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+
+# Measured HBM traffic of the step kernel per workload (rocprofv3 FETCH_SIZE
+# and WRITE_SIZE, scaled by a plain-copy calibration), valid only for the
+# kernel sources it was taken with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCES = ("paper_1612_01501_amd/csrc/step_kernel.hpp", "paper_1612_01501_amd/csrc/cell_model.hpp",
+                  "paper_1612_01501_amd/csrc/runtime.hip")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """Bytes per launch, or None when no counters were taken for this
+    workload or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            entry = json.load(fh).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not entry or entry.get("kernel_sources_sha256") != kernel_source_hash():
+        return None
+    return entry["bytes_per_launch"]
 WORKLOADS = {
     "csr4096": dict(steps=20000, warmup=1000),
     "uni96": dict(steps=2000, warmup=200),
@@ -107,7 +136,19 @@ def algorithmic_bytes(nets):
 CSR_SLOTS_PER_EDGE = 9
 
 
-def roofline(nets, launch_s):
+def step_kernel_name(info):
+    """The kernel(s) one step launches, from the context's launch groups."""
+    if info["step_mode"] == 3:
+        return "infoli::k_persist"
+    wide, total = info["n_tiles_wide"], info["n_tiles"]
+    if wide == 0:
+        return "infoli::k_step<256>"
+    if wide == total:
+        return "infoli::k_step<1024>"
+    return "infoli::k_step<256> + infoli::k_step<1024> (concurrent graph branches)"
+
+
+def roofline(nets, launch_s, kernel="infoli::k_step<256>"):
     kinds = {n.conn for n in nets}
     if len(kinds) > 1:
         # mixed batch: issue slots of the pair/edge work against the lane-slot peak
@@ -116,19 +157,19 @@ def roofline(nets, launch_s):
         achieved = slots / launch_s / 1e12
         peak = LANE_SLOTS_PER_S / 1e12
         return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T lane-slots/s",
-                "frac": achieved / peak, "traffic": None, "kernel": "infoli::k_step<256>",
+                "frac": achieved / peak, "traffic": None, "kernel": kernel,
                 "slots_per_launch": slots}
     if all(n.conn == "uniform" for n in nets):
         pairs = sum(n.n * n.n for n in nets)       # the kernel evaluates the diagonal too
         achieved = pairs / launch_s / 1e9
         peak = LANE_SLOTS_PER_S / UNIFORM_SLOTS_PER_PAIR / 1e9
         return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
-                "frac": achieved / peak, "traffic": None, "kernel": "infoli::k_step<256>",
+                "frac": achieved / peak, "traffic": None, "kernel": kernel,
                 "slots_per_pair": UNIFORM_SLOTS_PER_PAIR, "pairs_per_launch": pairs}
     abytes = algorithmic_bytes(nets)
     achieved = abytes / launch_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "infoli::k_step<256>",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
             "algorithmic_bytes_per_launch": abytes}
 
 
@@ -206,7 +247,7 @@ def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
 
     surr = surrogate_run()
     hold = surrogate_run(mode="plain_hold")
-    nofb = surrogate_run(sample_every=0, vs_spiking=1e30)
+    nofb = surrogate_run(sample_every=0, v_max=1e30, z_max=0.0)
     cells = net.n
     total_steps = 4 * every * samples
     out = {
@@ -218,7 +259,9 @@ def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
         "config": {"workload": f"surr65k: {desc}", "cells": cells, "gap_pairs_per_step": net.pairs_per_step(),
-                   "tiles": info["n_tiles"], "lanes_per_row": info["lanes_per_row"]},
+                   "tiles": info["n_tiles"], "tiles_1024": info["n_tiles_wide"],
+                   "csr_bitmap_networks": info["n_bitmap"], "csr_blocked_networks": info["n_blocked"],
+                   "lanes_per_row": info["lanes_per_row"]},
         "plain_cell_steps_per_s": cells * total_steps / (t_plain * 1e-3),
         "plain_ms_per_step": t_plain / total_steps,
         "speedup": t_plain / surr["ms"],
@@ -229,8 +272,9 @@ def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
         "ablation_mlp_no_fallback": {"speedup": t_plain / nofb["ms"], "rmse_mv": nofb["rmse_mv"],
                                      "spike_time_err_ms": nofb["spike_time_err_ms"]},
         "training": {**rep, "wall_s": train_wall},
-        "roofline": roofline(nets, t_plain * 1e-3 / total_steps),
+        "roofline": roofline(nets, t_plain * 1e-3 / total_steps, step_kernel_name(info)),
     }
+    out["roofline"]["traffic"] = measured_traffic(args.workload)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)
     print(json.dumps(out), flush=True)
@@ -261,7 +305,7 @@ def main():
                     help="only run a device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the per-step Vd exchange across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     steps = args.steps if args.steps is not None else WORKLOADS[args.workload]["steps"]
@@ -313,11 +357,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "cells": cells,
                    "gap_pairs_per_step": pairs, "step_mode": args.mode,
-                   "tiles": info["n_tiles"], "lanes_per_row": info["lanes_per_row"]},
+                   "tiles": info["n_tiles"], "tiles_1024": info["n_tiles_wide"],
+                   "csr_bitmap_networks": info["n_bitmap"], "csr_blocked_networks": info["n_blocked"],
+                   "lanes_per_row": info["lanes_per_row"]},
         "gap_pairs_per_s": pairs * steps / wall,
         "device_ms_per_step": dev_ms / steps,
-        "roofline": roofline(nets, launch_s),
+        "roofline": roofline(nets, launch_s, step_kernel_name(info)),
     }
+    out["roofline"]["traffic"] = measured_traffic(args.workload)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -52,7 +52,7 @@ typedef enum infoli_status {
     INFOLI_E_DEVICE = 4,        /* HIP runtime error, or no gfx950 device                   */
     INFOLI_E_NUMERIC = 5,       /* a state value became NaN or infinite while stepping      */
     INFOLI_E_STATE = 6,         /* call not valid in the context's current state            */
-    INFOLI_E_UNSUPPORTED = 7    /* valid request that this build does not implement        */
+    INFOLI_E_UNSUPPORTED = 7    /* valid request that the library does not implement       */
 } infoli_status;
 
 /* Connectivity storage of one network (Section 2.3: N x N weights). */
@@ -143,9 +143,9 @@ typedef struct infoli_options {
     int32_t autotune;            /* CSR tile shapes: 0 => built-in rule; 1 => timed on the
                                     device at init, cached on disk (INFOLI_TUNE_CACHE, else
                                     ~/.cache/infoli-tune-v2.txt); 2 => timed, cache ignored */
-    int32_t csr_path;            /* CSR networks with one weight g: 0 => tuned choice;
-                                    1 => edge gathers; 2 => coupling bitmap (one bit per
-                                    pair, networks of <= 16,384 cells)                     */
+    int32_t csr_path;            /* CSR networks: 0 => tuned choice; 1 => edge gathers;
+                                    2 => coupling bitmap (one weight g, <= 16,384 cells);
+                                    3 => Vd staged in LDS by column blocks (> 8,192 cells) */
 } infoli_options;
 
 typedef struct infoli_ctx infoli_ctx;
@@ -224,6 +224,10 @@ typedef struct infoli_info {
     int64_t device_bytes;       /* device memory held                                   */
     int32_t tuned;              /* networks whose tile shapes were timed at init        */
     int32_t tune_cached;        /* networks whose tile shapes came from the cache       */
+    int32_t n_tiles_wide;       /* of n_tiles, those in 1024-thread workgroups (a second
+                                   launch per step, concurrent with the first)          */
+    int32_t n_bitmap;           /* CSR networks on the coupling-bitmap path             */
+    int32_t n_blocked;          /* CSR networks on the column-blocked path              */
 } infoli_info;
 infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
 
@@ -237,7 +241,7 @@ infoli_status infoli_last_step_ms(infoli_ctx *ctx, float *ms);
  * cell's normalised [14 state variables, I_gap, I_app] to its normalised state
  * increment over a macro step of 4 time steps, during which the gap current
  * (computed exactly in fp32 at the macro step's start) and the input are held.
- * The plain method stays the fallback and the judge (drift check). This part
+ * The plain method stays the fallback and the reference (drift check). This part
  * is not in the paper; it serves callers that trade a bounded error for speed.
  *
  * Parameters: INFOLI_MLP_PARAMS fp32 values in the order W1[128][16] b1[128]
@@ -255,14 +259,15 @@ typedef struct infoli_train_cfg {
     int32_t steps;              /* optimiser steps                                        */
     float lr, beta1, beta2, eps;/* Adam; the rate decays from lr to lr_min (cosine)        */
     float lr_min;
-    float vs_max;               /* a trajectory whose Vs exceeds this (mV) restarts from
-                                   rest: the MLP learns the subthreshold regime only (the
-                                   plain method advances spiking cells)                    */
+    float v_max;                /* the surrogate's regime: transitions are recorded only
+                                   when they start with Vd, Vs, Va <= v_max (mV, >= -50)   */
     float bias_sd;              /* per-trajectory constant input ~ N(0, bias_sd^2)        */
     float gap_sd, gap_rho;      /* AR(1) gap current: stationary sd, lag-1 correlation    */
     float pulse_p;              /* pulse start probability per macro step                 */
     float pulse_lo, pulse_hi;   /* pulse amplitude ~ U[lo, hi] uA/cm^2                    */
     int32_t pulse_len;          /* pulse length in macro steps                            */
+    float ca_max;               /*   and [Ca] <= ca_max (above the rest value); the same
+                                   bounds as infoli_drift_cfg's                            */
     uint64_t seed;              /* counter-based draws of the data and the batches        */
     const float *init_params;   /* [INFOLI_MLP_PARAMS] initial weights (host), required   */
 } infoli_train_cfg;
@@ -280,16 +285,24 @@ enum { INFOLI_SURROGATE_MLP = 0,        /* MLP with drift check and plain fallba
 typedef struct infoli_drift_cfg {
     float theta_mv;             /* a checked cell whose MLP voltages differ from the plain
                                    ones by more than this (mV) is flagged                 */
-    float vs_spiking;           /* Vs above this (mV): the plain method                   */
+    float v_max;                /* regime served by the MLP: Vd, Vs, Va <= v_max (mV)     */
     int32_t sample_every;       /* checked cells per macro step: 1 in sample_every; 0 = none */
     int32_t hold_steps;         /* macro steps a flagged cell stays on the plain method   */
     int32_t mode;               /* INFOLI_SURROGATE_*                                     */
+    float z_max;                /* a cell with a normalised MLP input beyond +-z_max is
+                                   guarded (0: no bound)                                  */
+    float ca_max;               /*   and [Ca] <= ca_max                                   */
 } infoli_drift_cfg;
 
 typedef struct infoli_drift_report {
     int64_t plain_cell_macro_steps;  /* cell macro steps advanced by the plain method     */
     int64_t checked;                 /* drift checks made                                 */
     int64_t flagged;                 /* checks past theta                                 */
+    int64_t guarded;                 /* cell macro steps sent to the plain method by the
+                                        guards: a cell outside the regime (v_max, ca_max),
+                                        an input beyond z_max, or an MLP candidate with a
+                                        voltage above v_max or beyond +-150 mV (or not
+                                        finite)                                          */
     float ms;                        /* device time of the call                           */
 } infoli_drift_report;
 
@@ -309,8 +322,13 @@ infoli_status infoli_surrogate_get(infoli_ctx *ctx, float *params, float *norm);
 infoli_status infoli_surrogate_set(infoli_ctx *ctx, const float *params, const float *norm);
 
 /* Advance n_macro macro steps of 4 time steps each (single-network contexts).
- * cfg NULL => defaults (theta 0.5 mV, Vs > -40 mV plain, 1/64 checked per macro
- * step, 50 macro steps of fallback). report optional (blocking when given). */
+ * A cell takes the MLP unless it is held, checked or guarded (see the report's
+ * fields); a checked cell runs the plain method and is flagged when the MLP's
+ * voltages differ from it by more than theta; a flagged cell is held on the
+ * plain method for hold_steps macro steps.
+ * cfg NULL => defaults (theta 0.5 mV, v_max -40 mV, ca_max 20, 1/64 checked per
+ * macro step, 50 macro steps of hold, z_max 8). report optional (blocking when
+ * given). */
 infoli_status infoli_step_surrogate(infoli_ctx *ctx, int64_t n_macro, const infoli_drift_cfg *cfg,
                                     infoli_drift_report *report);
 

@@ -74,7 +74,9 @@ struct SurrogateState {
     uint16_t* wb = nullptr;             // bf16 copies
     float norm[64] = {0};               // in_mean[16] in_rstd[16] out_mean[16] out_std[16]
     int32_t* hold = nullptr;            // [cells]
-    uint32_t* counters = nullptr;       // [4]
+    unsigned long long* counters = nullptr;   // [4] plain, checked, flagged, guarded
+    void* list = nullptr;               // [cells] cells for the plain method this macro step
+    unsigned int* list_count = nullptr;
 };
 
 }  // namespace infoli_rt
@@ -88,6 +90,8 @@ struct infoli_ctx {
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
     hipStream_t side_stream = nullptr;  // second branch of captured steps
+    bool fork_groups = true;            // captured steps run the two launch groups concurrently
+    int n_cu = 256;                     // compute units of the device
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     infoli_options opt{};
     std::string err;
@@ -122,6 +126,8 @@ struct infoli_ctx {
     int32_t* d_col = nullptr;
     uint16_t* d_col16 = nullptr;
     uint32_t* d_bits = nullptr;
+    int32_t* d_blk = nullptr;       // blocked CSR: per-row block starts
+    int blk_cols = 8192;            // blocked CSR: cells per LDS block
     float* d_w = nullptr;
     float* d_stream = nullptr;
     int32_t* d_spk_count = nullptr;

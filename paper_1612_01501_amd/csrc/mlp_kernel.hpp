@@ -52,7 +52,7 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float sigmoid_f(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ __forceinline__ float silu_grad_f(float z) {
     const float s = sigmoid_f(z);
@@ -69,13 +69,33 @@ __device__ __forceinline__ MlpSmem mlp_smem(uint16_t* base) {
     return MlpSmem{base, base + kLdsW1, base + kLdsW1 + kLdsW2};
 }
 
-// Copy the bf16 weights (dense [out][in] in global memory) into padded LDS.
+// Copy the bf16 weights (dense [out][in] in global memory) into padded LDS,
+// four weights (8 bytes) per access, eight loads in flight per thread before
+// their stores. Every matrix offset and padded row start is a multiple of
+// four weights.
+template <int ROWS, int COLS, int S>
+__device__ __forceinline__ void copy_matrix_lds(const uint16_t* __restrict__ src, uint16_t* dst) {
+    constexpr int kChunks = ROWS * COLS / 4, kPerRow = COLS / 4, kUnroll = 8;
+    const uint2* g = reinterpret_cast<const uint2*>(src);
+    for (int e0 = threadIdx.x; e0 < kChunks; e0 += kUnroll * blockDim.x) {
+        uint2 v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int e = e0 + u * blockDim.x;
+            if (e < kChunks) v[u] = g[e];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int e = e0 + u * blockDim.x;
+            if (e < kChunks) *reinterpret_cast<uint2*>(dst + (e / kPerRow) * S + 4 * (e % kPerRow)) = v[u];
+        }
+    }
+}
+
 __device__ __forceinline__ void load_weights_lds(const uint16_t* __restrict__ wb, MlpSmem s) {
-    for (int e = threadIdx.x; e < kHid * kIn; e += blockDim.x) s.w1[(e / kIn) * kS1 + e % kIn] = wb[kOffW1 + e];
-    for (int e = threadIdx.x; e < kHid * kHid; e += blockDim.x)
-        s.w2[(e / kHid) * kS2 + e % kHid] = wb[kOffW2 + e];
-    for (int e = threadIdx.x; e < kOut * kHid; e += blockDim.x)
-        s.w3[(e / kHid) * kS3 + e % kHid] = wb[kOffW3 + e];
+    copy_matrix_lds<kHid, kIn, kS1>(wb + kOffW1, s.w1);
+    copy_matrix_lds<kHid, kHid, kS2>(wb + kOffW2, s.w2);
+    copy_matrix_lds<kOut, kHid, kS3>(wb + kOffW3, s.w3);
 }
 
 // A operand: rows rb*16 .. +15 of W (stride S), columns kb*16 + 4*(lane/16) .. +3
@@ -185,7 +205,7 @@ static __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const float* __restr
                                                      const float* __restrict__ tn, int64_t n_data,
                                                      int batch, uint64_t seed, uint64_t step,
                                                      TrainBufs buf) {
-    __shared__ uint16_t s_w[kMlpLdsElems];
+    __shared__ __align__(16) uint16_t s_w[kMlpLdsElems];
     const MlpSmem s = mlp_smem(s_w);
     load_weights_lds(wb, s);
     __syncthreads();
@@ -257,13 +277,18 @@ static __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const float* __restr
 }
 
 // Weight and bias gradients as GEMMs over the batch: one wave per 16x16
-// output tile, K = batch in order (deterministic). Tiles: dW1 8, dW2 64,
+// output tile and slice of the batch (split K), each slice summed in order
+// into its own partial gradient [kGradSplits][kNumParams]; the partials are
+// added in slice order afterwards (deterministic). Tiles: dW1 8, dW2 64,
 // dW3 8, then bias rows as products with a ones vector: db1 8, db2 8, db3 1.
 constexpr int kGradTiles = 8 + 64 + 8 + 8 + 8 + 1;
+constexpr int kGradSplits = 16;
 
-static __global__ __launch_bounds__(64) void k_mlp_wgrad(TrainBufs buf, int batch, float* __restrict__ grad,
+static __global__ __launch_bounds__(64) void k_mlp_wgrad(TrainBufs buf, int batch, float* __restrict__ grad_part,
                                                   float* __restrict__ loss_out) {
-    const int t = blockIdx.x;
+    const int t = blockIdx.x % kGradTiles;
+    const int split = blockIdx.x / kGradTiles;
+    float* grad = grad_part + (int64_t)split * kNumParams;
     const int l = threadIdx.x & 63;
     const int g = l >> 4;
     const uint16_t* A;   // [rows][batch]
@@ -286,7 +311,9 @@ static __global__ __launch_bounds__(64) void k_mlp_wgrad(TrainBufs buf, int batc
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     const uint16_t* arow = A + (int64_t)(ib * 16 + (l & 15)) * batch + 4 * g;
     const uint16_t* brow = Bm ? Bm + (int64_t)(jb * 16 + (l & 15)) * batch + 4 * g : nullptr;
-    for (int k = 0; k < batch; k += 16) {
+    const int kb = batch / 16;
+    const int k0 = (int)((int64_t)split * kb / kGradSplits), k1 = (int)((int64_t)(split + 1) * kb / kGradSplits);
+    for (int k = 16 * k0; k < 16 * k1; k += 16) {
         const bf16x4 av = *reinterpret_cast<const bf16x4*>(arow + k);
         const bf16x4 bv = Bm ? *reinterpret_cast<const bf16x4*>(brow + k) : ones;
         acc = mfma16(av, bv, acc);
@@ -300,20 +327,34 @@ static __global__ __launch_bounds__(64) void k_mlp_wgrad(TrainBufs buf, int batc
 #pragma unroll
         for (int e = 0; e < 4; ++e) grad[off + (ib * 16 + 4 * g + e) * ncols + jb * 16 + (l & 15)] = acc[e];
     }
-    if (t == 0 && l == 0 && loss_out) {
+    if (t == 0 && split == 0 && loss_out) {   // whole wave: strided partial sums, fixed butterfly
         float s = 0.0f;
-        for (int w = 0; w < batch / 16; ++w) s += buf.loss_part[w];
-        *loss_out = s / (float)(batch * kTargets);
+        for (int w = l; w < batch / 16; w += 64) s += buf.loss_part[w];
+        for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+        if (l == 0) *loss_out = s / (float)(batch * kTargets);
     }
 }
 
-// Adam (Kingma and Ba, 2015) on the fp32 masters, then their bf16 copies.
+// Sum of the split-K partial gradients, in slice order.
+__device__ __forceinline__ float grad_sum(const float* __restrict__ part, int splits, int e) {
+    float gr = part[e];
+    for (int sp = 1; sp < splits; ++sp) gr += part[(int64_t)sp * kNumParams + e];
+    return gr;
+}
+
+static __global__ void k_grad_reduce(const float* __restrict__ part, int splits, float* __restrict__ grad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < kNumParams) grad[e] = grad_sum(part, splits, e);
+}
+
+// Adam (Kingma and Ba, 2015) on the fp32 masters, then their bf16 copies;
+// the gradient is the sum of `splits` partials [splits][kNumParams].
 static __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
-                       const float* __restrict__ grad, uint16_t* __restrict__ wb, float lr, float b1,
+                       const float* __restrict__ grad, int splits, uint16_t* __restrict__ wb, float lr, float b1,
                        float b2, float eps, float corr1, float corr2) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kNumParams) return;
-    const float gr = grad[e];
+    const float gr = grad_sum(grad, splits, e);
     const float mm = b1 * m[e] + (1.0f - b1) * gr;
     const float vv = b2 * v[e] + (1.0f - b2) * gr * gr;
     m[e] = mm;
@@ -329,7 +370,7 @@ static __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restr
                                                      const uint16_t* __restrict__ wb,
                                                      const float* __restrict__ x, int batch,
                                                      float* __restrict__ y) {
-    __shared__ uint16_t s_w[kMlpLdsElems];
+    __shared__ __align__(16) uint16_t s_w[kMlpLdsElems];
     const MlpSmem s = mlp_smem(s_w);
     load_weights_lds(wb, s);
     __syncthreads();

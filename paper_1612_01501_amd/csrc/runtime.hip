@@ -204,12 +204,13 @@ void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int r
 // Launch group of a network: 1024-thread workgroups for bitmap tiles and
 // large all-to-all networks, 256-thread workgroups otherwise.
 int group_for(const InstDesc& d) {
-    if (d.conn == CONN_CSR && d.bitmap) return 1;
+    if (d.conn == CONN_CSR && (d.blocked || (d.bitmap && d.wide))) return 1;
     if (d.conn == CONN_UNIFORM && d.n >= 4096) return 1;
     return 0;
 }
 
-size_t lds_floats_for(const InstDesc& d, int block) {
+size_t lds_floats_for(const infoli_ctx* c, const InstDesc& d, int block) {
+    if (d.conn == CONN_CSR && d.blocked) return (size_t)std::min(d.n, c->blk_cols);
     if (d.conn == CONN_UNIFORM) return (size_t)std::min(d.n, kChunk) + 8 * (size_t)(block / 64);
     if (d.conn == CONN_CSR && d.bitmap) return bitmap_lds_floats(d.n);
     if (d.conn == CONN_CSR && d.vd_lds) return (size_t)d.n;
@@ -227,7 +228,7 @@ void finalize_tiles(infoli_ctx* c) {
         const int g = group_for(d);
         c->group_of[k] = g;
         append_tiles(planned[g], k, d.n, c->rows_of[k], c->deg_of[k]);
-        floats[g] = std::max(floats[g], lds_floats_for(d, c->grp[g].block));
+        floats[g] = std::max(floats[g], lds_floats_for(c, d, c->grp[g].block));
     }
     for (int g = 0; g < 2; ++g) {
         TileGroup& tg = c->grp[g];
@@ -278,6 +279,39 @@ void build_bitmaps(infoli_ctx* c, const infoli_network_spec* specs) {
     HIPX(hipMemcpy(c->d_bits, h.data(), sizeof(uint32_t) * words, hipMemcpyHostToDevice));
 }
 
+// Column blocks of CSR networks too large for one LDS copy of Vd: for each
+// row, the offset (from the row start) of its first edge in each block of
+// blk_cols cells (columns are sorted).
+void build_blocks(infoli_ctx* c, const infoli_network_spec* specs) {
+    int64_t total = 0;
+    for (int k = 0; k < c->n_inst; ++k) {
+        InstDesc& d = c->inst[k];
+        d.blk_off = -1;
+        d.nblk = 0;
+        if (d.conn != CONN_CSR || d.n <= kChunk || specs[k].nnz == 0) continue;
+        d.nblk = (d.n + c->blk_cols - 1) / c->blk_cols;
+        d.blk_off = total;
+        total += (int64_t)d.n * d.nblk;
+    }
+    if (total == 0) return;
+    std::vector<int32_t> h((size_t)total);
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstDesc& d = c->inst[k];
+        if (d.blk_off < 0) continue;
+        const infoli_network_spec& s = specs[k];
+        for (int i = 0; i < d.n; ++i) {
+            const int64_t rs = s.row_ptr[i], re = s.row_ptr[i + 1];
+            int64_t e = rs;
+            for (int b = 0; b < d.nblk; ++b) {
+                while (e < re && s.col[e] < b * c->blk_cols) ++e;
+                h[(size_t)(d.blk_off + (int64_t)i * d.nblk + b)] = (int32_t)(e - rs);
+            }
+        }
+    }
+    c->d_blk = c->alloc<int32_t>((size_t)total);
+    HIPX(hipMemcpy(c->d_blk, h.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice));
+}
+
 // ---------------------------------------------------------------- autotuner
 // For every class of CSR network (log-spaced size and degree buckets) the
 // candidate tile shapes (lanes per row, rows per tile, LDS staging of Vd) are
@@ -285,14 +319,15 @@ void build_bitmaps(infoli_ctx* c, const infoli_network_spec* specs) {
 // the next-state buffer) and the fastest is kept, in memory and in an
 // on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v1.txt).
 struct TuneChoice {
-    int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS, bitmap path
+    int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS, path (0 gathers, 1 bitmap, 2 blocked)
+    int block;             // workgroup size of the launch group (256 or 1024)
 };
 
 std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v3.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v5.txt";
     return "";
 }
 
@@ -300,39 +335,54 @@ std::string tune_key(const infoli_ctx* c, const InstDesc& d, double deg) {
     const int nb = (int)std::ceil(std::log2((double)d.n) * 4.0);
     const int db = (int)std::ceil(std::log2(deg + 1.0) * 4.0);
     char buf[128];
-    snprintf(buf, sizeof buf, "gfx950 groups2 c16=%d w=%d bits=%d n%d d%d", d.col16, d.has_w,
-             d.bits_off >= 0 ? 1 : 0, nb, db);
+    snprintf(buf, sizeof buf, "gfx950 groups2 c16=%d w=%d bits=%d blk=%d n%d d%d", d.col16, d.has_w,
+             d.bits_off >= 0 ? 1 : 0, d.blk_off >= 0 ? c->blk_cols : 0, nb, db);
     return buf;
 }
 
-std::map<std::string, TuneChoice> read_tune_cache(const std::string& path) {
+// Lines "<class key>|L R lds bm block" (the class's best shape),
+// "<class key>#256|..." (its best shape in 256-thread workgroups) and
+// "ctx <hash>|mode" (the whole-step launch choice of one mix of networks).
+std::map<std::string, TuneChoice> read_tune_cache(const std::string& path, std::map<std::string, int>* modes) {
     std::map<std::string, TuneChoice> m;
     if (path.empty()) return m;
     std::FILE* f = std::fopen(path.c_str(), "r");
     if (!f) return m;
-    char line[256];
+    char line[512];
     while (std::fgets(line, sizeof line, f)) {
         char* bar = std::strchr(line, '|');
         if (!bar) continue;
         *bar = 0;
+        if (std::strncmp(line, "ctx ", 4) == 0) {
+            int mode = -1;
+            if (std::sscanf(bar + 1, "%d", &mode) == 1 && mode >= 0 && mode <= 3) (*modes)[line] = mode;
+            continue;
+        }
         TuneChoice t;
-        if (std::sscanf(bar + 1, "%d %d %d %d", &t.L, &t.R, &t.lds, &t.bm) == 4 && t.L >= 4 && t.L <= 1024 &&
+        if (std::sscanf(bar + 1, "%d %d %d %d %d", &t.L, &t.R, &t.lds, &t.bm, &t.block) == 5 &&
+            (t.block == 256 || t.block == 1024) && t.L >= 4 && t.L <= 1024 &&
             (t.L & (t.L - 1)) == 0 && t.R >= 1 && t.R <= kMaxTileRows && (t.lds == 0 || t.lds == 1) &&
-            (t.bm == 0 || t.bm == 1))
+            (t.bm >= 0 && t.bm <= 2))
             m[line] = t;
     }
     std::fclose(f);
     return m;
 }
 
-void append_tune_cache(const std::string& path, const std::string& key, const TuneChoice& t) {
+void append_tune_line(const std::string& path, const std::string& line) {
     if (path.empty()) return;
     const size_t slash = path.find_last_of('/');
     if (slash != std::string::npos) mkdir(path.substr(0, slash).c_str(), 0755);
     std::FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s|%d %d %d %d\n", key.c_str(), t.L, t.R, t.lds, t.bm);
+    std::fprintf(f, "%s\n", line.c_str());
     std::fclose(f);
+}
+
+void append_tune_cache(const std::string& path, const std::string& key, const TuneChoice& t) {
+    char buf[64];
+    snprintf(buf, sizeof buf, "|%d %d %d %d %d", t.L, t.R, t.lds, t.bm, t.block);
+    append_tune_line(path, key + buf);
 }
 
 // Average duration of a dry launch of the tiles of networks `ks` (one size
@@ -344,10 +394,12 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
         InstDesc d = c->inst[k];
         d.lanes_per_row = t.L;
         d.vd_lds = t.lds;
-        d.bitmap = t.bm;
+        d.bitmap = t.bm == 1;
+        d.blocked = t.bm == 2;
         HIPX(hipMemcpy(c->d_inst + k, &d, sizeof(d), hipMemcpyHostToDevice));
         append_tiles(planned, k, d.n, t.R, 0.0);
-        if (t.bm) lds = std::max(lds, ((bitmap_lds_floats(d.n) + 3) / 4) * sizeof(float4));
+        if (t.bm == 1) lds = std::max(lds, ((bitmap_lds_floats(d.n) + 3) / 4) * sizeof(float4));
+        else if (t.bm == 2) lds = std::max(lds, ((size_t)(std::min(d.n, c->blk_cols) + 3) / 4) * sizeof(float4));
         else if (t.lds) lds = std::max(lds, ((size_t)(d.n + 3) / 4) * sizeof(float4));
     }
     std::vector<Tile> tl;
@@ -356,7 +408,7 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
     StepArgs a = make_args(c, false);
     a.tiles = d_tmp;
     a.dry = 1;
-    const int block = t.bm ? 1024 : 256;
+    const int block = t.block;
     for (int w = 0; w < 2; ++w) launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0);
     HIPX(hipEventRecord(c->ev0, c->stream));
     const int reps = 8;
@@ -370,11 +422,56 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
     return ms / reps;
 }
 
+void apply_choice(infoli_ctx* c, const std::vector<int>& ks, TuneChoice best) {
+    for (int k : ks)   // a cached choice this context cannot honour falls back to gathers
+        if ((best.bm == 1 && c->inst[k].bits_off < 0) || (best.bm == 2 && c->inst[k].blk_off < 0))
+            best = TuneChoice{std::min(best.L, 256), std::max(1, 256 / std::min(best.L, 256)), 0, 0, 256};
+    for (int k : ks) {
+        c->inst[k].lanes_per_row = best.L;
+        c->inst[k].vd_lds = best.lds;
+        c->inst[k].bitmap = best.bm == 1;
+        c->inst[k].blocked = best.bm == 2;
+        c->inst[k].wide = best.block == 1024;
+        c->rows_of[k] = best.R;
+    }
+}
+
+// Average duration of a dry whole step (both launch groups) as finalised.
+float time_step(infoli_ctx* c, bool fork) {
+    StepArgs a = make_args(c, false);
+    a.dry = 1;
+    for (int w = 0; w < 3; ++w) launch_groups(c, c->stream, a, c->cur, c->step, 0, fork);
+    HIPX(hipEventRecord(c->ev0, c->stream));
+    const int reps = 20;
+    for (int w = 0; w < reps; ++w) launch_groups(c, c->stream, a, c->cur, c->step, 0, fork);
+    HIPX(hipEventRecord(c->ev1, c->stream));
+    HIPX(hipGetLastError());
+    HIPX(hipEventSynchronize(c->ev1));
+    float ms = 0.0f;
+    HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    return ms / reps;
+}
+
+uint64_t fnv1a(const std::string& s) {
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char ch : s) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Per size/degree class of CSR network, the tile shape and path with the
+// shortest dry launch of that class alone (its best overall and its best in
+// 256-thread workgroups); then, for the whole mix of networks, the faster of
+// the per-class best shapes and the all-256 shapes, with the two launch
+// groups as concurrent branches or one after the other, timed as whole steps.
 void autotune(infoli_ctx* c) {
     if (c->opt.lanes_per_row || c->opt.tile_rows) return;   // shapes given by the caller
     const std::string path = tune_cache_path();
     std::map<std::string, TuneChoice> cache;
-    if (c->opt.autotune == 1) cache = read_tune_cache(path);
+    std::map<std::string, int> modes;
+    if (c->opt.autotune == 1) cache = read_tune_cache(path, &modes);
     // classes of CSR networks
     std::map<std::string, std::vector<int>> classes;
     for (int k = 0; k < c->n_inst; ++k) {
@@ -383,13 +480,17 @@ void autotune(infoli_ctx* c) {
         classes[tune_key(c, d, c->deg_of[k])].push_back(k);
     }
     Tile* d_tmp = nullptr;
+    std::map<std::string, std::pair<TuneChoice, TuneChoice>> chosen;   // best, best in 256 threads
     for (const auto& kv : classes) {
         const std::string& key = kv.first;
         const std::vector<int>& ks = kv.second;
-        TuneChoice best{0, 0, 0, 0};
+        TuneChoice best{0, 0, 0, 0, 256}, best256{0, 0, 0, 0, 256};
         auto hit = cache.find(key);
-        if (hit != cache.end() && hit->second.L <= 256) {
+        auto hit256 = cache.find(key + "#256");
+        if (hit != cache.end() && hit256 != cache.end() && hit->second.L <= 256 && hit256->second.L <= 256 &&
+            hit256->second.block == 256) {
             best = hit->second;
+            best256 = hit256->second;
             c->tune_cached += (int)ks.size();
         } else {
             if (!d_tmp) d_tmp = c->alloc<Tile>(c->total_cells + 1);
@@ -400,48 +501,97 @@ void autotune(infoli_ctx* c) {
                 n = std::max(n, c->inst[k].n);
                 deg = std::max(deg, c->deg_of[k]);
             }
-            float best_ms = 1e30f;
+            float best_ms = 1e30f, best256_ms = 1e30f;
+            auto consider = [&](const TuneChoice& t) {
+                const float ms = time_shape(c, ks, t, d_tmp);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+                if (t.block == 256 && ms < best256_ms) {
+                    best256_ms = ms;
+                    best256 = t;
+                }
+            };
             for (int L = 4; L <= 256; L *= 2) {
                 if (L > 4 && L > 2.0 * deg) break;
                 if (deg / L > 256.0) continue;
                 for (int m = 1; m <= 4; m *= 2) {
                     const int R = std::max(1, 256 / L) * m;
                     if (R > kMaxTileRows) continue;
-                    for (int lds = 0; lds <= (n <= kChunk ? 1 : 0); ++lds) {
-                        const TuneChoice t{L, R, lds, 0};
-                        const float ms = time_shape(c, ks, t, d_tmp);
-                        if (ms < best_ms) {
-                            best_ms = ms;
-                            best = t;
-                        }
-                    }
+                    for (int lds = 0; lds <= (n <= kChunk ? 1 : 0); ++lds) consider(TuneChoice{L, R, lds, 0, 256});
                 }
             }
             // the bitmap path, when every network of the class has one
             bool all_bits = c->d_bits != nullptr;
             for (int k : ks) all_bits = all_bits && c->inst[k].bits_off >= 0;
-            if (all_bits) {
-                const TuneChoice t{best.L, kBitRows, 0, 1};
-                const float ms = time_shape(c, ks, t, d_tmp);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
+            if (all_bits)
+                for (int blk : {256, 1024}) consider(TuneChoice{best256.L, kBitRows, 0, 1, blk});
+            // the column-blocked path, when every network of the class has it
+            bool all_blk = c->d_blk != nullptr;
+            for (int k : ks) all_blk = all_blk && c->inst[k].blk_off >= 0;
+            if (all_blk)
+                for (int L = 8; L <= 64; L *= 2) {
+                    if (L > 8 && L > 2.0 * deg / c->inst[ks[0]].nblk) break;
+                    for (int m = 1; m <= kBlkPasses; m *= 2) {
+                        const int R = (1024 / L) * m;
+                        if (R > kMaxTileRows) continue;
+                        consider(TuneChoice{L, R, 0, 2, 1024});
+                    }
                 }
-            }
             append_tune_cache(path, key, best);
+            append_tune_cache(path, key + "#256", best256);
             c->tuned += (int)ks.size();
         }
-        if (best.bm) {
-            for (int k : ks)
-                if (c->inst[k].bits_off < 0) best = TuneChoice{best.L, std::max(1, 256 / best.L), 0, 0};
-        }
-        for (int k : ks) {
-            c->inst[k].lanes_per_row = best.L;
-            c->inst[k].vd_lds = best.lds;
-            c->inst[k].bitmap = best.bm;
-            c->rows_of[k] = best.R;
-        }
+        chosen[key] = {best, best256};
     }
+
+    // whole-step choice for this mix of networks
+    std::vector<std::string> parts;
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstDesc& d = c->inst[k];
+        char buf[64];
+        snprintf(buf, sizeof buf, "%d:%d:%d", d.conn, d.n, group_for(d));
+        parts.push_back(d.conn == CONN_CSR && c->deg_of[k] > 0.0 ? tune_key(c, d, c->deg_of[k]) : buf);
+    }
+    std::sort(parts.begin(), parts.end());
+    std::string sig;
+    for (const auto& p : parts) sig += p + ";";
+    char ctx_key[64];
+    snprintf(ctx_key, sizeof ctx_key, "ctx %016llx", (unsigned long long)fnv1a(sig));
+    auto apply_all = [&](bool use256) {
+        for (const auto& kv : classes) {
+            const auto& ch = chosen[kv.first];
+            apply_choice(c, kv.second, use256 ? ch.second : ch.first);
+        }
+    };
+    int mode = 0;   // bit 0: 256-thread shapes for every class; bit 1: groups one after the other
+    auto mh = modes.find(ctx_key);
+    if (mh != modes.end()) {
+        mode = mh->second;
+    } else {
+        float best_ms = 1e30f;
+        for (int m = 0; m < 4; ++m) {
+            const bool use256 = m & 1;
+            bool differs = false;   // the all-256 variant only where some class prefers 1024 threads
+            for (const auto& kv : chosen) differs = differs || kv.second.first.block != 256;
+            if (use256 && !differs) continue;
+            apply_all(use256);
+            finalize_tiles(c);
+            const bool both = !c->grp[0].tiles.empty() && !c->grp[1].tiles.empty();
+            if ((m & 2) && !both) continue;
+            const float ms = time_step(c, !(m & 2));
+            if (ms < best_ms) {
+                best_ms = ms;
+                mode = m;
+            }
+        }
+        char line[96];
+        snprintf(line, sizeof line, "%s|%d", ctx_key, mode);
+        append_tune_line(path, line);
+    }
+    apply_all(mode & 1);
+    c->fork_groups = !(mode & 2);
 }
 
 void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t ninst,
@@ -461,8 +611,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         fail(INFOLI_E_INVALID_ARG, "lanes_per_row must be 0 or a power of two in [4, 256]");
     if (c->opt.autotune < 0 || c->opt.autotune > 2)
         fail(INFOLI_E_INVALID_ARG, "autotune must be 0, 1 or 2");
-    if (c->opt.csr_path < 0 || c->opt.csr_path > 2)
-        fail(INFOLI_E_INVALID_ARG, "csr_path must be 0, 1 or 2");
+    if (c->opt.csr_path < 0 || c->opt.csr_path > 3)
+        fail(INFOLI_E_INVALID_ARG, "csr_path must be 0, 1, 2 or 3");
     if (c->opt.tile_rows < 0 || c->opt.tile_rows > kMaxTileRows)
         fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
     for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
@@ -479,10 +629,17 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         fail(INFOLI_E_DEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
 
     c->n_inst = ninst;
+    c->n_cu = std::max(1, prop.multiProcessorCount);
     c->dt = specs[0].dt_ms;
     c->step = specs[0].step0;
     c->grp[0].block = 256;
     c->grp[1].block = 1024;
+    {
+        int lds_max = 0;
+        HIPX(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        // 16,384-cell blocks (64 KB) when the 1024-thread kernel's static LDS fits beside them
+        c->blk_cols = lds_max >= 16384 * 4 + 8192 ? 16384 : 8192;
+    }
 
     // ---- layout of the flattened networks
     int64_t cells = 0, rp_total = 0, w_total = 0, col_total = 0, stream_total = 0;
@@ -661,11 +818,20 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     HIPX(hipMemset(c->igap, 0, sizeof(float) * S));
     HIPX(hipDeviceSynchronize());
     build_bitmaps(c, specs);
+    build_blocks(c, specs);
     if (c->opt.autotune && c->opt.csr_path == 0) autotune(c);
+    if (c->opt.csr_path == 3)
+        for (int k = 0; k < ninst; ++k)
+            if (c->inst[k].blk_off >= 0) {
+                c->inst[k].blocked = 1;
+                c->inst[k].lanes_per_row = std::min(64, std::max(8, c->inst[k].lanes_per_row));
+                c->rows_of[k] = std::min(kMaxTileRows, 1024 / c->inst[k].lanes_per_row);
+            }
     if (c->opt.csr_path == 2)
         for (int k = 0; k < ninst; ++k)
             if (c->inst[k].bits_off >= 0) {
                 c->inst[k].bitmap = 1;
+                c->inst[k].wide = 0;
                 c->rows_of[k] = kBitRows;
             }
     finalize_tiles(c);
@@ -685,6 +851,8 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     a.col = c->d_col;
     a.col16 = c->d_col16;
     a.bits = c->d_bits;
+    a.blk = c->d_blk;
+    a.blk_cols = c->blk_cols;
     a.w = c->d_w;
     a.i_stream = c->d_stream;
     a.spike_count = c->d_spk_count;
@@ -708,7 +876,7 @@ hipGraphExec_t get_graph(infoli_ctx* c, int parity) {
     HIPX(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int from = parity;
     for (int k = 0; k < c->opt.graph_chunk; ++k) {
-        launch_groups(c, c->cap_stream, a, from, 0, k, true);
+        launch_groups(c, c->cap_stream, a, from, 0, k, c->fork_groups);
         from ^= 1;
     }
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -993,6 +1161,11 @@ infoli_status infoli_get_info(const infoli_ctx* ctx, infoli_info* info) {
     info->device_bytes = (int64_t)ctx->device_bytes;
     info->tuned = ctx->tuned;
     info->tune_cached = ctx->tune_cached;
+    info->n_tiles_wide = (int32_t)ctx->grp[1].tiles.size();
+    for (const InstDesc& d : ctx->inst) {
+        info->n_bitmap += d.conn == CONN_CSR && d.bitmap;
+        info->n_blocked += d.conn == CONN_CSR && d.blocked;
+    }
     return INFOLI_OK;
 }
 

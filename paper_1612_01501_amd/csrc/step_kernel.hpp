@@ -18,6 +18,10 @@
 //                four lane groups per cell take interleaved 32-sender blocks
 //                of a 128-sender group (conflict-free LDS rows), waves split
 //                the groups; every pair is evaluated and masked.
+//   BLOCKED CSR  (networks too large for one LDS copy of Vd) Vd is staged in
+//                LDS one column block at a time; each row's edges of that
+//                block (precomputed offsets, columns sorted) gather from LDS;
+//                partial sums stay in registers across blocks.
 //   CSR          groups of L lanes per row stride over the row's edges and
 //                gather Vd of the neighbours, from a copy of the network's
 //                Vd staged in LDS when the tile's edges outnumber the cells,
@@ -62,8 +66,12 @@ struct InstDesc {
     int32_t vd_lds;        // CSR: stage the network's Vd in LDS (n <= kChunk)
     int32_t col16;         // CSR: columns stored as uint16
     int32_t bitmap;        // CSR with uniform g: gap from the coupling bitmap
-    int32_t pad0[2];
+    int32_t blocked;       // CSR: Vd staged in LDS one column block at a time
+    int32_t nblk;          // blocked: number of column blocks
+    int32_t wide;          // bitmap: run in the 1024-thread launch group
+    int32_t pad1;
     int64_t bits_off;      // bitmap: offset of the network's first word
+    int64_t blk_off;       // blocked: offset of the network's [n][nblk] block starts
     CellParams p;
 };
 
@@ -90,18 +98,22 @@ struct StepArgs {
     const int32_t* col;        // CSR columns (local cell index)
     const uint16_t* col16;     // CSR columns, 16-bit form
     const uint32_t* bits;      // coupling bitmaps
+    const int32_t* blk;        // blocked CSR: per row, first edge of each column block
+    int32_t blk_cols;          // blocked CSR: cells per column block
     const float* w;            // DENSE matrices and CSR weights
     const float* i_stream;     // dense input streams
     int32_t* spike_count;      // [cells]
     float* spike_times;        // [cells][spike_cap]
     int32_t* flags;            // [0]: non-finite state seen
     float* igap_out;           // gap-only mode: [cells]
+    unsigned int* list_reset;  // when set, workgroup 0 zeroes it (the surrogate's plain-cell list)
     const int64_t* d_step;     // when set, step = *d_step + step offset
     int64_t stride;            // state row stride (floats)
     float dt;
     int32_t spike_cap;
     int32_t gap_only;
     int32_t dry;               // timing runs: write the next state only
+    int32_t pad1;
 };
 
 __device__ __forceinline__ float wave_sum_xor(float v, int width) {
@@ -263,10 +275,106 @@ __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& 
     }
 }
 
+constexpr int kBlkPasses = 4;       // row passes per tile kept in registers
+
+template <int BLOCK, bool C16, bool HASW>
+__device__ __forceinline__ void gap_csr_blocked(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                                const float* __restrict__ vd, float* s_vd, float* s_part,
+                                                float* s_ig) {
+    const int L = d.lanes_per_row;
+    const int groups = BLOCK / L;
+    const int grp = threadIdx.x / L;
+    const int lig = threadIdx.x % L;
+    const int C = a.blk_cols;
+    const int64_t* rp = a.row_ptr + d.rp_off;
+    const int32_t* c32 = a.col + d.w_off;
+    const uint16_t* c16 = a.col16 + d.w_off;
+    const float* wv = a.w + d.w_off;
+    const int32_t* bo = a.blk + d.blk_off;
+    float acc[kBlkPasses], vi[kBlkPasses];
+#pragma unroll
+    for (int q = 0; q < kBlkPasses; ++q) {
+        acc[q] = 0.0f;
+        const int r = t.row0 + q * groups + grp;
+        vi[q] = r < t.row1 ? vd[r] : 0.0f;
+    }
+    for (int b = 0; b < d.nblk; ++b) {
+        const int j0 = b * C;
+        const int jn = min(C, d.n - j0);
+        __syncthreads();
+        for (int k = threadIdx.x; k < jn; k += BLOCK) s_vd[k] = vd[j0 + k];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBlkPasses; ++q) {
+            const int r = t.row0 + q * groups + grp;
+            if (r >= t.row1) continue;
+            const int64_t rs = rp[r];
+            const int64_t e = b + 1 < d.nblk ? rs + bo[(int64_t)r * d.nblk + b + 1] : rp[r + 1];
+            int64_t k = rs + bo[(int64_t)r * d.nblk + b] + lig;
+            float a0 = 0.0f, a1 = 0.0f;
+            for (; k + (kBatch - 1) * L < e; k += kBatch * L) {
+                int j[kBatch];
+                float w[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    j[u] = (C16 ? (int)c16[k + u * L] : c32[k + u * L]) - j0;
+                    w[u] = HASW ? wv[k + u * L] : 1.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; u += 2) {
+                    const float d0 = vi[q] - s_vd[j[u]], d1 = vi[q] - s_vd[j[u + 1]];
+                    a0 = fmaf(w[u], d0 * gap_factor(d0), a0);
+                    a1 = fmaf(w[u + 1], d1 * gap_factor(d1), a1);
+                }
+            }
+            for (; k < e; k += L) {
+                const int jj = (C16 ? (int)c16[k] : c32[k]) - j0;
+                const float d0 = vi[q] - s_vd[jj];
+                a0 = fmaf(HASW ? wv[k] : 1.0f, d0 * gap_factor(d0), a0);
+            }
+            acc[q] += a0 + a1;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kBlkPasses; ++q) {
+        const int r = t.row0 + q * groups + grp;
+        float v = acc[q];
+        if (L <= 64) {
+            v = wave_sum_xor(v, L);
+            if (r < t.row1 && lig == 0) s_ig[r - t.row0] = HASW ? v : d.g * v;
+        } else {
+            v = wave_sum_xor(v, 64);
+            const int wave = threadIdx.x >> 6;
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) s_part[wave] = v;
+            __syncthreads();
+            if (lig == 0 && r < t.row1) {
+                float tot = 0.0f;
+                for (int w = 0; w < L / 64; ++w) tot += s_part[wave + w];
+                s_ig[r - t.row0] = HASW ? tot : d.g * tot;
+            }
+        }
+    }
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
                                         const float* __restrict__ vd, float* s_vd, float* s_part,
                                         float* s_ig) {
+    // column-blocked tiles run in 1024-thread workgroups only (the runtime
+    // places them there); elsewhere the same rows take the gathers below
+    if constexpr (BLOCK == 1024) {
+        if (d.blocked) {
+            if (d.col16) {
+                if (d.has_w) gap_csr_blocked<BLOCK, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
+                else gap_csr_blocked<BLOCK, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            } else {
+                if (d.has_w) gap_csr_blocked<BLOCK, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
+                else gap_csr_blocked<BLOCK, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            }
+            return;
+        }
+    }
     if (d.vd_lds) {
         for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k];
         __syncthreads();
@@ -383,6 +491,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
     // (min(n, kChunk) + 8 per wave) or the largest LDS-staged CSR network
     extern __shared__ float4 s_v4[];
 
+    if (a.list_reset && blockIdx.x == 0 && threadIdx.x == 0) *a.list_reset = 0u;
     const Tile t = a.tiles[blockIdx.x];
     const InstDesc& d = a.inst[t.inst];
     const int64_t step = (a.d_step ? *a.d_step : step_arg) + step_off;

@@ -39,12 +39,15 @@ void ensure_surrogate_buffers(infoli_ctx* c) {
     s.params = c->alloc<float>(kNumParams);
     s.m = c->alloc<float>(kNumParams);
     s.v = c->alloc<float>(kNumParams);
-    s.grad = c->alloc<float>(kNumParams);
+    s.grad = c->alloc<float>((size_t)kNumParams * kGradSplits);   // split-K partials
     s.wb = c->alloc<uint16_t>(kNumParams);
     s.hold = c->alloc<int32_t>(c->stride);
-    s.counters = c->alloc<uint32_t>(4);
+    s.counters = c->alloc<unsigned long long>(4);
     HIPX(hipMemset(s.hold, 0, sizeof(int32_t) * c->stride));
-    HIPX(hipMemset(s.counters, 0, sizeof(uint32_t) * 4));
+    HIPX(hipMemset(s.counters, 0, sizeof(unsigned long long) * 4));
+    s.list = c->alloc<PlainEntry>(c->stride);
+    s.list_count = c->alloc<unsigned int>(1);
+    HIPX(hipMemset(s.list_count, 0, sizeof(unsigned int)));
 }
 
 void check_params(const float* p, int64_t n) {
@@ -78,11 +81,15 @@ SurrArgs surr_args(infoli_ctx* c, const infoli_drift_cfg& dc, int64_t macro_inde
     a.hold = c->surr.hold;
     a.counters = c->surr.counters;
     a.theta_mv = dc.theta_mv;
-    a.vs_spiking = dc.vs_spiking;
+    a.v_max = dc.v_max;
+    a.ca_max = dc.ca_max;
+    a.z_max = dc.z_max;
     a.sample_every = dc.sample_every;
     a.hold_steps = dc.hold_steps;
     a.mode = dc.mode;
     a.macro_index = macro_index;
+    a.list = static_cast<PlainEntry*>(c->surr.list);
+    a.list_count = c->surr.list_count;
     return a;
 }
 
@@ -91,6 +98,7 @@ SurrArgs surr_args(infoli_ctx* c, const infoli_drift_cfg& dc, int64_t macro_inde
 void launch_macro(infoli_ctx* c, hipStream_t st, const infoli_drift_cfg& dc, int from, int64_t step0) {
     StepArgs g = make_args(c, false);
     g.gap_only = 1;
+    g.list_reset = c->surr.list_count;
     launch_groups(c, st, g, from, step0, 0, false);
     const StepArgs a = make_args(c, false);
     const int64_t cells = c->total_cells;
@@ -100,9 +108,13 @@ void launch_macro(infoli_ctx* c, hipStream_t st, const infoli_drift_cfg& dc, int
         return;
     }
     const SurrArgs s = surr_args(c, dc, step0 / kMacro);
-    const unsigned blocks = (unsigned)std::min<int64_t>((cells + 63) / 64, 256);
+    // two workgroups (eight waves) per compute unit: LDS holds two weight copies
+    const unsigned blocks = (unsigned)std::min<int64_t>((cells + 63) / 64, 2 * (int64_t)c->n_cu);
     hipLaunchKernelGGL(k_surrogate_step, dim3(blocks), dim3(256), 0, st, a, s, c->state[from],
                        c->state[from ^ 1], step0, cells);
+    const unsigned lblocks = (unsigned)std::min<int64_t>((cells + 255) / 256, 512);
+    hipLaunchKernelGGL(k_plain_list, dim3(lblocks), dim3(256), 0, st, a, s, c->state[from], c->state[from ^ 1],
+                       step0);
 }
 
 }  // namespace
@@ -122,7 +134,8 @@ infoli_status infoli_default_train_cfg(infoli_train_cfg* cfg) {
     cfg->steps = 20000;
     cfg->lr = 1e-3f;
     cfg->lr_min = 1e-5f;
-    cfg->vs_max = -40.0f;
+    cfg->v_max = -40.0f;
+    cfg->ca_max = 20.0f;
     cfg->beta1 = 0.9f;
     cfg->beta2 = 0.999f;
     cfg->eps = 1e-8f;
@@ -143,11 +156,14 @@ infoli_status infoli_default_drift_cfg(infoli_drift_cfg* cfg) {
         g_thread_error = "cfg is NULL";
         return INFOLI_E_INVALID_ARG;
     }
+    std::memset(cfg, 0, sizeof(*cfg));
     cfg->theta_mv = 0.5f;
-    cfg->vs_spiking = -40.0f;
+    cfg->v_max = -40.0f;
+    cfg->ca_max = 20.0f;
     cfg->sample_every = 64;
     cfg->hold_steps = 50;
     cfg->mode = INFOLI_SURROGATE_MLP;
+    cfg->z_max = 8.0f;
     return INFOLI_OK;
 }
 
@@ -163,8 +179,9 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
         if (cfg->batch < 16 || cfg->batch % 64 != 0 || cfg->batch > (1 << 20))
             fail(INFOLI_E_INVALID_ARG, "batch must be a positive multiple of 64 up to 2^20");
         if (cfg->steps < 0 || cfg->n_trajectories < 1 || cfg->n_transitions < cfg->batch ||
-            cfg->burn_in < 0 || cfg->pulse_len < 0 || !(cfg->lr > 0.0f) || !(cfg->lr_min >= 0.0f) ||
-            !(cfg->lr_min <= cfg->lr) || !std::isfinite(cfg->vs_max) ||
+            cfg->burn_in < 0 || cfg->pulse_len < 0 || !(cfg->lr > 0.0f) ||
+            !(cfg->lr_min >= 0.0f) || !(cfg->lr_min <= cfg->lr) ||
+            !(cfg->v_max >= -50.0f && cfg->v_max < 1000.0f) || std::isnan(cfg->ca_max) ||
             !(cfg->gap_rho >= 0.0f && cfg->gap_rho < 1.0f))
             fail(INFOLI_E_INVALID_ARG, "bad training configuration");
         check_params(cfg->init_params, kNumParams);
@@ -189,6 +206,7 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
         std::memset(&g, 0, sizeof(g));
         g.p = ctx->inst[0].p;
         rest_state_host(reinterpret_cast<const float*>(&ctx->inst[0].p), -60.0f, g.rest);
+        if (!(cfg->ca_max > g.rest[SV_CA])) fail(INFOLI_E_INVALID_ARG, "ca_max must exceed the rest [Ca]");
         g.dt = ctx->dt;
         g.bias_sd = cfg->bias_sd;
         g.gap_sd = cfg->gap_sd;
@@ -197,7 +215,8 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
         g.pulse_lo = cfg->pulse_lo;
         g.pulse_hi = cfg->pulse_hi;
         g.pulse_len = cfg->pulse_len;
-        g.vs_max = cfg->vs_max;
+        g.v_max = cfg->v_max;
+        g.ca_max = cfg->ca_max;
         g.burn_in = cfg->burn_in;
         g.per_traj = (int32_t)per_traj;
         g.n_traj = cfg->n_trajectories;
@@ -248,14 +267,16 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
         for (int t = 1; t <= cfg->steps; ++t) {
             hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(B / 64), dim3(256), 0, st, s.params, s.wb, xd, td, n_data, B,
                                cfg->seed | 1ull, (uint64_t)t, tb);
-            hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles), dim3(64), 0, st, tb, B, s.grad, dloss + (t - 1));
+            hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles * kGradSplits), dim3(64), 0, st, tb, B, s.grad,
+                               dloss + (t - 1));
             c1 *= cfg->beta1;
             c2 *= cfg->beta2;
             // cosine decay of the learning rate from lr to lr_min
             const double frac = cfg->steps > 1 ? (double)(t - 1) / (double)(cfg->steps - 1) : 0.0;
             const float lr_t = (float)(cfg->lr_min + 0.5 * (cfg->lr - cfg->lr_min) * (1.0 + std::cos(M_PI * frac)));
             hipLaunchKernelGGL(k_adam, dim3((kNumParams + 255) / 256), dim3(256), 0, st, s.params, s.m, s.v, s.grad,
-                               s.wb, lr_t, cfg->beta1, cfg->beta2, cfg->eps, (float)(1.0 - c1), (float)(1.0 - c2));
+                               kGradSplits, s.wb, lr_t, cfg->beta1, cfg->beta2, cfg->eps, (float)(1.0 - c1),
+                               (float)(1.0 - c2));
         }
         HIPX(hipGetLastError());
         HIPX(hipEventRecord(e2, st));
@@ -322,13 +343,14 @@ infoli_status infoli_step_surrogate(infoli_ctx* ctx, int64_t n_macro, const info
         if (n_macro < 0) fail(INFOLI_E_INVALID_ARG, "n_macro must be >= 0");
         if (dc.mode != INFOLI_SURROGATE_MLP && dc.mode != INFOLI_SURROGATE_PLAIN_HOLD)
             fail(INFOLI_E_INVALID_ARG, "unknown surrogate mode %d", dc.mode);
-        if (dc.sample_every < 0 || dc.hold_steps < 0 || !(dc.theta_mv >= 0.0f) || !std::isfinite(dc.vs_spiking))
+        if (dc.sample_every < 0 || dc.hold_steps < 0 || !(dc.theta_mv >= 0.0f) || std::isnan(dc.v_max) ||
+            std::isnan(dc.ca_max) || !(dc.z_max >= 0.0f))
             fail(INFOLI_E_INVALID_ARG, "bad drift configuration");
         if (ctx->n_inst != 1) fail(INFOLI_E_UNSUPPORTED, "the surrogate runs on single-network contexts");
         ensure_surrogate_buffers(ctx);
         if (dc.mode == INFOLI_SURROGATE_MLP && !ctx->surr.ready)
             fail(INFOLI_E_STATE, "no surrogate trained or set");
-        uint32_t before[4];
+        unsigned long long before[4];
         HIPX(hipStreamSynchronize(ctx->stream));
         HIPX(hipMemcpy(before, ctx->surr.counters, sizeof(before), hipMemcpyDeviceToHost));
         HIPX(hipEventRecord(ctx->ev0, ctx->stream));
@@ -342,12 +364,13 @@ infoli_status infoli_step_surrogate(infoli_ctx* ctx, int64_t n_macro, const info
         ctx->timed = true;
         if (rep) {
             HIPX(hipEventSynchronize(ctx->ev1));
-            uint32_t after[4];
+            unsigned long long after[4];
             HIPX(hipMemcpy(after, ctx->surr.counters, sizeof(after), hipMemcpyDeviceToHost));
             std::memset(rep, 0, sizeof(*rep));
             rep->plain_cell_macro_steps = (int64_t)(after[0] - before[0]);
             rep->checked = (int64_t)(after[1] - before[1]);
             rep->flagged = (int64_t)(after[2] - before[2]);
+            rep->guarded = (int64_t)(after[3] - before[3]);
             HIPX(hipEventElapsedTime(&rep->ms, ctx->ev0, ctx->ev1));
         }
     });
@@ -387,6 +410,7 @@ infoli_status infoli_mlp_loss_grad(const float* params, const float* x, const fl
         float* dx = dev_alloc<float>(tmp.owned, (size_t)batch * 16);
         float* dt = dev_alloc<float>(tmp.owned, (size_t)batch * 16);
         float* dg = dev_alloc<float>(tmp.owned, kNumParams);
+        float* dpart = dev_alloc<float>(tmp.owned, (size_t)kNumParams * kGradSplits);
         float* dl = dev_alloc<float>(tmp.owned, 1);
         TrainBufs tb;
         tb.xT = dev_alloc<uint16_t>(tmp.owned, (size_t)16 * batch);
@@ -402,7 +426,8 @@ infoli_status infoli_mlp_loss_grad(const float* params, const float* x, const fl
         hipLaunchKernelGGL(k_mlp_to_bf16, dim3((kNumParams + 255) / 256), dim3(256), 0, 0, dp, dw);
         hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((batch + 63) / 64), dim3(256), 0, 0, dp, dw, dx, dt, (int64_t)batch,
                            batch, 0ull, 0ull, tb);
-        hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles), dim3(64), 0, 0, tb, batch, dg, dl);
+        hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles * kGradSplits), dim3(64), 0, 0, tb, batch, dpart, dl);
+        hipLaunchKernelGGL(k_grad_reduce, dim3((kNumParams + 255) / 256), dim3(256), 0, 0, dpart, kGradSplits, dg);
         HIPX(hipGetLastError());
         HIPX(hipDeviceSynchronize());
         HIPX(hipMemcpy(grad, dg, sizeof(float) * kNumParams, hipMemcpyDeviceToHost));
@@ -429,7 +454,7 @@ infoli_status infoli_mlp_adam_step(float* params, float* m, float* v, const floa
         HIPX(hipMemcpy(dv, v, sizeof(float) * kNumParams, hipMemcpyHostToDevice));
         HIPX(hipMemcpy(dg, grad, sizeof(float) * kNumParams, hipMemcpyHostToDevice));
         const double c1 = 1.0 - std::pow((double)beta1, (double)t), c2 = 1.0 - std::pow((double)beta2, (double)t);
-        hipLaunchKernelGGL(k_adam, dim3((kNumParams + 255) / 256), dim3(256), 0, 0, dp, dm, dv, dg, dw, lr, beta1,
+        hipLaunchKernelGGL(k_adam, dim3((kNumParams + 255) / 256), dim3(256), 0, 0, dp, dm, dv, dg, 1, dw, lr, beta1,
                            beta2, eps, (float)c1, (float)c2);
         HIPX(hipGetLastError());
         HIPX(hipDeviceSynchronize());

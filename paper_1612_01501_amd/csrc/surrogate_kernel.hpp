@@ -3,9 +3,10 @@
 // A macro step holds each cell's gap current (computed exactly, in fp32, from
 // the Vd at the macro step's start) and evoked input for its four steps; the
 // MLP maps the normalised [state, I_gap, I_app] to the normalised state
-// increment. The plain method stays the judge and the fallback: cells in the
-// spiking regime (Vs above a threshold), cells flagged by an earlier drift
-// check, and a rotating sample of cells re-checked this macro step are
+// increment. The plain method stays the reference and the fallback: cells
+// outside the MLP's regime (a voltage above v_max or [Ca] above ca_max), cells
+// whose MLP candidate leaves it, cells flagged by an earlier drift check, and
+// a rotating sample of cells re-checked this macro step are listed and
 // advanced by four plain forward-Euler steps; a checked cell whose MLP result
 // differs from the plain one by more than theta in any voltage is flagged for
 // a number of macro steps. Every cell advanced by the plain method takes the
@@ -33,14 +34,30 @@ struct SurrArgs {
     NormStats norm;
     const float* igap;          // [cells] held gap currents
     int32_t* hold;              // [cells] macro steps left on the plain method
-    uint32_t* counters;         // [0] cells on plain, [1] checked, [2] newly flagged
+    unsigned long long* counters;   // [0] cells on plain, [1] checked, [2] flagged, [3] guarded
     float theta_mv;             // drift threshold on Vd, Vs, Va
-    float vs_spiking;           // Vs above this: plain method
+    float v_max;                // regime served by the MLP: every voltage <= v_max
+    float ca_max;               //   and [Ca] <= ca_max
+    float z_max;                // normalised inputs beyond +-z_max: plain method (0: no bound)
     int32_t sample_every;       // check cells with (cell + macro) % sample_every == 0; 0 = never
     int32_t hold_steps;         // macro steps a flagged cell stays on the plain method
     int32_t mode;               // 0 surrogate, 1 plain for every cell (gap held 4 steps)
     int64_t macro_index;
+    struct PlainEntry* list;    // cells for the plain method this macro step
+    unsigned int* list_count;   // zeroed by the macro step's gap launch
 };
+
+// A cell handed to the plain method, with the MLP's candidate voltages (used
+// when the cell is checked).
+struct PlainEntry {
+    int32_t cell;
+    float vd, vs, va;
+};
+
+// Largest |V| (mV) accepted from the MLP; beyond it the candidate is rejected.
+constexpr float kMlpVoltageBound = 150.0f;
+// Lanes l, l+16, l+32, l+48 of a wave hold the four feature groups of one cell.
+constexpr unsigned long long kCellLanes = 0x0001000100010001ull;
 
 constexpr int kMacro = 4;
 
@@ -48,7 +65,7 @@ constexpr int kMacro = 4;
 static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrArgs s, const float* __restrict__ xin,
                                                         float* __restrict__ xout, int64_t step0,
                                                         int64_t n_cells_total) {
-    __shared__ uint16_t s_w[kMlpLdsElems];
+    __shared__ __align__(16) uint16_t s_w[kMlpLdsElems];
     const MlpSmem sm = mlp_smem(s_w);
     if (s.mode == 0) {
         load_weights_lds(s.wb, sm);
@@ -67,12 +84,15 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
         const float ig = s.igap[c];
         const float ia0 = evoked_input(a, d, step0, li, c);
 
-        // decide plain vs MLP (lanes of group 0 look at the cell's soma voltage)
+        // reasons known before the MLP runs (the same on the cell's four lanes)
+        const float vd0 = xin[SV_VD * a.stride + c];
         const float vs0 = xin[SV_VS * a.stride + c];
-        int hold = s.hold[c];
+        const float va0 = xin[SV_VA * a.stride + c];
+        const float ca0 = xin[SV_CA * a.stride + c];
+        const bool in_regime = fmaxf(vd0, fmaxf(vs0, va0)) <= s.v_max && ca0 <= s.ca_max;
+        const int hold = s.hold[c];
         const bool check = s.sample_every > 0 &&
                            ((c + s.macro_index) % s.sample_every) == 0;
-        const bool plain = s.mode == 1 || hold > 0 || vs0 > s.vs_spiking || check;
 
         // MLP on every lane (the matrix cores need the whole wave)
         f32x4 y = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -82,6 +102,7 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
             const int v = 4 * g + e;
             xg[e] = v < NSV ? xin[v * a.stride + c] : 0.0f;
         }
+        bool far = false;       // a normalised input of this lane's group outside the bound
         if (s.mode == 0) {
             f32x4 xnv;
 #pragma unroll
@@ -89,9 +110,12 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
                 const int v = 4 * g + e;
                 const float raw = v < NSV ? xg[e] : (v == 14 ? ig : ia0);
                 xnv[e] = (raw - s.norm.in_mean[v]) * s.norm.in_rstd[v];
+                far = far || !(fabsf(xnv[e]) <= s.z_max);
             }
+            if (!(s.z_max > 0.0f)) far = false;
             y = mlp_forward(sm, s.params, pack_bf16(xnv), nullptr, nullptr);
         }
+        const bool cell_far = ((__ballot(far) >> (l & 15)) & kCellLanes) != 0;
         // MLP candidate: x + denormalised increment (lane holds 4 variables)
         f32x4 xm;
 #pragma unroll
@@ -104,6 +128,22 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
         const float mvs = __shfl(xm[1], (l & 15) + 16, 64);      // v = 5  (g 1, e 1)
         const float mva = __shfl(xm[3], (l & 15) + 32, 64);      // v = 11 (g 2, e 3)
 
+        // Guards, tested every macro step: a cell outside the regime the MLP
+        // was trained on, with inputs far from the training data, or whose
+        // MLP candidate leaves the regime (or is unusable) takes the plain
+        // method for this macro step.
+        const bool cand_bad = !(fabsf(mvd) <= kMlpVoltageBound && fabsf(mvs) <= kMlpVoltageBound &&
+                                fabsf(mva) <= kMlpVoltageBound) ||
+                              fmaxf(mvd, fmaxf(mvs, mva)) > s.v_max;
+        const bool guard = s.mode == 0 && (!in_regime || cell_far || cand_bad);
+        const bool plain = s.mode == 1 || hold > 0 || check || guard;
+
+        // counters, one atomic per wave (group-0 lanes stand for their cells)
+        const bool lead = g == 0 && live;
+        const unsigned long long n_plain = __popcll(__ballot(lead && plain));
+        const unsigned long long n_check = __popcll(__ballot(lead && s.mode == 0 && check));
+        const unsigned long long n_guard = __popcll(__ballot(lead && guard));
+
         if (!plain) {
             if (live)
 #pragma unroll
@@ -113,7 +153,6 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
                 }
             // spike of an MLP cell: Va crossing 0 mV within the macro step
             if (g == 0 && live) {
-                const float va0 = xin[SV_VA * a.stride + c];
                 if (va0 < 0.0f && mva >= 0.0f) {
                     const int cnt = a.spike_count[c];
                     if (a.spike_cap > 0) {
@@ -124,8 +163,42 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
                     a.spike_count[c] = cnt + 1;
                 }
             }
-        } else if (g == 0 && live) {
-            // plain method: four forward-Euler steps with the gap current held
+        }
+        // cells for the plain method: appended to the list (one atomic per wave)
+        const unsigned long long pmask = __ballot(lead && plain);
+        if (pmask) {
+            unsigned int base = 0;
+            if (l == 0) base = atomicAdd(s.list_count, (unsigned int)__popcll(pmask));
+            base = __shfl(base, 0, 64);
+            if (lead && plain) {
+                const unsigned int pos = base + (unsigned int)__popcll(pmask & ((1ull << l) - 1ull));
+                s.list[pos] = PlainEntry{(int32_t)c, mvd, mvs, mva};
+            }
+        }
+        if (l == 0) {
+            if (n_plain) atomicAdd(&s.counters[0], n_plain);
+            if (n_check) atomicAdd(&s.counters[1], n_check);
+            if (n_guard) atomicAdd(&s.counters[3], n_guard);
+        }
+    }
+}
+
+// The listed cells: four plain forward-Euler steps with the macro step's gap
+// current held, spike detection, and for checked cells the drift test
+// against the MLP candidate (past theta: hold_steps macro steps of plain
+// method). One thread per listed cell.
+static __global__ __launch_bounds__(256) void k_plain_list(StepArgs a, SurrArgs s, const float* __restrict__ xin,
+                                                           float* __restrict__ xout, int64_t step0) {
+    const unsigned int count = *s.list_count;
+    const InstDesc& d = a.inst[0];
+    for (unsigned int b = blockIdx.x * blockDim.x; b < count; b += gridDim.x * blockDim.x) {
+        const unsigned int i = b + threadIdx.x;
+        bool flagged = false;
+        if (i < count) {
+            const PlainEntry e = s.list[i];
+            const int64_t c = e.cell;
+            const int li = (int)(c - d.cell_off);
+            const float ig = s.igap[c];
             float x[NSV], yv[NSV];
 #pragma unroll
             for (int v = 0; v < NSV; ++v) x[v] = xin[v * a.stride + c];
@@ -151,18 +224,20 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
                 chk += x[v];
             }
             if (!isfinite(chk)) atomicOr(a.flags, 1);
+            const int hold = s.hold[c];
             int new_hold = hold > 0 ? hold - 1 : 0;
-            if (s.mode == 0 && check) {
-                atomicAdd(&s.counters[1], 1u);
-                const float dev = fmaxf(fabsf(mvd - x[SV_VD]), fmaxf(fabsf(mvs - x[SV_VS]), fabsf(mva - x[SV_VA])));
+            const bool check = s.sample_every > 0 && ((c + s.macro_index) % s.sample_every) == 0;
+            if (check) {
+                const float dev = fmaxf(fabsf(e.vd - x[SV_VD]), fmaxf(fabsf(e.vs - x[SV_VS]), fabsf(e.va - x[SV_VA])));
                 if (!(dev <= s.theta_mv)) {
                     new_hold = s.hold_steps;
-                    atomicAdd(&s.counters[2], 1u);
+                    flagged = true;
                 }
             }
             if (new_hold != hold) s.hold[c] = new_hold;
-            atomicAdd(&s.counters[0], 1u);
         }
+        const unsigned long long fm = __ballot(flagged);
+        if ((threadIdx.x & 63) == 0 && fm) atomicAdd(&s.counters[2], (unsigned long long)__popcll(fm));
     }
 }
 
@@ -207,9 +282,11 @@ static __global__ __launch_bounds__(256) void k_hold4(StepArgs a, const float* _
 // ---------------------------------------------------------------- training data
 // Independent cells driven by random currents, advanced by the plain method:
 // each macro step records (state, I_gap, I_app) and the state increment over
-// four steps with both currents held. A trajectory whose soma voltage exceeds
-// vs_max restarts from the (jittered) rest state, so every recorded
-// transition starts in the subthreshold regime the surrogate serves. Per trajectory: a constant bias
+// four steps with both currents held. Only transitions the surrogate would be
+// asked to make are recorded: those starting in its regime (every voltage
+// <= v_max, [Ca] <= ca_max); the trajectory itself runs on through spikes. A
+// trajectory that records nothing for kMaxIdle macro steps, or leaves the
+// model's range, restarts from the (jittered) rest state. Per trajectory: a constant bias
 // N(0, bias_sd); a gap current following an AR(1) process with stationary
 // standard deviation gap_sd and lag-one correlation gap_rho per macro step;
 // pulses of amplitude U[pulse_lo, pulse_hi] lasting pulse_len macro steps,
@@ -222,7 +299,7 @@ struct DataGenArgs {
     float rest[NSV];
     float dt;
     float bias_sd, gap_sd, gap_rho, pulse_p, pulse_lo, pulse_hi;
-    float vs_max;             // restart when the soma voltage exceeds this
+    float v_max, ca_max;      // regime: transitions starting outside are not recorded
     int32_t pulse_len;
     int32_t burn_in;          // largest number of unrecorded macro steps
     int32_t per_traj;         // recorded macro steps per trajectory
@@ -242,15 +319,25 @@ __device__ __forceinline__ float normal01(uint64_t seed, uint64_t traj, uint64_t
     return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
 }
 
+constexpr int kMaxIdle = 4000;
+
+__device__ __forceinline__ void rest_jittered(const DataGenArgs& g, uint64_t t, uint64_t m, float* x) {
+#pragma unroll
+    for (int v = 0; v < NSV; ++v) x[v] = g.rest[v];
+    x[SV_VD] += 2.0f * u01(g.seed, t, m, 10) - 1.0f;
+    x[SV_VS] += 2.0f * u01(g.seed, t, m, 11) - 1.0f;
+    x[SV_VA] += 2.0f * u01(g.seed, t, m, 12) - 1.0f;
+}
+
+// Termination: after the burn-in every macro step either records or counts
+// towards kMaxIdle; a restart puts the voltages at -60 +- 1 mV and [Ca] at
+// rest, inside the regime (the host requires v_max >= -50 mV and ca_max above
+// the rest value), so the next step records.
 static __global__ void k_surrogate_data(DataGenArgs g) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= g.n_traj) return;
     float x[NSV], y[NSV];
-#pragma unroll
-    for (int v = 0; v < NSV; ++v) x[v] = g.rest[v];
-    x[SV_VD] += 2.0f * u01(g.seed, t, 0, 10) - 1.0f;
-    x[SV_VS] += 2.0f * u01(g.seed, t, 0, 11) - 1.0f;
-    x[SV_VA] += 2.0f * u01(g.seed, t, 0, 12) - 1.0f;
+    rest_jittered(g, t, 0, x);
     const float bias = g.bias_sd * normal01(g.seed, t, 0, 20);
     float gap = g.gap_sd * normal01(g.seed, t, 0, 30);
     int pulse_left = 0;
@@ -259,28 +346,25 @@ static __global__ void k_surrogate_data(DataGenArgs g) {
     // burn-in of this trajectory: uniform in [0, burn_in] macro steps, so the
     // recorded states cover the slow variables' whole excursion
     const int burn = (int)(u01(g.seed, t, 0, 60) * (float)(g.burn_in + 1));
-    for (int m = 1; m <= burn + g.per_traj; ++m) {
-        if (x[SV_VS] > g.vs_max) {
-            // spiking regime: the surrogate leaves it to the plain method
-#pragma unroll
-            for (int v = 0; v < NSV; ++v) x[v] = g.rest[v];
-            x[SV_VD] += 2.0f * u01(g.seed, t, m, 13) - 1.0f;
-            x[SV_VS] += 2.0f * u01(g.seed, t, m, 14) - 1.0f;
-            x[SV_VA] += 2.0f * u01(g.seed, t, m, 15) - 1.0f;
+    int idle = 0, rec = 0;
+    for (int64_t m = 1; rec < g.per_traj; ++m) {
+        if (idle > kMaxIdle) {
+            rest_jittered(g, t, m, x);
             gap = 0.0f;
             pulse_left = 0;
+            idle = 0;
         }
         gap = g.gap_rho * gap + innov * normal01(g.seed, t, m, 40);
         if (pulse_left == 0 && u01(g.seed, t, m, 50) < g.pulse_p) {
             pulse_left = g.pulse_len;
             pulse_amp = g.pulse_lo + (g.pulse_hi - g.pulse_lo) * u01(g.seed, t, m, 51);
         }
-        const float iapp = bias + (pulse_left > 0 ? pulse_amp : 0.0f);
+        float iapp = bias + (pulse_left > 0 ? pulse_amp : 0.0f);
         if (pulse_left > 0) --pulse_left;
         float x0[NSV];
-        float used_iapp = iapp;
 #pragma unroll
         for (int v = 0; v < NSV; ++v) x0[v] = x[v];
+        bool served = fmaxf(x0[SV_VD], fmaxf(x0[SV_VS], x0[SV_VA])) <= g.v_max && x0[SV_CA] <= g.ca_max;
         for (int k = 0; k < kMacro; ++k) {
             cell_step(g.p, x, gap, iapp, g.dt, y);
 #pragma unroll
@@ -296,27 +380,33 @@ static __global__ void k_surrogate_data(DataGenArgs g) {
             for (int v = 0; v < NSV; ++v) x[v] = x0[v] = g.rest[v];
             gap = 0.0f;
             pulse_left = 0;
-            used_iapp = bias;
+            iapp = bias;
+            served = true;
             for (int k = 0; k < kMacro; ++k) {
                 cell_step(g.p, x, gap, bias, g.dt, y);
 #pragma unroll
                 for (int v = 0; v < NSV; ++v) x[v] = y[v];
             }
         }
-        if (m > burn) {
-            const int64_t r = (int64_t)(m - burn - 1) * g.n_traj + t;
-            float* xr = g.x_raw + r * 16;
-            float* dr = g.d_raw + r * 16;
-#pragma unroll
-            for (int v = 0; v < NSV; ++v) {
-                xr[v] = x0[v];
-                dr[v] = x[v] - x0[v];
-            }
-            xr[14] = gap;
-            xr[15] = used_iapp;
-            dr[14] = 0.0f;
-            dr[15] = 0.0f;
+        if (m <= burn) continue;
+        if (!served) {
+            ++idle;
+            continue;
         }
+        idle = 0;
+        const int64_t r = (int64_t)rec * g.n_traj + t;
+        ++rec;
+        float* xr = g.x_raw + r * 16;
+        float* dr = g.d_raw + r * 16;
+#pragma unroll
+        for (int v = 0; v < NSV; ++v) {
+            xr[v] = x0[v];
+            dr[v] = x[v] - x0[v];
+        }
+        xr[14] = gap;
+        xr[15] = iapp;
+        dr[14] = 0.0f;
+        dr[15] = 0.0f;
     }
 }
 

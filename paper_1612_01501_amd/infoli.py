@@ -80,17 +80,19 @@ class Info(ctypes.Structure):
                 ("step_mode", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("tuned", ctypes.c_int32),
-                ("tune_cached", ctypes.c_int32)]
+                ("tune_cached", ctypes.c_int32), ("n_tiles_wide", ctypes.c_int32),
+                ("n_bitmap", ctypes.c_int32), ("n_blocked", ctypes.c_int32)]
 
 
 class TrainCfg(ctypes.Structure):
     _fields_ = [("n_transitions", ctypes.c_int64), ("n_trajectories", ctypes.c_int32),
                 ("burn_in", ctypes.c_int32), ("batch", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float), ("lr_min", ctypes.c_float), ("vs_max", ctypes.c_float),
+                ("eps", ctypes.c_float), ("lr_min", ctypes.c_float), ("v_max", ctypes.c_float),
                 ("bias_sd", ctypes.c_float), ("gap_sd", ctypes.c_float),
                 ("gap_rho", ctypes.c_float), ("pulse_p", ctypes.c_float), ("pulse_lo", ctypes.c_float),
-                ("pulse_hi", ctypes.c_float), ("pulse_len", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("pulse_hi", ctypes.c_float), ("pulse_len", ctypes.c_int32),
+                ("ca_max", ctypes.c_float), ("seed", ctypes.c_uint64),
                 ("init_params", _PF)]
 
 
@@ -101,14 +103,14 @@ class TrainReport(ctypes.Structure):
 
 
 class DriftCfg(ctypes.Structure):
-    _fields_ = [("theta_mv", ctypes.c_float), ("vs_spiking", ctypes.c_float),
+    _fields_ = [("theta_mv", ctypes.c_float), ("v_max", ctypes.c_float),
                 ("sample_every", ctypes.c_int32), ("hold_steps", ctypes.c_int32),
-                ("mode", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("z_max", ctypes.c_float), ("ca_max", ctypes.c_float)]
 
 
 class DriftReport(ctypes.Structure):
     _fields_ = [("plain_cell_macro_steps", ctypes.c_int64), ("checked", ctypes.c_int64),
-                ("flagged", ctypes.c_int64), ("ms", ctypes.c_float)]
+                ("flagged", ctypes.c_int64), ("guarded", ctypes.c_int64), ("ms", ctypes.c_float)]
 
 
 _lib = None

@@ -131,6 +131,35 @@ def test_forced_fallback(infoli):
     np.testing.assert_array_equal(out[0], out[1])
 
 
+def test_guards_send_cells_to_plain(infoli):
+    """Cells outside the MLP's regime (a voltage above v_max, [Ca] above
+    ca_max) take the plain method: with no sampled checks their macro step
+    equals the held-gap plain step bit for bit, and each is counted as
+    guarded; cells inside the regime and away from it take the MLP."""
+    net = I.config4(seed=4, n=2048, degree=100)
+    x0 = infoli.initial_state(net)
+    odd = {10: (VS, -30.0), 20: (1, 50.0), 30: (VD, -35.0), 40: (VA, -20.0)}
+    for i, (v, val) in odd.items():
+        x0[v, i] = val
+    sim, _, _ = _trained(infoli, net, x0, steps=200, n_transitions=100_000)
+    params, norm = sim.surrogate_get()
+    sim.close()
+    out, reps = {}, {}
+    for mode in ("mlp", "plain_hold"):
+        s = infoli.Simulator(net, init_states=[x0], step_mode="graph")
+        s.surrogate_set(params, norm)
+        reps[mode] = s.step_surrogate(1, mode=mode, sample_every=0)
+        out[mode] = s.read_state(0)
+        s.close()
+    r = reps["mlp"]
+    assert r["checked"] == 0 and r["guarded"] >= len(odd)
+    assert r["plain_cell_macro_steps"] == r["guarded"]
+    for i in odd:
+        np.testing.assert_array_equal(out["mlp"][:, i], out["plain_hold"][:, i])
+    differs = np.any(out["mlp"] != out["plain_hold"], axis=0)
+    assert differs.sum() >= net.n - r["guarded"] - 16     # the rest took the MLP
+
+
 def test_surrogate_set_get_roundtrip_and_errors(infoli):
     net = I.Network(n=100, conn="none")
     sim = infoli.Simulator(net)
@@ -155,7 +184,8 @@ def test_trained_surrogate_accuracy_and_gain(infoli):
     """The 65,536-cell recipe at 8,192 cells (mean degree 1,000, g = 3.84e-3,
     bias, pulse, jitter): after training on device-generated transitions the
     surrogate run stays within 1 mV RMSE of the plain run over 2,000 steps,
-    spikes (if any) within 0.5 ms, and it is faster than the plain method."""
+    spikes (if any) within 0.5 ms, and it is faster than the plain method
+    (drift checks on, default guards)."""
     net = I.config4(seed=1, n=8192)
     x0 = infoli.initial_state(net)
     sim, rep, hist = _trained(infoli, net, x0)        # defaults: 10^6 transitions, 20,000 steps

@@ -171,4 +171,5 @@ def test_default_train_and_drift_cfg():
     c = infoli.default_train_cfg()
     assert c.batch % 64 == 0 and c.n_transitions >= 1_000_000 and c.lr > 0
     d = infoli.default_drift_cfg()
-    assert d.theta_mv == 0.5 and d.sample_every == 64 and d.hold_steps == 50 and d.vs_spiking == -40.0
+    assert d.theta_mv == 0.5 and d.sample_every == 64 and d.hold_steps == 50 and d.v_max == -40.0
+    assert d.z_max == 8.0 and c.v_max == d.v_max and c.ca_max == d.ca_max
