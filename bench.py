@@ -18,6 +18,8 @@ Workloads (--workload):
            steps against the trained MLP surrogate for 2,500 macro steps of
            4 dt (drift check 1/64 cells, theta 0.5 mV), with the two
            ablations (held gap without MLP; MLP without fallback)
+  csr65k   the surr65k network stepped by the plain method only, 2,000
+           steps (the large-CSR, column-blocked gap path)
   batch256 256 independent networks, N_k ~ U{64..2048}, density ~ U{5, 25,
            100 %} (100 % all-to-all, else ER CSR), g_k ~ U[0.01, 0.08],
            pulse amplitude ~ U[2, 10] uA/cm^2, 10,000 steps, one launch per
@@ -75,6 +77,7 @@ WORKLOADS = {
     "uni16k": dict(steps=4000, warmup=100),
     "batch256": dict(steps=10000, warmup=200),
     "surr65k": dict(steps=10000, warmup=100),
+    "csr65k": dict(steps=2000, warmup=100),
 }
 
 
@@ -95,6 +98,10 @@ def build_workload(name):
         desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR), g=3.84e-3 mS/cm^2, "
                 "bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms; "
                 "MLP 16-128-128-16 BF16 on MFMA, 4 dt per macro step")
+    elif name == "csr65k":
+        nets = [I.config4()]
+        desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR), g=3.84e-3 mS/cm^2, "
+                "bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms; plain method")
     elif name == "uni16k":
         nets = [I.config2()]
         desc = "16,384 cells all-to-all, g=0.04*96/N mS/cm^2, +-1 mV jitter, no input, FP32, dt=0.05 ms"

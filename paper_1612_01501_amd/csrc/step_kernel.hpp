@@ -127,6 +127,13 @@ __device__ __forceinline__ float gap_factor(float dv) {
     return fmaf(0.8f, __builtin_amdgcn_exp2f(-(dv * dv) * kL2eOver100), 0.2f);
 }
 
+// The same factor of a voltage difference prescaled by kPreScale (Vd staged
+// in LDS times sqrt(log2(e)/100)): 0.8 * 2^(-dv'^2) + 0.2; the sum over a row
+// is scaled back by kInvPreScale once.
+__device__ __forceinline__ float gap_factor_ps(float dvs) {
+    return fmaf(0.8f, __builtin_amdgcn_exp2f(-(dvs * dvs)), 0.2f);
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d, const Tile& t,
                                             const float* __restrict__ vd, float* s_ig,
@@ -224,11 +231,15 @@ __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& 
     const uint16_t* c16 = a.col16 + d.w_off;
     const float* wv = a.w + d.w_off;
     auto col_at = [&](int64_t k) -> int { return C16 ? (int)c16[k] : c32[k]; };
+    // LDS: staged voltages are prescaled (gap_factor_ps), the row sum is
+    // scaled back at the end
     auto v_at = [&](int j) -> float { return LDS ? s_vd[j] : vd[j]; };
     auto term = [&](float w, float vi, float vj) -> float {
         const float dv = vi - vj;
-        return HASW ? w * (dv * gap_factor(dv)) : dv * gap_factor(dv);
+        const float f = LDS ? gap_factor_ps(dv) : gap_factor(dv);
+        return HASW ? w * (dv * f) : dv * f;
     };
+    const float back = LDS ? kInvPreScale : 1.0f;
     for (int r0 = t.row0; r0 < t.row1; r0 += groups) {
         const int r = r0 + grp;
         float acc0 = 0.0f, acc1 = 0.0f;
@@ -253,12 +264,30 @@ __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& 
                     acc1 += term(w[u + 1], vi, v[u + 1]);
                 }
             }
-            for (; k < e; k += L) acc0 += term(HASW ? wv[k] : 0.0f, vi, v_at(col_at(k)));
+            // the remaining (< kBatch) edges of this lane as one masked
+            // batch, so their loads are in flight together as well
+            if (k < e) {
+                int j[kBatch];
+                float w[kBatch], v[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const bool ok = k + u * L < e;
+                    j[u] = ok ? col_at(k + u * L) : r;      // the row itself: dV = 0
+                    w[u] = HASW && ok ? wv[k + u * L] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) v[u] = v_at(j[u]);
+#pragma unroll
+                for (int u = 0; u < kBatch; u += 2) {
+                    acc0 += term(w[u], vi, v[u]);
+                    acc1 += term(w[u + 1], vi, v[u + 1]);
+                }
+            }
         }
         float acc = acc0 + acc1;
         if (L <= 64) {
             // all lanes of a group run the butterfly together
-            acc = wave_sum_xor(acc, L);
+            acc = wave_sum_xor(acc, L) * back;
             if (r < t.row1 && lig == 0) s_ig[r - t.row0] = HASW ? acc : d.g * acc;
         } else {
             acc = wave_sum_xor(acc, 64);
@@ -268,6 +297,7 @@ __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& 
             if (lig == 0 && r < t.row1) {
                 float tot = 0.0f;
                 for (int w = 0; w < L / 64; ++w) tot += s_part[wave + w];
+                tot *= back;
                 s_ig[r - t.row0] = HASW ? tot : d.g * tot;
             }
             __syncthreads();
@@ -296,14 +326,15 @@ __device__ __forceinline__ void gap_csr_blocked(const StepArgs& a, const InstDes
     for (int q = 0; q < kBlkPasses; ++q) {
         acc[q] = 0.0f;
         const int r = t.row0 + q * groups + grp;
-        vi[q] = r < t.row1 ? vd[r] : 0.0f;
+        vi[q] = r < t.row1 ? vd[r] * kPreScale : 0.0f;
     }
     for (int b = 0; b < d.nblk; ++b) {
         const int j0 = b * C;
         const int jn = min(C, d.n - j0);
         __syncthreads();
-        for (int k = threadIdx.x; k < jn; k += BLOCK) s_vd[k] = vd[j0 + k];
+        for (int k = threadIdx.x; k < jn; k += BLOCK) s_vd[k] = vd[j0 + k] * kPreScale;
         __syncthreads();
+        const float* sb = s_vd - j0;      // indexed by the global column
 #pragma unroll
         for (int q = 0; q < kBlkPasses; ++q) {
             const int r = t.row0 + q * groups + grp;
@@ -317,20 +348,33 @@ __device__ __forceinline__ void gap_csr_blocked(const StepArgs& a, const InstDes
                 float w[kBatch];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    j[u] = (C16 ? (int)c16[k + u * L] : c32[k + u * L]) - j0;
+                    j[u] = C16 ? (int)c16[k + u * L] : c32[k + u * L];
                     w[u] = HASW ? wv[k + u * L] : 1.0f;
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; u += 2) {
-                    const float d0 = vi[q] - s_vd[j[u]], d1 = vi[q] - s_vd[j[u + 1]];
-                    a0 = fmaf(w[u], d0 * gap_factor(d0), a0);
-                    a1 = fmaf(w[u + 1], d1 * gap_factor(d1), a1);
+                    const float d0 = vi[q] - sb[j[u]], d1 = vi[q] - sb[j[u + 1]];
+                    a0 = fmaf(w[u], d0 * gap_factor_ps(d0), a0);
+                    a1 = fmaf(w[u + 1], d1 * gap_factor_ps(d1), a1);
                 }
             }
-            for (; k < e; k += L) {
-                const int jj = (C16 ? (int)c16[k] : c32[k]) - j0;
-                const float d0 = vi[q] - s_vd[jj];
-                a0 = fmaf(HASW ? wv[k] : 1.0f, d0 * gap_factor(d0), a0);
+            // the remaining (< kBatch) edges as one masked batch: loads in
+            // flight together; a masked entry reads slot 0 with weight 0
+            if (k < e) {
+                int j[kBatch];
+                float w[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const bool ok = k + u * L < e;
+                    j[u] = ok ? (C16 ? (int)c16[k + u * L] : c32[k + u * L]) : j0;
+                    w[u] = ok ? (HASW ? wv[k + u * L] : 1.0f) : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; u += 2) {
+                    const float d0 = vi[q] - sb[j[u]], d1 = vi[q] - sb[j[u + 1]];
+                    a0 = fmaf(w[u], d0 * gap_factor_ps(d0), a0);
+                    a1 = fmaf(w[u + 1], d1 * gap_factor_ps(d1), a1);
+                }
             }
             acc[q] += a0 + a1;
         }
@@ -340,7 +384,7 @@ __device__ __forceinline__ void gap_csr_blocked(const StepArgs& a, const InstDes
         const int r = t.row0 + q * groups + grp;
         float v = acc[q];
         if (L <= 64) {
-            v = wave_sum_xor(v, L);
+            v = wave_sum_xor(v, L) * kInvPreScale;
             if (r < t.row1 && lig == 0) s_ig[r - t.row0] = HASW ? v : d.g * v;
         } else {
             v = wave_sum_xor(v, 64);
@@ -351,6 +395,7 @@ __device__ __forceinline__ void gap_csr_blocked(const StepArgs& a, const InstDes
             if (lig == 0 && r < t.row1) {
                 float tot = 0.0f;
                 for (int w = 0; w < L / 64; ++w) tot += s_part[wave + w];
+                tot *= kInvPreScale;
                 s_ig[r - t.row0] = HASW ? tot : d.g * tot;
             }
         }
@@ -376,7 +421,7 @@ __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, co
         }
     }
     if (d.vd_lds) {
-        for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k];
+        for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k] * kPreScale;
         __syncthreads();
         if (d.col16) {
             if (d.has_w) gap_csr_impl<BLOCK, true, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
@@ -447,8 +492,8 @@ __device__ __forceinline__ void gap_bitmap(const StepArgs& a, const InstDesc& d,
                     const int tb = 4 * q + e;
                     const float dv = vis - vv[e];
                     const float f = fmaf(0.8f, __builtin_amdgcn_exp2f(-(dv * dv)), 0.2f);
-                    // all ones when the bit is set, else zero
-                    const int m = (int)(wbits << (31 - tb)) >> 31;
+                    // all ones when the bit is set, else zero (signed 1-bit field)
+                    const int m = __builtin_amdgcn_sbfe((int)wbits, tb, 1);
                     const float dm = __int_as_float(__float_as_int(dv) & m);
                     if (e & 1) acc1 = fmaf(dm, f, acc1);
                     else acc0 = fmaf(dm, f, acc0);
