@@ -127,6 +127,10 @@ struct infoli_ctx {
     uint16_t* d_col16 = nullptr;
     uint32_t* d_bits = nullptr;
     int32_t* d_blk = nullptr;       // blocked CSR: per-row block starts
+    int32_t* d_ca = nullptr;        // chunked rows: per-row chunk starts
+    int32_t* d_cb = nullptr;        // chunked blocks: per-row, per-block chunk starts
+    uint4* d_chk = nullptr;         // chunks of eight 16-bit columns
+    float* d_chkw = nullptr;        // per-edge weights in the chunk layout
     int blk_cols = 8192;            // blocked CSR: cells per LDS block
     float* d_w = nullptr;
     float* d_stream = nullptr;

@@ -30,22 +30,16 @@ constexpr int kMlpLdsElems = kLdsW1 + kLdsW2 + kLdsW3;     // bf16 elements (42 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// fp32 -> bf16, round to nearest even on the bit pattern; NaN stays quiet NaN
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// fp32 -> bf16 by the hardware conversion (v_cvt_pk_bf16_f32: round to
+// nearest even, two values per instruction; NaN stays NaN)
+typedef __bf16 hbf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ bf16x4 pack_bf16(f32x4 v) {
-    bf16x4 r;
-    r[0] = (short)to_bf16(v[0]);
-    r[1] = (short)to_bf16(v[1]);
-    r[2] = (short)to_bf16(v[2]);
-    r[3] = (short)to_bf16(v[3]);
-    return r;
+    const hbf16x4 h = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+    return __builtin_bit_cast(bf16x4, h);
 }
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {

@@ -210,7 +210,8 @@ int group_for(const InstDesc& d) {
 }
 
 size_t lds_floats_for(const infoli_ctx* c, const InstDesc& d, int block) {
-    if (d.conn == CONN_CSR && d.blocked) return (size_t)std::min(d.n, c->blk_cols);
+    if (d.conn == CONN_CSR && d.blocked)   // the column block, then the tile rows' own voltages
+        return (size_t)std::min(d.n, c->blk_cols) + (d.cb_off >= 0 ? kSelfSlots : 0);
     if (d.conn == CONN_UNIFORM) return (size_t)std::min(d.n, kChunk) + 8 * (size_t)(block / 64);
     if (d.conn == CONN_CSR && d.bitmap) return bitmap_lds_floats(d.n);
     if (d.conn == CONN_CSR && d.vd_lds) return (size_t)d.n;
@@ -312,14 +313,112 @@ void build_blocks(infoli_ctx* c, const infoli_network_spec* specs) {
     HIPX(hipMemcpy(c->d_blk, h.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice));
 }
 
+// Chunked column lists for 16-byte vector loads (kChunkCols 16-bit columns
+// per chunk). Rows layout, for networks whose columns fit 16 bits: row i's
+// columns padded with i itself to whole chunks; per row its first chunk
+// ([n + 1], relative to the network's first chunk). Blocks layout, for
+// networks with column blocks: per row and block of C columns, the columns
+// relative to the block start padded with min(n, C) + (i mod kSelfSlots) to
+// whole chunks; per row and block the first chunk ([n][nblk + 1]). Per-edge
+// weights follow the same layout, 0 on padding.
+void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
+    const int C = c->blk_cols;
+    int64_t nca = 0, ncb = 0, nchunks = 0;
+    bool any_w = false;
+    auto chunks_of = [](int64_t cnt) { return (cnt + kChunkCols - 1) / kChunkCols; };
+    for (int k = 0; k < c->n_inst; ++k) {
+        InstDesc& d = c->inst[k];
+        d.ca_off = d.cb_off = d.chk_off = d.chkb_off = -1;
+        const infoli_network_spec& s = specs[k];
+        if (d.conn != CONN_CSR || s.nnz == 0) continue;
+        any_w = any_w || d.has_w;
+        if (d.n <= 65536) {
+            int64_t ch = 0;
+            for (int i = 0; i < d.n; ++i) ch += chunks_of(s.row_ptr[i + 1] - s.row_ptr[i]);
+            if (ch > INT32_MAX) continue;
+            d.ca_off = nca;
+            nca += d.n + 1;
+            d.chk_off = nchunks;
+            nchunks += ch;
+        }
+        if (d.blk_off >= 0 && C + kSelfSlots <= 65536) {
+            int64_t ch = 0;
+            for (int i = 0; i < d.n; ++i) {
+                int64_t e = s.row_ptr[i];
+                for (int b = 0; b < d.nblk; ++b) {
+                    const int64_t e0 = e;
+                    while (e < s.row_ptr[i + 1] && s.col[e] < (int64_t)(b + 1) * C) ++e;
+                    ch += chunks_of(e - e0);
+                }
+            }
+            if (ch > INT32_MAX) continue;
+            d.cb_off = ncb;
+            ncb += (int64_t)d.n * (d.nblk + 1);
+            d.chkb_off = nchunks;
+            nchunks += ch;
+        }
+    }
+    if (nchunks == 0) return;
+    std::vector<uint16_t> hc((size_t)nchunks * kChunkCols);
+    std::vector<float> hw(any_w ? (size_t)nchunks * kChunkCols : 1, 0.0f);
+    std::vector<int32_t> ha((size_t)std::max<int64_t>(nca, 1)), hb((size_t)std::max<int64_t>(ncb, 1));
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstDesc& d = c->inst[k];
+        const infoli_network_spec& s = specs[k];
+        if (d.ca_off >= 0) {
+            int64_t pos = 0;   // chunk index relative to the network's first
+            for (int i = 0; i < d.n; ++i) {
+                ha[(size_t)(d.ca_off + i)] = (int32_t)pos;
+                const int64_t rs = s.row_ptr[i], cnt = s.row_ptr[i + 1] - rs;
+                const int64_t base = (d.chk_off + pos) * kChunkCols;
+                for (int64_t e = 0; e < chunks_of(cnt) * kChunkCols; ++e) {
+                    hc[(size_t)(base + e)] = (uint16_t)(e < cnt ? s.col[rs + e] : i);
+                    if (d.has_w) hw[(size_t)(base + e)] = e < cnt ? s.w_csr[rs + e] : 0.0f;
+                }
+                pos += chunks_of(cnt);
+            }
+            ha[(size_t)(d.ca_off + d.n)] = (int32_t)pos;
+        }
+        if (d.cb_off >= 0) {
+            int64_t pos = 0;
+            for (int i = 0; i < d.n; ++i) {
+                int64_t e = s.row_ptr[i];
+                const uint16_t pad = (uint16_t)(std::min(d.n, C) + (i & (kSelfSlots - 1)));
+                for (int b = 0; b < d.nblk; ++b) {
+                    hb[(size_t)(d.cb_off + (int64_t)i * (d.nblk + 1) + b)] = (int32_t)pos;
+                    const int64_t e0 = e;
+                    while (e < s.row_ptr[i + 1] && s.col[e] < (int64_t)(b + 1) * C) ++e;
+                    const int64_t cnt = e - e0;
+                    const int64_t base = (d.chkb_off + pos) * kChunkCols;
+                    for (int64_t x = 0; x < chunks_of(cnt) * kChunkCols; ++x) {
+                        hc[(size_t)(base + x)] = x < cnt ? (uint16_t)(s.col[e0 + x] - (int64_t)b * C) : pad;
+                        if (d.has_w) hw[(size_t)(base + x)] = x < cnt ? s.w_csr[e0 + x] : 0.0f;
+                    }
+                    pos += chunks_of(cnt);
+                }
+                hb[(size_t)(d.cb_off + (int64_t)i * (d.nblk + 1) + d.nblk)] = (int32_t)pos;
+            }
+        }
+    }
+    c->d_chk = c->alloc<uint4>((size_t)nchunks);
+    HIPX(hipMemcpy(c->d_chk, hc.data(), sizeof(uint16_t) * hc.size(), hipMemcpyHostToDevice));
+    c->d_chkw = c->alloc<float>(hw.size());
+    HIPX(hipMemcpy(c->d_chkw, hw.data(), sizeof(float) * hw.size(), hipMemcpyHostToDevice));
+    c->d_ca = c->alloc<int32_t>(ha.size());
+    HIPX(hipMemcpy(c->d_ca, ha.data(), sizeof(int32_t) * ha.size(), hipMemcpyHostToDevice));
+    c->d_cb = c->alloc<int32_t>(hb.size());
+    HIPX(hipMemcpy(c->d_cb, hb.data(), sizeof(int32_t) * hb.size(), hipMemcpyHostToDevice));
+}
+
 // ---------------------------------------------------------------- autotuner
 // For every class of CSR network (log-spaced size and degree buckets) the
 // candidate tile shapes (lanes per row, rows per tile, LDS staging of Vd) are
 // timed on the network's own device data with dry launches (they write only
 // the next-state buffer) and the fastest is kept, in memory and in an
-// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v1.txt).
+// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v7.txt).
 struct TuneChoice {
-    int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS, path (0 gathers, 1 bitmap, 2 blocked)
+    int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS,
+                           // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers)
     int block;             // workgroup size of the launch group (256 or 1024)
 };
 
@@ -327,7 +426,7 @@ std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v5.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v7.txt";
     return "";
 }
 
@@ -355,14 +454,14 @@ std::map<std::string, TuneChoice> read_tune_cache(const std::string& path, std::
         *bar = 0;
         if (std::strncmp(line, "ctx ", 4) == 0) {
             int mode = -1;
-            if (std::sscanf(bar + 1, "%d", &mode) == 1 && mode >= 0 && mode <= 3) (*modes)[line] = mode;
+            if (std::sscanf(bar + 1, "%d", &mode) == 1 && mode >= 0 && mode <= 7) (*modes)[line] = mode;
             continue;
         }
         TuneChoice t;
         if (std::sscanf(bar + 1, "%d %d %d %d %d", &t.L, &t.R, &t.lds, &t.bm, &t.block) == 5 &&
             (t.block == 256 || t.block == 1024) && t.L >= 4 && t.L <= 1024 &&
             (t.L & (t.L - 1)) == 0 && t.R >= 1 && t.R <= kMaxTileRows && (t.lds == 0 || t.lds == 1) &&
-            (t.bm >= 0 && t.bm <= 2))
+            (t.bm >= 0 && t.bm <= 3))
             m[line] = t;
     }
     std::fclose(f);
@@ -396,10 +495,12 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
         d.vd_lds = t.lds;
         d.bitmap = t.bm == 1;
         d.blocked = t.bm == 2;
+        d.chunked = t.bm == 3;
         HIPX(hipMemcpy(c->d_inst + k, &d, sizeof(d), hipMemcpyHostToDevice));
         append_tiles(planned, k, d.n, t.R, 0.0);
         if (t.bm == 1) lds = std::max(lds, ((bitmap_lds_floats(d.n) + 3) / 4) * sizeof(float4));
-        else if (t.bm == 2) lds = std::max(lds, ((size_t)(std::min(d.n, c->blk_cols) + 3) / 4) * sizeof(float4));
+        else if (t.bm == 2)
+            lds = std::max(lds, ((size_t)(std::min(d.n, c->blk_cols) + kSelfSlots + 3) / 4) * sizeof(float4));
         else if (t.lds) lds = std::max(lds, ((size_t)(d.n + 3) / 4) * sizeof(float4));
     }
     std::vector<Tile> tl;
@@ -424,13 +525,15 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
 
 void apply_choice(infoli_ctx* c, const std::vector<int>& ks, TuneChoice best) {
     for (int k : ks)   // a cached choice this context cannot honour falls back to gathers
-        if ((best.bm == 1 && c->inst[k].bits_off < 0) || (best.bm == 2 && c->inst[k].blk_off < 0))
+        if ((best.bm == 1 && c->inst[k].bits_off < 0) || (best.bm == 2 && c->inst[k].blk_off < 0) ||
+            (best.bm == 3 && c->inst[k].ca_off < 0))
             best = TuneChoice{std::min(best.L, 256), std::max(1, 256 / std::min(best.L, 256)), 0, 0, 256};
     for (int k : ks) {
         c->inst[k].lanes_per_row = best.L;
         c->inst[k].vd_lds = best.lds;
         c->inst[k].bitmap = best.bm == 1;
         c->inst[k].blocked = best.bm == 2;
+        c->inst[k].chunked = best.bm == 3;
         c->inst[k].wide = best.block == 1024;
         c->rows_of[k] = best.R;
     }
@@ -480,17 +583,23 @@ void autotune(infoli_ctx* c) {
         classes[tune_key(c, d, c->deg_of[k])].push_back(k);
     }
     Tile* d_tmp = nullptr;
-    std::map<std::string, std::pair<TuneChoice, TuneChoice>> chosen;   // best, best in 256 threads
+    struct ClassChoice {
+        TuneChoice best, best256, best256nc;   // overall; in 256 threads; in 256 threads, not chunked
+    };
+    std::map<std::string, ClassChoice> chosen;
     for (const auto& kv : classes) {
         const std::string& key = kv.first;
         const std::vector<int>& ks = kv.second;
-        TuneChoice best{0, 0, 0, 0, 256}, best256{0, 0, 0, 0, 256};
+        TuneChoice best{0, 0, 0, 0, 256}, best256{0, 0, 0, 0, 256}, best256nc{0, 0, 0, 0, 256};
         auto hit = cache.find(key);
         auto hit256 = cache.find(key + "#256");
-        if (hit != cache.end() && hit256 != cache.end() && hit->second.L <= 256 && hit256->second.L <= 256 &&
-            hit256->second.block == 256) {
+        auto hitnc = cache.find(key + "#256nc");
+        if (hit != cache.end() && hit256 != cache.end() && hitnc != cache.end() && hit->second.L <= 256 &&
+            hit256->second.L <= 256 && hit256->second.block == 256 && hitnc->second.L <= 256 &&
+            hitnc->second.block == 256 && hitnc->second.bm != 3) {
             best = hit->second;
             best256 = hit256->second;
+            best256nc = hitnc->second;
             c->tune_cached += (int)ks.size();
         } else {
             if (!d_tmp) d_tmp = c->alloc<Tile>(c->total_cells + 1);
@@ -501,7 +610,9 @@ void autotune(infoli_ctx* c) {
                 n = std::max(n, c->inst[k].n);
                 deg = std::max(deg, c->deg_of[k]);
             }
-            float best_ms = 1e30f, best256_ms = 1e30f;
+            float best_ms = 1e30f, best256_ms = 1e30f, best256nc_ms = 1e30f;
+            bool all_rows = c->d_ca != nullptr;    // every network of the class has the chunked rows layout
+            for (int k : ks) all_rows = all_rows && c->inst[k].ca_off >= 0;
             auto consider = [&](const TuneChoice& t) {
                 const float ms = time_shape(c, ks, t, d_tmp);
                 if (ms < best_ms) {
@@ -512,6 +623,10 @@ void autotune(infoli_ctx* c) {
                     best256_ms = ms;
                     best256 = t;
                 }
+                if (t.block == 256 && t.bm != 3 && ms < best256nc_ms) {
+                    best256nc_ms = ms;
+                    best256nc = t;
+                }
             };
             for (int L = 4; L <= 256; L *= 2) {
                 if (L > 4 && L > 2.0 * deg) break;
@@ -519,7 +634,10 @@ void autotune(infoli_ctx* c) {
                 for (int m = 1; m <= 4; m *= 2) {
                     const int R = std::max(1, 256 / L) * m;
                     if (R > kMaxTileRows) continue;
-                    for (int lds = 0; lds <= (n <= kChunk ? 1 : 0); ++lds) consider(TuneChoice{L, R, lds, 0, 256});
+                    for (int lds = 0; lds <= (n <= kChunk ? 1 : 0); ++lds) {
+                        consider(TuneChoice{L, R, lds, 0, 256});
+                        if (all_rows) consider(TuneChoice{L, R, lds, 3, 256});
+                    }
                 }
             }
             // the bitmap path, when every network of the class has one
@@ -541,9 +659,10 @@ void autotune(infoli_ctx* c) {
                 }
             append_tune_cache(path, key, best);
             append_tune_cache(path, key + "#256", best256);
+            append_tune_cache(path, key + "#256nc", best256nc);
             c->tuned += (int)ks.size();
         }
-        chosen[key] = {best, best256};
+        chosen[key] = {best, best256, best256nc};
     }
 
     // whole-step choice for this mix of networks
@@ -559,24 +678,32 @@ void autotune(infoli_ctx* c) {
     for (const auto& p : parts) sig += p + ";";
     char ctx_key[64];
     snprintf(ctx_key, sizeof ctx_key, "ctx %016llx", (unsigned long long)fnv1a(sig));
-    auto apply_all = [&](bool use256) {
-        for (const auto& kv : classes) {
-            const auto& ch = chosen[kv.first];
-            apply_choice(c, kv.second, use256 ? ch.second : ch.first);
-        }
+    // variant of the per-class choices: bit 0, each class in its best
+    // 256-thread shape; bit 2, chunked gathers replaced by the best
+    // non-chunked 256-thread shape
+    auto pick = [&](const ClassChoice& ch, int m) {
+        TuneChoice t = (m & 1) ? ch.best256 : ch.best;
+        if ((m & 4) && t.bm == 3) t = ch.best256nc;
+        return t;
     };
-    int mode = 0;   // bit 0: 256-thread shapes for every class; bit 1: groups one after the other
+    auto apply_all = [&](int m) {
+        for (const auto& kv : classes) apply_choice(c, kv.second, pick(chosen[kv.first], m));
+    };
+    // bit 0 and bit 2 as above; bit 1: the two launch groups one after the other
+    int mode = 0;
     auto mh = modes.find(ctx_key);
     if (mh != modes.end()) {
         mode = mh->second;
     } else {
+        bool wide = false, chunk = false;   // variants that change something
+        for (const auto& kv : chosen) {
+            wide = wide || kv.second.best.block != 256;
+            chunk = chunk || kv.second.best.bm == 3 || kv.second.best256.bm == 3;
+        }
         float best_ms = 1e30f;
-        for (int m = 0; m < 4; ++m) {
-            const bool use256 = m & 1;
-            bool differs = false;   // the all-256 variant only where some class prefers 1024 threads
-            for (const auto& kv : chosen) differs = differs || kv.second.first.block != 256;
-            if (use256 && !differs) continue;
-            apply_all(use256);
+        for (int m = 0; m < 8; ++m) {
+            if (((m & 1) && !wide) || ((m & 4) && !chunk)) continue;
+            apply_all(m);
             finalize_tiles(c);
             const bool both = !c->grp[0].tiles.empty() && !c->grp[1].tiles.empty();
             if ((m & 2) && !both) continue;
@@ -590,7 +717,7 @@ void autotune(infoli_ctx* c) {
         snprintf(line, sizeof line, "%s|%d", ctx_key, mode);
         append_tune_line(path, line);
     }
-    apply_all(mode & 1);
+    apply_all(mode);
     c->fork_groups = !(mode & 2);
 }
 
@@ -611,8 +738,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         fail(INFOLI_E_INVALID_ARG, "lanes_per_row must be 0 or a power of two in [4, 256]");
     if (c->opt.autotune < 0 || c->opt.autotune > 2)
         fail(INFOLI_E_INVALID_ARG, "autotune must be 0, 1 or 2");
-    if (c->opt.csr_path < 0 || c->opt.csr_path > 3)
-        fail(INFOLI_E_INVALID_ARG, "csr_path must be 0, 1, 2 or 3");
+    if (c->opt.csr_path < 0 || c->opt.csr_path > 4)
+        fail(INFOLI_E_INVALID_ARG, "csr_path must be 0, 1, 2, 3 or 4");
     if (c->opt.tile_rows < 0 || c->opt.tile_rows > kMaxTileRows)
         fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
     for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
@@ -819,6 +946,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     HIPX(hipDeviceSynchronize());
     build_bitmaps(c, specs);
     build_blocks(c, specs);
+    build_chunks(c, specs);
     if (c->opt.autotune && c->opt.csr_path == 0) autotune(c);
     if (c->opt.csr_path == 3)
         for (int k = 0; k < ninst; ++k)
@@ -827,6 +955,9 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
                 c->inst[k].lanes_per_row = std::min(64, std::max(8, c->inst[k].lanes_per_row));
                 c->rows_of[k] = std::min(kMaxTileRows, 1024 / c->inst[k].lanes_per_row);
             }
+    if (c->opt.csr_path == 4)
+        for (int k = 0; k < ninst; ++k)
+            if (c->inst[k].ca_off >= 0) c->inst[k].chunked = 1;
     if (c->opt.csr_path == 2)
         for (int k = 0; k < ninst; ++k)
             if (c->inst[k].bits_off >= 0) {
@@ -852,6 +983,10 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     a.col16 = c->d_col16;
     a.bits = c->d_bits;
     a.blk = c->d_blk;
+    a.ca = c->d_ca;
+    a.cb = c->d_cb;
+    a.chk = c->d_chk;
+    a.chkw = c->d_chkw;
     a.blk_cols = c->blk_cols;
     a.w = c->d_w;
     a.i_stream = c->d_stream;

@@ -69,9 +69,13 @@ struct InstDesc {
     int32_t blocked;       // CSR: Vd staged in LDS one column block at a time
     int32_t nblk;          // blocked: number of column blocks
     int32_t wide;          // bitmap: run in the 1024-thread launch group
-    int32_t pad1;
+    int32_t chunked;       // CSR gathers from the chunked rows layout
     int64_t bits_off;      // bitmap: offset of the network's first word
     int64_t blk_off;       // blocked: offset of the network's [n][nblk] block starts
+    int64_t ca_off;        // chunked rows: offset of the [n + 1] row chunk starts, -1 none
+    int64_t chk_off;       // chunked rows: first chunk of the network
+    int64_t cb_off;        // chunked blocks: offset of the [n][nblk + 1] chunk starts, -1 none
+    int64_t chkb_off;      // chunked blocks: first chunk of the network
     CellParams p;
 };
 
@@ -100,6 +104,10 @@ struct StepArgs {
     const uint32_t* bits;      // coupling bitmaps
     const int32_t* blk;        // blocked CSR: per row, first edge of each column block
     int32_t blk_cols;          // blocked CSR: cells per column block
+    const int32_t* ca;         // chunked rows: per row, first chunk (relative to the network's)
+    const int32_t* cb;         // chunked blocks: per row and block, first chunk
+    const uint4* chk;          // chunks of eight 16-bit columns
+    const float* chkw;         // per-edge weights in the chunk layout (8 per chunk)
     const float* w;            // DENSE matrices and CSR weights
     const float* i_stream;     // dense input streams
     int32_t* spike_count;      // [cells]
@@ -402,6 +410,183 @@ __device__ __forceinline__ void gap_csr_blocked(const StepArgs& a, const InstDes
     }
 }
 
+// ---------------------------------------------------------------- chunked CSR
+// Column lists in 16-byte chunks of eight 16-bit columns, read with one
+// vector load per lane per chunk: the L lanes of a row read consecutive
+// chunks, so a row's 128-byte cache line is touched by one load instruction.
+// Padding entries make a zero term (their voltage is the row's own, dV = 0).
+constexpr int kChunkCols = 8;
+
+__device__ __forceinline__ uint4 pad_chunk(uint32_t v) {
+    const uint32_t w = v | (v << 16);
+    return make_uint4(w, w, w, w);
+}
+
+// Sixteen edges of a row from two chunks: columns j, voltages from `src`
+// (LDS, prescaled; or global), accumulated into acc0/acc1.
+template <bool PS, bool HASW>
+__device__ __forceinline__ void chunk_pair_terms(const uint4 q0, const uint4 q1, const float4* w4,
+                                                 const float* src, float vi, float& acc0, float& acc1) {
+    const uint32_t wd[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    float v[2 * kChunkCols];
+#pragma unroll
+    for (int e = 0; e < 2 * kChunkCols; ++e) {
+        const uint32_t j = (e & 1) ? (wd[e >> 1] >> 16) : (wd[e >> 1] & 0xffffu);
+        v[e] = src[j];
+    }
+#pragma unroll
+    for (int e = 0; e < 2 * kChunkCols; e += 2) {
+        const float d0 = vi - v[e], d1 = vi - v[e + 1];
+        const float f0 = PS ? gap_factor_ps(d0) : gap_factor(d0);
+        const float f1 = PS ? gap_factor_ps(d1) : gap_factor(d1);
+        if (HASW) {
+            const float4 wa = w4[e >> 2];
+            const float w0 = (e & 3) == 0 ? wa.x : wa.z, w1 = (e & 3) == 0 ? wa.y : wa.w;
+            acc0 = fmaf(w0, d0 * f0, acc0);
+            acc1 = fmaf(w1, d1 * f1, acc1);
+        } else {
+            acc0 = fmaf(d0, f0, acc0);
+            acc1 = fmaf(d1, f1, acc1);
+        }
+    }
+}
+
+// Gathers over whole rows (networks of at most 65,536 cells): row r's chunks
+// [ca[r], ca[r + 1]), padded with r itself.
+template <int BLOCK, bool LDS, bool HASW>
+__device__ __forceinline__ void gap_chunks(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                           const float* __restrict__ vd, const float* s_vd, float* s_part,
+                                           float* s_ig) {
+    const int L = d.lanes_per_row;
+    const int groups = BLOCK / L;
+    const int grp = threadIdx.x / L;
+    const int lig = threadIdx.x % L;
+    const int32_t* ca = a.ca + d.ca_off;
+    const uint4* ch = a.chk + d.chk_off;
+    const float4* cw = reinterpret_cast<const float4*>(a.chkw) + 2 * d.chk_off;
+    const float* src = LDS ? s_vd : vd;
+    const float back = LDS ? kInvPreScale : 1.0f;
+    for (int r0 = t.row0; r0 < t.row1; r0 += groups) {
+        const int r = r0 + grp;
+        float acc0 = 0.0f, acc1 = 0.0f;
+        if (r < t.row1) {
+            const float vi = src[r];
+            const uint4 padc = pad_chunk((uint32_t)r);
+            const int ce = ca[r + 1];
+            for (int c = ca[r] + lig; c < ce; c += 2 * L) {
+                const bool ok1 = c + L < ce;
+                const uint4 q0 = ch[c];
+                const uint4 q1 = ok1 ? ch[c + L] : padc;
+                float4 w4[4];
+                if (HASW) {
+                    w4[0] = cw[2 * (int64_t)c];
+                    w4[1] = cw[2 * (int64_t)c + 1];
+                    w4[2] = ok1 ? cw[2 * (int64_t)(c + L)] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    w4[3] = ok1 ? cw[2 * (int64_t)(c + L) + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                chunk_pair_terms<LDS, HASW>(q0, q1, w4, src, vi, acc0, acc1);
+            }
+        }
+        float acc = acc0 + acc1;
+        if (L <= 64) {
+            acc = wave_sum_xor(acc, L) * back;
+            if (r < t.row1 && lig == 0) s_ig[r - t.row0] = HASW ? acc : d.g * acc;
+        } else {
+            acc = wave_sum_xor(acc, 64);
+            const int wave = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0) s_part[wave] = acc;
+            __syncthreads();
+            if (lig == 0 && r < t.row1) {
+                float tot = 0.0f;
+                for (int w = 0; w < L / 64; ++w) tot += s_part[wave + w];
+                tot *= back;
+                s_ig[r - t.row0] = HASW ? tot : d.g * tot;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+constexpr int kSelfSlots = 256;     // LDS slots after a column block: the tile rows' own voltages
+
+// Column blocks with chunks: per row and block, the columns relative to the
+// block start, padded with S + (r mod 256), S = min(n, C), the LDS slot
+// holding row r's own (prescaled) voltage; LDS holds S + kSelfSlots floats.
+template <int BLOCK, bool HASW>
+__device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                                   const float* __restrict__ vd, float* s_vd, float* s_part,
+                                                   float* s_ig) {
+    const int L = d.lanes_per_row;
+    const int groups = BLOCK / L;
+    const int grp = threadIdx.x / L;
+    const int lig = threadIdx.x % L;
+    const int C = a.blk_cols;
+    const int nb1 = d.nblk + 1;
+    const int32_t* cb = a.cb + d.cb_off;
+    const uint4* ch = a.chk + d.chkb_off;
+    const float4* cw = reinterpret_cast<const float4*>(a.chkw) + 2 * d.chkb_off;
+    const int S = min(d.n, C);     // own-voltage slots follow the largest block
+    for (int k = threadIdx.x; k < t.row1 - t.row0; k += BLOCK)
+        s_vd[S + ((t.row0 + k) & (kSelfSlots - 1))] = vd[t.row0 + k] * kPreScale;
+    float acc[kBlkPasses], vi[kBlkPasses];
+#pragma unroll
+    for (int q = 0; q < kBlkPasses; ++q) {
+        acc[q] = 0.0f;
+        const int r = t.row0 + q * groups + grp;
+        vi[q] = r < t.row1 ? vd[r] * kPreScale : 0.0f;
+    }
+    for (int b = 0; b < d.nblk; ++b) {
+        const int j0 = b * C;
+        const int jn = min(C, d.n - j0);
+        __syncthreads();
+        for (int k = threadIdx.x; k < jn; k += BLOCK) s_vd[k] = vd[j0 + k] * kPreScale;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBlkPasses; ++q) {
+            const int r = t.row0 + q * groups + grp;
+            if (r >= t.row1) continue;
+            const uint4 padc = pad_chunk((uint32_t)(S + (r & (kSelfSlots - 1))));
+            const int ce = cb[(int64_t)r * nb1 + b + 1];
+            float a0 = 0.0f, a1 = 0.0f;
+            for (int c = cb[(int64_t)r * nb1 + b] + lig; c < ce; c += 2 * L) {
+                const bool ok1 = c + L < ce;
+                const uint4 q0 = ch[c];
+                const uint4 q1 = ok1 ? ch[c + L] : padc;
+                float4 w4[4];
+                if (HASW) {
+                    w4[0] = cw[2 * (int64_t)c];
+                    w4[1] = cw[2 * (int64_t)c + 1];
+                    w4[2] = ok1 ? cw[2 * (int64_t)(c + L)] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    w4[3] = ok1 ? cw[2 * (int64_t)(c + L) + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                chunk_pair_terms<true, HASW>(q0, q1, w4, s_vd, vi[q], a0, a1);
+            }
+            acc[q] += a0 + a1;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kBlkPasses; ++q) {
+        const int r = t.row0 + q * groups + grp;
+        float v = acc[q];
+        if (L <= 64) {
+            v = wave_sum_xor(v, L) * kInvPreScale;
+            if (r < t.row1 && lig == 0) s_ig[r - t.row0] = HASW ? v : d.g * v;
+        } else {
+            v = wave_sum_xor(v, 64);
+            const int wave = threadIdx.x >> 6;
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) s_part[wave] = v;
+            __syncthreads();
+            if (lig == 0 && r < t.row1) {
+                float tot = 0.0f;
+                for (int w = 0; w < L / 64; ++w) tot += s_part[wave + w];
+                tot *= kInvPreScale;
+                s_ig[r - t.row0] = HASW ? tot : d.g * tot;
+            }
+        }
+    }
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
                                         const float* __restrict__ vd, float* s_vd, float* s_part,
@@ -409,6 +594,11 @@ __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, co
     // column-blocked tiles run in 1024-thread workgroups only (the runtime
     // places them there); elsewhere the same rows take the gathers below
     if constexpr (BLOCK == 1024) {
+        if (d.blocked && d.cb_off >= 0) {
+            if (d.has_w) gap_chunks_blocked<BLOCK, true>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_chunks_blocked<BLOCK, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            return;
+        }
         if (d.blocked) {
             if (d.col16) {
                 if (d.has_w) gap_csr_blocked<BLOCK, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
@@ -419,6 +609,18 @@ __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, co
             }
             return;
         }
+    }
+    if (d.chunked && d.ca_off >= 0) {
+        if (d.vd_lds) {
+            for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k] * kPreScale;
+            __syncthreads();
+            if (d.has_w) gap_chunks<BLOCK, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_chunks<BLOCK, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
+        } else {
+            if (d.has_w) gap_chunks<BLOCK, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_chunks<BLOCK, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
+        }
+        return;
     }
     if (d.vd_lds) {
         for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k] * kPreScale;

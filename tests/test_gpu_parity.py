@@ -456,9 +456,11 @@ def test_autotuner_times_caches_and_stays_exact(infoli, o32, tmp_path, monkeypat
         else:
             assert info["tuned"] == 0 and info["tune_cached"] == 2
     lines = (tmp_path / "tune.txt").read_text().strip().splitlines()
-    # per class its best and its best 256-thread shape, then the whole-step choice
-    assert len(lines) == 5 and all("|" in l for l in lines)
+    # per class its best, best 256-thread and best non-chunked 256-thread
+    # shapes, then the whole-step choice
+    assert len(lines) == 7 and all("|" in l for l in lines)
     assert sum(l.startswith("ctx ") for l in lines) == 1 and sum("#256|" in l for l in lines) == 2
+    assert sum("#256nc|" in l for l in lines) == 2
     for k, net in enumerate(nets):
         np.testing.assert_array_equal(out[0][k], out[1][k])
         ref = o32.run(net, 300, x0=x0s[k])["x"]
@@ -537,6 +539,35 @@ def test_bitmap_gap_current(infoli, o64, n):
     ref = o64.gap(net, x0[0].astype(np.float64))
     tol = gap_bound(net, x0[0])
     assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
+# ------------------------------------------------------------------ chunked column lists
+@pytest.mark.parametrize("n,p,weights", [(1000, 0.03, False), (3000, 0.2, True), (9000, 0.01, False)])
+def test_chunked_gathers(infoli, o32, o64, n, p, weights):
+    """Gathers from 16-byte column chunks (rows padded with their own index):
+    gap currents against fp64 after 100 steps and one step against the
+    oracle; with per-edge weights, with and without Vd in LDS (9,000 cells
+    gather from global memory)."""
+    net = I.config1(p, seed=n, n=n)
+    if weights:
+        # symmetric weights: w_ij = w_ji (the same for a pair in both rows)
+        rows = np.repeat(np.arange(n), np.diff(net.row_ptr))
+        key = np.minimum(rows, net.col) * n + np.maximum(rows, net.col)
+        _, inv = np.unique(key, return_inverse=True)
+        net.w_csr = I.rng(n + 2).uniform(0.01, 0.08, inv.max() + 1).astype(np.float32)[inv]
+    x0 = infoli.initial_state(net)
+    sim = infoli.Simulator(net, init_states=[x0], csr_path=4, step_mode="graph", graph_chunk=50)
+    sim.step(100)
+    xk = sim.read_state(0)
+    ig = sim.read_gap_current(0).astype(np.float64)
+    sim.step(1)
+    xk1 = sim.read_state(0)
+    sim.close()
+    ref_ig = o64.gap(net, xk[0].astype(np.float64))
+    tol = gap_bound(net, xk[0])
+    assert np.all(np.abs(ig - ref_ig) <= tol), np.max(np.abs(ig - ref_ig) / tol)
+    ref = o32.run(net, 1, x0=xk, step0=100)["x"]
+    assert per_var_error(xk1[None], ref[None]).max() <= 1e-5
 
 
 # ------------------------------------------------------------------ column-blocked path
