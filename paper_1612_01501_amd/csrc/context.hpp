@@ -62,6 +62,7 @@ struct TileGroup {
     int block = 256;
     std::vector<Tile> tiles;
     Tile* d_tiles = nullptr;
+    size_t cap = 0;                 // tiles d_tiles holds (reused when the tuner re-plans)
     size_t lds = 16;                // dynamic LDS bytes of the launch
 };
 

@@ -240,7 +240,10 @@ void finalize_tiles(infoli_ctx* c) {
         for (const auto& pt : planned[g]) tg.tiles.push_back(pt.second);
         if (tg.tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
         if (!tg.tiles.empty()) {
-            tg.d_tiles = c->alloc<Tile>(tg.tiles.size());
+            if (tg.tiles.size() > tg.cap) {
+                tg.d_tiles = c->alloc<Tile>(tg.tiles.size());
+                tg.cap = tg.tiles.size();
+            }
             HIPX(hipMemcpy(tg.d_tiles, tg.tiles.data(), sizeof(Tile) * tg.tiles.size(), hipMemcpyHostToDevice));
         }
     }
@@ -415,7 +418,7 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
 // candidate tile shapes (lanes per row, rows per tile, LDS staging of Vd) are
 // timed on the network's own device data with dry launches (they write only
 // the next-state buffer) and the fastest is kept, in memory and in an
-// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v7.txt).
+// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v8.txt).
 struct TuneChoice {
     int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS,
                            // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers)
@@ -426,7 +429,7 @@ std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v7.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v8.txt";
     return "";
 }
 
@@ -442,7 +445,8 @@ std::string tune_key(const infoli_ctx* c, const InstDesc& d, double deg) {
 // Lines "<class key>|L R lds bm block" (the class's best shape),
 // "<class key>#256|..." (its best shape in 256-thread workgroups) and
 // "ctx <hash>|mode" (the whole-step launch choice of one mix of networks).
-std::map<std::string, TuneChoice> read_tune_cache(const std::string& path, std::map<std::string, int>* modes) {
+std::map<std::string, TuneChoice> read_tune_cache(const std::string& path,
+                                                  std::map<std::string, std::vector<int>>* modes) {
     std::map<std::string, TuneChoice> m;
     if (path.empty()) return m;
     std::FILE* f = std::fopen(path.c_str(), "r");
@@ -452,9 +456,15 @@ std::map<std::string, TuneChoice> read_tune_cache(const std::string& path, std::
         char* bar = std::strchr(line, '|');
         if (!bar) continue;
         *bar = 0;
-        if (std::strncmp(line, "ctx ", 4) == 0) {
-            int mode = -1;
-            if (std::sscanf(bar + 1, "%d", &mode) == 1 && mode >= 0 && mode <= 7) (*modes)[line] = mode;
+        if (std::strncmp(line, "ctx ", 4) == 0) {   // mode, then one refinement per class
+            std::vector<int> v;
+            char* p = bar + 1;
+            char* end = nullptr;
+            for (long x = std::strtol(p, &end, 10); end != p; x = std::strtol(p, &end, 10)) {
+                v.push_back((int)x);
+                p = end;
+            }
+            if (!v.empty() && v[0] >= 0 && v[0] <= 7) (*modes)[line] = v;
             continue;
         }
         TuneChoice t;
@@ -539,20 +549,25 @@ void apply_choice(infoli_ctx* c, const std::vector<int>& ks, TuneChoice best) {
     }
 }
 
-// Average duration of a dry whole step (both launch groups) as finalised.
+// Average duration of a dry whole step (both launch groups) as finalised;
+// the smallest of five averages of 40 steps.
 float time_step(infoli_ctx* c, bool fork) {
     StepArgs a = make_args(c, false);
     a.dry = 1;
     for (int w = 0; w < 3; ++w) launch_groups(c, c->stream, a, c->cur, c->step, 0, fork);
-    HIPX(hipEventRecord(c->ev0, c->stream));
-    const int reps = 20;
-    for (int w = 0; w < reps; ++w) launch_groups(c, c->stream, a, c->cur, c->step, 0, fork);
-    HIPX(hipEventRecord(c->ev1, c->stream));
-    HIPX(hipGetLastError());
-    HIPX(hipEventSynchronize(c->ev1));
-    float ms = 0.0f;
-    HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    return ms / reps;
+    const int reps = 40;
+    float best = 1e30f;
+    for (int trial = 0; trial < 5; ++trial) {
+        HIPX(hipEventRecord(c->ev0, c->stream));
+        for (int w = 0; w < reps; ++w) launch_groups(c, c->stream, a, c->cur, c->step, 0, fork);
+        HIPX(hipEventRecord(c->ev1, c->stream));
+        HIPX(hipGetLastError());
+        HIPX(hipEventSynchronize(c->ev1));
+        float ms = 0.0f;
+        HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        best = std::min(best, ms / reps);
+    }
+    return best;
 }
 
 uint64_t fnv1a(const std::string& s) {
@@ -573,7 +588,7 @@ void autotune(infoli_ctx* c) {
     if (c->opt.lanes_per_row || c->opt.tile_rows) return;   // shapes given by the caller
     const std::string path = tune_cache_path();
     std::map<std::string, TuneChoice> cache;
-    std::map<std::string, int> modes;
+    std::map<std::string, std::vector<int>> modes;
     if (c->opt.autotune == 1) cache = read_tune_cache(path, &modes);
     // classes of CSR networks
     std::map<std::string, std::vector<int>> classes;
@@ -583,23 +598,33 @@ void autotune(infoli_ctx* c) {
         classes[tune_key(c, d, c->deg_of[k])].push_back(k);
     }
     Tile* d_tmp = nullptr;
+    constexpr int kAlts = 3;
     struct ClassChoice {
         TuneChoice best, best256, best256nc;   // overall; in 256 threads; in 256 threads, not chunked
+        TuneChoice alt[kAlts];                 // the fastest distinct 256-thread shapes, fastest first
+        int nalt = 0;
     };
     std::map<std::string, ClassChoice> chosen;
     for (const auto& kv : classes) {
         const std::string& key = kv.first;
         const std::vector<int>& ks = kv.second;
         TuneChoice best{0, 0, 0, 0, 256}, best256{0, 0, 0, 0, 256}, best256nc{0, 0, 0, 0, 256};
+        ClassChoice cc;
         auto hit = cache.find(key);
         auto hit256 = cache.find(key + "#256");
         auto hitnc = cache.find(key + "#256nc");
-        if (hit != cache.end() && hit256 != cache.end() && hitnc != cache.end() && hit->second.L <= 256 &&
-            hit256->second.L <= 256 && hit256->second.block == 256 && hitnc->second.L <= 256 &&
-            hitnc->second.block == 256 && hitnc->second.bm != 3) {
+        auto hita = cache.find(key + "#a0");
+        if (hit != cache.end() && hit256 != cache.end() && hitnc != cache.end() && hita != cache.end() &&
+            hit->second.L <= 256 && hit256->second.L <= 256 && hit256->second.block == 256 &&
+            hitnc->second.L <= 256 && hitnc->second.block == 256 && hitnc->second.bm != 3) {
             best = hit->second;
             best256 = hit256->second;
             best256nc = hitnc->second;
+            for (int a = 0; a < kAlts; ++a) {
+                auto h = cache.find(key + "#a" + std::to_string(a));
+                if (h == cache.end() || h->second.block != 256 || h->second.L > 256) break;
+                cc.alt[cc.nalt++] = h->second;
+            }
             c->tune_cached += (int)ks.size();
         } else {
             if (!d_tmp) d_tmp = c->alloc<Tile>(c->total_cells + 1);
@@ -611,10 +636,12 @@ void autotune(infoli_ctx* c) {
                 deg = std::max(deg, c->deg_of[k]);
             }
             float best_ms = 1e30f, best256_ms = 1e30f, best256nc_ms = 1e30f;
+            std::vector<std::pair<float, TuneChoice>> timed;
             bool all_rows = c->d_ca != nullptr;    // every network of the class has the chunked rows layout
             for (int k : ks) all_rows = all_rows && c->inst[k].ca_off >= 0;
             auto consider = [&](const TuneChoice& t) {
                 const float ms = time_shape(c, ks, t, d_tmp);
+                if (t.block == 256) timed.push_back({ms, t});
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = t;
@@ -657,12 +684,22 @@ void autotune(infoli_ctx* c) {
                         consider(TuneChoice{L, R, 0, 2, 1024});
                     }
                 }
+            std::stable_sort(timed.begin(), timed.end(),
+                             [](const auto& x, const auto& y) { return x.first < y.first; });
+            for (const auto& tt : timed) {
+                if (cc.nalt == kAlts) break;
+                cc.alt[cc.nalt++] = tt.second;
+            }
             append_tune_cache(path, key, best);
             append_tune_cache(path, key + "#256", best256);
             append_tune_cache(path, key + "#256nc", best256nc);
+            for (int a = 0; a < cc.nalt; ++a) append_tune_cache(path, key + "#a" + std::to_string(a), cc.alt[a]);
             c->tuned += (int)ks.size();
         }
-        chosen[key] = {best, best256, best256nc};
+        cc.best = best;
+        cc.best256 = best256;
+        cc.best256nc = best256nc;
+        chosen[key] = cc;
     }
 
     // whole-step choice for this mix of networks
@@ -691,33 +728,87 @@ void autotune(infoli_ctx* c) {
     };
     // bit 0 and bit 2 as above; bit 1: the two launch groups one after the other
     int mode = 0;
+    const int ncls = (int)classes.size();
+    std::vector<int> refine(ncls, -1);   // per class: -1 its mode choice, else that alternative
     auto mh = modes.find(ctx_key);
-    if (mh != modes.end()) {
-        mode = mh->second;
+    if (mh != modes.end() && (int)mh->second.size() == 1 + ncls) {
+        mode = mh->second[0];
+        for (int i = 0; i < ncls; ++i) refine[i] = mh->second[1 + i];
     } else {
         bool wide = false, chunk = false;   // variants that change something
         for (const auto& kv : chosen) {
             wide = wide || kv.second.best.block != 256;
             chunk = chunk || kv.second.best.bm == 3 || kv.second.best256.bm == 3;
         }
-        float best_ms = 1e30f;
-        for (int m = 0; m < 8; ++m) {
-            if (((m & 1) && !wide) || ((m & 4) && !chunk)) continue;
-            apply_all(m);
-            finalize_tiles(c);
-            const bool both = !c->grp[0].tiles.empty() && !c->grp[1].tiles.empty();
-            if ((m & 2) && !both) continue;
-            const float ms = time_step(c, !(m & 2));
-            if (ms < best_ms) {
-                best_ms = ms;
-                mode = m;
+        // every variant timed in two interleaved rounds, the smaller kept
+        float mode_ms[8];
+        for (float& v : mode_ms) v = 1e30f;
+        for (int round = 0; round < 2; ++round)
+            for (int m = 0; m < 8; ++m) {
+                if (((m & 1) && !wide) || ((m & 4) && !chunk)) continue;
+                apply_all(m);
+                finalize_tiles(c);
+                const bool both = !c->grp[0].tiles.empty() && !c->grp[1].tiles.empty();
+                if ((m & 2) && !both) continue;
+                mode_ms[m] = std::min(mode_ms[m], time_step(c, !(m & 2)));
+            }
+        for (int m = 1; m < 8; ++m)
+            if (mode_ms[m] < mode_ms[mode]) mode = m;
+        // Refinement in the whole step: a class timed alone can rank shapes
+        // differently from the full step. Every class with at least 5 % of
+        // the step's pairs tries its fastest 256-thread alternatives with
+        // the others fixed; a change stays when the step is 2 % faster.
+        apply_all(mode);
+        finalize_tiles(c);
+        double total = 0.0;
+        std::vector<std::pair<double, int>> order;
+        int i = 0;
+        for (const auto& kv : classes) {
+            double pairs = 0.0;
+            for (int k : kv.second) pairs += c->deg_of[k] * c->inst[k].n;
+            order.push_back({pairs, i++});
+            total += pairs;
+        }
+        std::sort(order.begin(), order.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+        std::vector<std::string> keys;
+        for (const auto& kv : classes) keys.push_back(kv.first);
+        for (const auto& o : order) {
+            if (o.first < 0.05 * total) break;
+            const std::string& key = keys[o.second];
+            const ClassChoice& ch = chosen[key];
+            const TuneChoice base = pick(ch, mode);
+            for (int a = 0; a < ch.nalt; ++a) {
+                const TuneChoice& t = ch.alt[a];
+                const TuneChoice& now = refine[o.second] >= 0 ? ch.alt[refine[o.second]] : base;
+                if (t.L == now.L && t.R == now.R && t.lds == now.lds && t.bm == now.bm && t.block == now.block)
+                    continue;
+                // the current choice and the alternative, timed back to back twice
+                float cur_ms = 1e30f, alt_ms = 1e30f;
+                for (int round = 0; round < 2; ++round) {
+                    apply_choice(c, classes[key], now);
+                    finalize_tiles(c);
+                    cur_ms = std::min(cur_ms, time_step(c, !(mode & 2)));
+                    apply_choice(c, classes[key], t);
+                    finalize_tiles(c);
+                    alt_ms = std::min(alt_ms, time_step(c, !(mode & 2)));
+                }
+                if (alt_ms < 0.98f * cur_ms) refine[o.second] = a;
+                else apply_choice(c, classes[key], now);
             }
         }
-        char line[96];
-        snprintf(line, sizeof line, "%s|%d", ctx_key, mode);
+        std::string line = ctx_key;
+        line += "|" + std::to_string(mode);
+        for (int r : refine) line += " " + std::to_string(r);
         append_tune_line(path, line);
     }
     apply_all(mode);
+    {
+        int i = 0;
+        for (const auto& kv : classes) {
+            const int r = refine[i++];
+            if (r >= 0 && r < chosen[kv.first].nalt) apply_choice(c, kv.second, chosen[kv.first].alt[r]);
+        }
+    }
     c->fork_groups = !(mode & 2);
 }
 

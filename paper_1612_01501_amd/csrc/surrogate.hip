@@ -90,6 +90,14 @@ SurrArgs surr_args(infoli_ctx* c, const infoli_drift_cfg& dc, int64_t macro_inde
     a.macro_index = macro_index;
     a.list = static_cast<PlainEntry*>(c->surr.list);
     a.list_count = c->surr.list_count;
+    // checked cells this macro step: (cell + macro_index) % sample_every == 0
+    a.check_first = 0;
+    a.n_checks = 0;
+    if (dc.mode == INFOLI_SURROGATE_MLP && dc.sample_every > 0) {
+        const int64_t S = dc.sample_every;
+        a.check_first = (S - macro_index % S) % S;
+        a.n_checks = a.check_first < c->total_cells ? (c->total_cells - 1 - a.check_first) / S + 1 : 0;
+    }
     return a;
 }
 

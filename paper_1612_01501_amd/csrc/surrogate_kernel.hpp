@@ -43,8 +43,12 @@ struct SurrArgs {
     int32_t hold_steps;         // macro steps a flagged cell stays on the plain method
     int32_t mode;               // 0 surrogate, 1 plain for every cell (gap held 4 steps)
     int64_t macro_index;
-    struct PlainEntry* list;    // cells for the plain method this macro step
-    unsigned int* list_count;   // zeroed by the macro step's gap launch
+    struct PlainEntry* list;    // cells for the plain method this macro step: the checked cells
+                                // first (cell check_first + i * sample_every at slot i), then
+                                // the others, appended
+    unsigned int* list_count;   // appended entries; zeroed by the macro step's gap launch
+    int64_t check_first;        // first checked cell of this macro step
+    int64_t n_checks;           // checked cells (0 when sample_every == 0)
 };
 
 // A cell handed to the plain method, with the MLP's candidate voltages (used
@@ -138,10 +142,8 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
         const bool guard = s.mode == 0 && (!in_regime || cell_far || cand_bad);
         const bool plain = s.mode == 1 || hold > 0 || check || guard;
 
-        // counters, one atomic per wave (group-0 lanes stand for their cells)
+        // guarded cells counted with one atomic per wave that has any
         const bool lead = g == 0 && live;
-        const unsigned long long n_plain = __popcll(__ballot(lead && plain));
-        const unsigned long long n_check = __popcll(__ballot(lead && s.mode == 0 && check));
         const unsigned long long n_guard = __popcll(__ballot(lead && guard));
 
         if (!plain) {
@@ -164,22 +166,22 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
                 }
             }
         }
-        // cells for the plain method: appended to the list (one atomic per wave)
-        const unsigned long long pmask = __ballot(lead && plain);
+        // cells for the plain method: a checked cell at its own slot (no
+        // atomic); the others appended after the checked ones, one atomic per
+        // wave that has any
+        if (lead && plain && check)
+            s.list[(int32_t)(c - s.check_first) / s.sample_every] = PlainEntry{(int32_t)c, mvd, mvs, mva};
+        const unsigned long long pmask = __ballot(lead && plain && !check);
         if (pmask) {
             unsigned int base = 0;
             if (l == 0) base = atomicAdd(s.list_count, (unsigned int)__popcll(pmask));
             base = __shfl(base, 0, 64);
-            if (lead && plain) {
+            if (lead && plain && !check) {
                 const unsigned int pos = base + (unsigned int)__popcll(pmask & ((1ull << l) - 1ull));
-                s.list[pos] = PlainEntry{(int32_t)c, mvd, mvs, mva};
+                s.list[s.n_checks + pos] = PlainEntry{(int32_t)c, mvd, mvs, mva};
             }
         }
-        if (l == 0) {
-            if (n_plain) atomicAdd(&s.counters[0], n_plain);
-            if (n_check) atomicAdd(&s.counters[1], n_check);
-            if (n_guard) atomicAdd(&s.counters[3], n_guard);
-        }
+        if (l == 0 && n_guard) atomicAdd(&s.counters[3], n_guard);
     }
 }
 
@@ -189,10 +191,14 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
 // method). One thread per listed cell.
 static __global__ __launch_bounds__(256) void k_plain_list(StepArgs a, SurrArgs s, const float* __restrict__ xin,
                                                            float* __restrict__ xout, int64_t step0) {
-    const unsigned int count = *s.list_count;
+    const int64_t count = s.n_checks + *s.list_count;   // checked cells first, then the appended
     const InstDesc& d = a.inst[0];
-    for (unsigned int b = blockIdx.x * blockDim.x; b < count; b += gridDim.x * blockDim.x) {
-        const unsigned int i = b + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&s.counters[0], (unsigned long long)count);
+        if (s.n_checks) atomicAdd(&s.counters[1], (unsigned long long)s.n_checks);
+    }
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < count; b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = b + threadIdx.x;
         bool flagged = false;
         if (i < count) {
             const PlainEntry e = s.list[i];
@@ -226,7 +232,7 @@ static __global__ __launch_bounds__(256) void k_plain_list(StepArgs a, SurrArgs 
             if (!isfinite(chk)) atomicOr(a.flags, 1);
             const int hold = s.hold[c];
             int new_hold = hold > 0 ? hold - 1 : 0;
-            const bool check = s.sample_every > 0 && ((c + s.macro_index) % s.sample_every) == 0;
+            const bool check = i < s.n_checks;
             if (check) {
                 const float dev = fmaxf(fabsf(e.vd - x[SV_VD]), fmaxf(fabsf(e.vs - x[SV_VS]), fabsf(e.va - x[SV_VA])));
                 if (!(dev <= s.theta_mv)) {

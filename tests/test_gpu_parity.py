@@ -457,10 +457,13 @@ def test_autotuner_times_caches_and_stays_exact(infoli, o32, tmp_path, monkeypat
             assert info["tuned"] == 0 and info["tune_cached"] == 2
     lines = (tmp_path / "tune.txt").read_text().strip().splitlines()
     # per class its best, best 256-thread and best non-chunked 256-thread
-    # shapes, then the whole-step choice
-    assert len(lines) == 7 and all("|" in l for l in lines)
-    assert sum(l.startswith("ctx ") for l in lines) == 1 and sum("#256|" in l for l in lines) == 2
-    assert sum("#256nc|" in l for l in lines) == 2
+    # shapes and up to three 256-thread alternatives; then the whole-step
+    # choice for the mix (mode and one refinement per class)
+    assert all("|" in l for l in lines)
+    ctx = [l for l in lines if l.startswith("ctx ")]
+    assert len(ctx) == 1 and len(ctx[0].split("|")[1].split()) == 1 + 2
+    assert sum("#256|" in l for l in lines) == 2 and sum("#256nc|" in l for l in lines) == 2
+    assert 2 <= sum("#a" in l for l in lines) <= 6
     for k, net in enumerate(nets):
         np.testing.assert_array_equal(out[0][k], out[1][k])
         ref = o32.run(net, 300, x0=x0s[k])["x"]
