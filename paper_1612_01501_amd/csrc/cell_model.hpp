@@ -37,12 +37,15 @@ __device__ __forceinline__ float boltz(float v, float vh, float k) {
     return 1.0f / (1.0f + expf(-(v - vh) / k));
 }
 
-// Next state of one cell. x: previous state, igap: gap current leaving the
-// dendrite, iapp: evoked input into the dendrite, dt in ms.
-__device__ __forceinline__ void cell_step(const CellParams& p, const float* __restrict__ x,
-                                          float igap, float iapp, float dt,
-                                          float* __restrict__ y) {
-    const float vd = x[SV_VD], vs = x[SV_VS], va = x[SV_VA];
+// The update is Jacobi (every derivative from the previous-step state), so
+// each compartment's next state is a function of x alone; the three parts
+// below write disjoint entries of y and together are cell_step.
+
+// Dendrite part: y[Vd, Ca, r, s, q]. igap: gap current leaving the dendrite,
+// iapp: evoked input into the dendrite, dt in ms.
+__device__ __forceinline__ void cell_step_dendrite(const CellParams& p, const float* __restrict__ x,
+                                                   float igap, float iapp, float dt, float* __restrict__ y) {
+    const float vd = x[SV_VD], vs = x[SV_VS];
 
     // Dendrite: high-threshold Ca (r^2), Ca-activated K (s), h current (q),
     // leak, coupling to the soma, gap junctions and the evoked input.
@@ -65,6 +68,19 @@ __device__ __forceinline__ void cell_step(const CellParams& p, const float* __re
     const float qinf = boltz(vd, -80.0f, -4.0f);
     const float rq = expf(-0.086f * vd - 14.6f) + expf(0.070f * vd - 1.87f);  // 1/tau_q
     const float dq = (qinf - x[SV_Q]) * rq;
+
+    // C_m = 1 uF/cm^2: dV/dt equals the net inward current density.
+    y[SV_VD] = vd + dt * dvd;
+    y[SV_CA] = x[SV_CA] + dt * dca;
+    y[SV_R] = x[SV_R] + dt * dr;
+    y[SV_S] = x[SV_S] + dt * ds;
+    y[SV_Q] = x[SV_Q] + dt * dq;
+}
+
+// Soma part: y[Vs, k, l, h, n, x].
+__device__ __forceinline__ void cell_step_soma(const CellParams& p, const float* __restrict__ x, float dt,
+                                               float* __restrict__ y) {
+    const float vd = x[SV_VD], vs = x[SV_VS], va = x[SV_VA];
 
     // Soma: low-threshold Ca (k^3 l), Na (instantaneous m^3, h), delayed
     // rectifier K (n^4), K (x^4), leak, coupling to dendrite and axon.
@@ -92,6 +108,19 @@ __device__ __forceinline__ void cell_step(const CellParams& p, const float* __re
     const float bxs = 1.69f * expf(-0.0125f * (vs + 35.0f));
     const float dx = axs - (axs + bxs) * x[SV_X];
 
+    y[SV_VS] = vs + dt * dvs;
+    y[SV_K] = kk + dt * dk;
+    y[SV_L] = x[SV_L] + dt * dl;
+    y[SV_H] = x[SV_H] + dt * dh;
+    y[SV_N] = x[SV_N] + dt * dn;
+    y[SV_X] = x[SV_X] + dt * dx;
+}
+
+// Axon part: y[Va, ha, xa].
+__device__ __forceinline__ void cell_step_axon(const CellParams& p, const float* __restrict__ x, float dt,
+                                               float* __restrict__ y) {
+    const float vs = x[SV_VS], va = x[SV_VA];
+
     // Axon: Na (instantaneous m^3, h), K (x^4), leak, coupling to the soma.
     const float ma = boltz(va, -30.0f, 5.5f);
     const float inaa = p.gNaA * ma * ma * ma * x[SV_HA] * (va - p.eNa);
@@ -107,21 +136,19 @@ __device__ __forceinline__ void cell_step(const CellParams& p, const float* __re
     const float bxa = 1.69f * expf(-0.0125f * (va + 35.0f));
     const float dxa = axa - (axa + bxa) * x[SV_XA];
 
-    // C_m = 1 uF/cm^2: dV/dt equals the net inward current density.
-    y[SV_VD] = vd + dt * dvd;
-    y[SV_CA] = x[SV_CA] + dt * dca;
-    y[SV_R] = x[SV_R] + dt * dr;
-    y[SV_S] = x[SV_S] + dt * ds;
-    y[SV_Q] = x[SV_Q] + dt * dq;
-    y[SV_VS] = vs + dt * dvs;
-    y[SV_K] = kk + dt * dk;
-    y[SV_L] = x[SV_L] + dt * dl;
-    y[SV_H] = x[SV_H] + dt * dh;
-    y[SV_N] = x[SV_N] + dt * dn;
-    y[SV_X] = x[SV_X] + dt * dx;
     y[SV_VA] = va + dt * dva;
     y[SV_HA] = x[SV_HA] + dt * dha;
     y[SV_XA] = x[SV_XA] + dt * dxa;
+}
+
+// Next state of one cell. x: previous state, igap: gap current leaving the
+// dendrite, iapp: evoked input into the dendrite, dt in ms.
+__device__ __forceinline__ void cell_step(const CellParams& p, const float* __restrict__ x,
+                                          float igap, float iapp, float dt,
+                                          float* __restrict__ y) {
+    cell_step_dendrite(p, x, igap, iapp, dt, y);
+    cell_step_soma(p, x, dt, y);
+    cell_step_axon(p, x, dt, y);
 }
 
 }  // namespace infoli

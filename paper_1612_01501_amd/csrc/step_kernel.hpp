@@ -745,10 +745,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
     const float* vd = xin + (int64_t)SV_VD * a.stride + d.cell_off;
     const int nrows = t.row1 - t.row0;
 
-    // Thread k < nrows owns cell row0 + k for the compartment update; its
-    // state loads are issued first so their latency overlaps the gap work.
-    const bool own = (int)threadIdx.x < nrows && !a.gap_only;
-    const int li = t.row0 + threadIdx.x;
+    // The compartment update of cell row0 + k: with at most 64 rows, lane k
+    // of wave 0 advances its dendrite and axon and lane k of wave 1 its soma
+    // (the update is Jacobi, so the parts are independent and their
+    // arithmetic is cell_step's); else thread k advances the whole cell.
+    // State loads are issued first so their latency overlaps the gap work.
+    const bool split = nrows <= 64;
+    const int k_own = split ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+    const int part = split ? (int)(threadIdx.x >> 6) : 0;   // 0: dendrite + axon (or all), 1: soma
+    const bool own = k_own < nrows && part < 2 && !a.gap_only;
+    const int li = t.row0 + k_own;
     const int64_t cell = d.cell_off + li;
     float x[NSV];
     float iapp = 0.0f;
@@ -775,9 +781,39 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
         for (int k = threadIdx.x; k < nrows; k += BLOCK) a.igap_out[d.cell_off + t.row0 + k] = s_ig[k];
         return;
     }
-    if (own) {
+    if (own && split) {
         float y[NSV];
-        cell_step(d.p, x, s_ig[threadIdx.x], iapp, a.dt, y);
+        float chk = 0.0f;
+        if (part == 0) {
+            cell_step_dendrite(d.p, x, s_ig[k_own], iapp, a.dt, y);
+            cell_step_axon(d.p, x, a.dt, y);
+#pragma unroll
+            for (int v : {SV_VD, SV_CA, SV_R, SV_S, SV_Q, SV_VA, SV_HA, SV_XA}) {
+                xout[v * a.stride + cell] = y[v];
+                chk += y[v];
+            }
+        } else {
+            cell_step_soma(d.p, x, a.dt, y);
+#pragma unroll
+            for (int v : {SV_VS, SV_K, SV_L, SV_H, SV_N, SV_X}) {
+                xout[v * a.stride + cell] = y[v];
+                chk += y[v];
+            }
+        }
+        if (a.dry) return;
+        if (!isfinite(chk)) atomicOr(a.flags, 1);
+        // axon output (wave 0): upward 0 mV crossing, time interpolated within the step
+        if (part == 0 && x[SV_VA] < 0.0f && y[SV_VA] >= 0.0f) {
+            const int c = a.spike_count[cell];
+            if (a.spike_cap > 0) {
+                const float frac = (0.0f - x[SV_VA]) / (y[SV_VA] - x[SV_VA]);
+                a.spike_times[cell * a.spike_cap + (c % a.spike_cap)] = ((float)step + frac) * a.dt;
+            }
+            a.spike_count[cell] = c + 1;
+        }
+    } else if (own) {
+        float y[NSV];
+        cell_step(d.p, x, s_ig[k_own], iapp, a.dt, y);
         float chk = 0.0f;
 #pragma unroll
         for (int v = 0; v < NSV; ++v) {

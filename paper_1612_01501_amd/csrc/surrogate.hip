@@ -120,9 +120,9 @@ void launch_macro(infoli_ctx* c, hipStream_t st, const infoli_drift_cfg& dc, int
     const unsigned blocks = (unsigned)std::min<int64_t>((cells + 63) / 64, 2 * (int64_t)c->n_cu);
     hipLaunchKernelGGL(k_surrogate_step, dim3(blocks), dim3(256), 0, st, a, s, c->state[from],
                        c->state[from ^ 1], step0, cells);
-    const unsigned lblocks = (unsigned)std::min<int64_t>((cells + 255) / 256, 512);
-    hipLaunchKernelGGL(k_plain_list, dim3(lblocks), dim3(256), 0, st, a, s, c->state[from], c->state[from ^ 1],
-                       step0);
+    const unsigned lblocks = (unsigned)std::min<int64_t>((cells + 63) / 64, 2048);
+    hipLaunchKernelGGL(k_plain_list, dim3(lblocks), dim3(kListBlock), 0, st, a, s, c->state[from],
+                       c->state[from ^ 1], step0);
 }
 
 }  // namespace

@@ -188,62 +188,94 @@ static __global__ __launch_bounds__(256) void k_surrogate_step(StepArgs a, SurrA
 // The listed cells: four plain forward-Euler steps with the macro step's gap
 // current held, spike detection, and for checked cells the drift test
 // against the MLP candidate (past theta: hold_steps macro steps of plain
-// method). One thread per listed cell.
-static __global__ __launch_bounds__(256) void k_plain_list(StepArgs a, SurrArgs s, const float* __restrict__ xin,
-                                                           float* __restrict__ xout, int64_t step0) {
+// method). A workgroup of two waves takes 64 listed cells: wave 0 advances
+// their dendrite and axon, wave 1 their soma (cell_step's arithmetic, split
+// by compartment); the state is exchanged through LDS after every step.
+constexpr int kListBlock = 128;
+
+static __global__ __launch_bounds__(kListBlock) void k_plain_list(StepArgs a, SurrArgs s,
+                                                                  const float* __restrict__ xin,
+                                                                  float* __restrict__ xout, int64_t step0) {
+    __shared__ float s_x[2][NSV][64];
     const int64_t count = s.n_checks + *s.list_count;   // checked cells first, then the appended
     const InstDesc& d = a.inst[0];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         atomicAdd(&s.counters[0], (unsigned long long)count);
         if (s.n_checks) atomicAdd(&s.counters[1], (unsigned long long)s.n_checks);
     }
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < count; b += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = b + threadIdx.x;
-        bool flagged = false;
-        if (i < count) {
-            const PlainEntry e = s.list[i];
-            const int64_t c = e.cell;
-            const int li = (int)(c - d.cell_off);
-            const float ig = s.igap[c];
-            float x[NSV], yv[NSV];
+    const int lane = threadIdx.x & 63;
+    const int part = threadIdx.x >> 6;        // 0: dendrite and axon, 1: soma
+    for (int64_t b = (int64_t)blockIdx.x * 64; b < count; b += (int64_t)gridDim.x * 64) {
+        const int64_t i = b + lane;
+        const bool act = i < count;
+        PlainEntry e{0, 0.0f, 0.0f, 0.0f};
+        if (act) e = s.list[i];
+        const int64_t c = e.cell;            // cell 0 for idle lanes: read, never written
+        const int li = (int)(c - d.cell_off);
+        const float ig = s.igap[c];
+        float x[NSV], y[NSV];
 #pragma unroll
-            for (int v = 0; v < NSV; ++v) x[v] = xin[v * a.stride + c];
-            int cnt = a.spike_count[c];
-            for (int k = 0; k < kMacro; ++k) {
-                const int64_t st = step0 + k;
-                cell_step(d.p, x, ig, evoked_input(a, d, st, li, c), a.dt, yv);
-                if (x[SV_VA] < 0.0f && yv[SV_VA] >= 0.0f) {
-                    if (a.spike_cap > 0) {
-                        const float frac = (0.0f - x[SV_VA]) / (yv[SV_VA] - x[SV_VA]);
+        for (int v = 0; v < NSV; ++v) x[v] = xin[v * a.stride + c];
+        int cnt = part == 0 ? a.spike_count[c] : 0;
+        for (int k = 0; k < kMacro; ++k) {
+            const int64_t st = step0 + k;
+            if (part == 0) {
+                cell_step_dendrite(d.p, x, ig, evoked_input(a, d, st, li, c), a.dt, y);
+                cell_step_axon(d.p, x, a.dt, y);
+                if (x[SV_VA] < 0.0f && y[SV_VA] >= 0.0f) {
+                    if (act && a.spike_cap > 0) {
+                        const float frac = (0.0f - x[SV_VA]) / (y[SV_VA] - x[SV_VA]);
                         a.spike_times[c * a.spike_cap + (cnt % a.spike_cap)] = ((float)st + frac) * a.dt;
                     }
                     ++cnt;
                 }
 #pragma unroll
-                for (int v = 0; v < NSV; ++v) x[v] = yv[v];
-            }
-            a.spike_count[c] = cnt;
-            float chk = 0.0f;
+                for (int v : {SV_VD, SV_CA, SV_R, SV_S, SV_Q, SV_VA, SV_HA, SV_XA}) s_x[k & 1][v][lane] = y[v];
+            } else {
+                cell_step_soma(d.p, x, a.dt, y);
 #pragma unroll
-            for (int v = 0; v < NSV; ++v) {
-                xout[v * a.stride + c] = x[v];
-                chk += x[v];
+                for (int v : {SV_VS, SV_K, SV_L, SV_H, SV_N, SV_X}) s_x[k & 1][v][lane] = y[v];
             }
-            if (!isfinite(chk)) atomicOr(a.flags, 1);
-            const int hold = s.hold[c];
-            int new_hold = hold > 0 ? hold - 1 : 0;
-            const bool check = i < s.n_checks;
-            if (check) {
-                const float dev = fmaxf(fabsf(e.vd - x[SV_VD]), fmaxf(fabsf(e.vs - x[SV_VS]), fabsf(e.va - x[SV_VA])));
-                if (!(dev <= s.theta_mv)) {
-                    new_hold = s.hold_steps;
-                    flagged = true;
+            // one barrier per step: buffer k & 1 is rewritten two steps later,
+            // after every thread has passed the next barrier
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < NSV; ++v) x[v] = s_x[k & 1][v][lane];
+        }
+        bool flagged = false;
+        if (act) {
+            float chk = 0.0f;
+            if (part == 0) {
+                a.spike_count[c] = cnt;
+#pragma unroll
+                for (int v : {SV_VD, SV_CA, SV_R, SV_S, SV_Q, SV_VA, SV_HA, SV_XA}) {
+                    xout[v * a.stride + c] = x[v];
+                    chk += x[v];
+                }
+            } else {
+#pragma unroll
+                for (int v : {SV_VS, SV_K, SV_L, SV_H, SV_N, SV_X}) {
+                    xout[v * a.stride + c] = x[v];
+                    chk += x[v];
                 }
             }
-            if (new_hold != hold) s.hold[c] = new_hold;
+            if (!isfinite(chk)) atomicOr(a.flags, 1);
+            if (part == 0) {
+                const int hold = s.hold[c];
+                int new_hold = hold > 0 ? hold - 1 : 0;
+                if (i < s.n_checks) {
+                    const float dev =
+                        fmaxf(fabsf(e.vd - x[SV_VD]), fmaxf(fabsf(e.vs - x[SV_VS]), fabsf(e.va - x[SV_VA])));
+                    if (!(dev <= s.theta_mv)) {
+                        new_hold = s.hold_steps;
+                        flagged = true;
+                    }
+                }
+                if (new_hold != hold) s.hold[c] = new_hold;
+            }
         }
         const unsigned long long fm = __ballot(flagged);
-        if ((threadIdx.x & 63) == 0 && fm) atomicAdd(&s.counters[2], (unsigned long long)__popcll(fm));
+        if (lane == 0 && fm) atomicAdd(&s.counters[2], (unsigned long long)__popcll(fm));
     }
 }
 
