@@ -382,3 +382,32 @@ def test_spike_time_interpolation(o64):
     for k, n in enumerate(ups):
         t = (n + (0 - va[n]) / (va[n + 1] - va[n])) * 0.05
         assert r["times"][0, k] == pytest.approx(t, rel=1e-12)
+
+
+# ------------------------------------------------------------------ work counts
+def test_instrumented_operation_counts(tmp_path):
+    """The oracle body compiled with a counting number type: one cell-step's
+    right-hand side evaluates exactly 21 exp/expm1 (dendrite 5: the two r
+    rates, the q sigmoid and q's two-exp rate; soma 11: five sigmoids, l's two
+    exps, h, n and x's two rates; axon 5: two sigmoids, h_a and x_a's two
+    rates) and 224 arithmetic operations in all; one
+    gap-junction pair term is 9 operations with one exp (Algorithm 1:
+    subtract, square, negate, divide by 100, exp, scale by 0.8, add 0.2,
+    times dV, times w). Table 1's 859 operations per cell-step counts each exp
+    as a routine of ~31 operations (203 + 21 x 31 = 854); its ~12 per
+    connection counts the exp as one (9 + the accumulation)."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no g++")
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "count_ops")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-fopenmp", "-o", exe,
+                    os.path.join(here, "opcount", "count_ops.cpp")], check=True, capture_output=True)
+    params = " ".join(repr(float(v)) for v in I.DEFAULT_PARAMS)
+    out = subprocess.run([exe], input=params, text=True, check=True, capture_output=True).stdout.split()
+    rhs_ops, rhs_tr, pair_ops, pair_tr = map(int, out)
+    assert rhs_tr == 21 and rhs_ops == 224
+    assert pair_tr == 1 and pair_ops == 9
+    assert abs((rhs_ops - rhs_tr) + 31 * rhs_tr - 859) < 20
