@@ -20,6 +20,8 @@ Workloads (--workload):
            ablations (held gap without MLP; MLP without fallback)
   csr65k   the surr65k network stepped by the plain method only, 2,000
            steps (the large-CSR, column-blocked gap path)
+  ngj16m   2^24 uncoupled cells: the compartment update alone, 1.95 GB of
+           state per step (beyond the 256 MB cache), 200 steps
   batch256 256 independent networks, N_k ~ U{64..2048}, density ~ U{5, 25,
            100 %} (100 % all-to-all, else ER CSR), g_k ~ U[0.01, 0.08],
            pulse amplitude ~ U[2, 10] uA/cm^2, 10,000 steps, one launch per
@@ -78,6 +80,7 @@ WORKLOADS = {
     "batch256": dict(steps=10000, warmup=200),
     "surr65k": dict(steps=10000, warmup=100),
     "csr65k": dict(steps=2000, warmup=100),
+    "ngj16m": dict(steps=200, warmup=10),
 }
 
 
@@ -102,6 +105,12 @@ def build_workload(name):
         nets = [I.config4()]
         desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR), g=3.84e-3 mS/cm^2, "
                 "bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms; plain method")
+    elif name == "ngj16m":
+        n = 1 << 24
+        nets = [I.Network(n=n, conn="none", jitter=I.voltage_jitter(n, 2000), bias=I.input_bias(n, 3000),
+                          pulses=[I.Pulse(400, 500, 6.0)], label="ngj_n16m")]
+        desc = ("16,777,216 uncoupled cells (no gap junctions: the compartment update alone, 1.95 GB of "
+                "state per step, beyond the 256 MB cache), bias N(0,0.5), jitter, FP32, dt=0.05 ms")
     elif name == "uni16k":
         nets = [I.config2()]
         desc = "16,384 cells all-to-all, g=0.04*96/N mS/cm^2, +-1 mV jitter, no input, FP32, dt=0.05 ms"
@@ -118,6 +127,10 @@ def build_workload(name):
 LANE_SLOTS_PER_S = 256 * 64 * 2.4e9
 EXP_SLOTS = 2
 UNIFORM_SLOTS_PER_PAIR = 3 + EXP_SLOTS
+# Compartment update per cell-step: 276 VALU instructions in its compiled
+# form, of which 39 transcendental (21 v_exp_f32, 18 v_rcp_f32) at half rate,
+# costing a second slot each.
+CELL_SLOTS = 276 + 39
 
 
 def algorithmic_bytes(nets):
@@ -143,19 +156,21 @@ def algorithmic_bytes(nets):
 CSR_SLOTS_PER_EDGE = 9
 
 
-def step_kernel_name(info):
-    """The kernel(s) one step launches, from the context's launch groups."""
+def step_kernel_name(info, nets):
+    """The kernel(s) one step launches, from the context's launch groups
+    (networks without gap junctions alone take the compartment-only variant)."""
     if info["step_mode"] == 3:
         return "infoli::k_persist"
     wide, total = info["n_tiles_wide"], info["n_tiles"]
+    narrow = "infoli::k_step<256, true>" if all(n.conn == "none" for n in nets) else "infoli::k_step<256, false>"
     if wide == 0:
-        return "infoli::k_step<256>"
+        return narrow
     if wide == total:
-        return "infoli::k_step<1024>"
-    return "infoli::k_step<256> + infoli::k_step<1024> (concurrent graph branches)"
+        return "infoli::k_step<1024, false>"
+    return f"{narrow} + infoli::k_step<1024, false> (concurrent graph branches)"
 
 
-def roofline(nets, launch_s, kernel="infoli::k_step<256>"):
+def roofline(nets, launch_s, kernel="infoli::k_step<256, false>"):
     kinds = {n.conn for n in nets}
     if len(kinds) > 1:
         # mixed batch: issue slots of the pair/edge work against the lane-slot peak
@@ -170,14 +185,23 @@ def roofline(nets, launch_s, kernel="infoli::k_step<256>"):
         pairs = sum(n.n * n.n for n in nets)       # the kernel evaluates the diagonal too
         achieved = pairs / launch_s / 1e9
         peak = LANE_SLOTS_PER_S / UNIFORM_SLOTS_PER_PAIR / 1e9
+        # the exp-shared minimum: f(dV) = f(-dV), so one exp serves both directions
+        peak_shared = LANE_SLOTS_PER_S / (UNIFORM_SLOTS_PER_PAIR - EXP_SLOTS / 2) / 1e9
         return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
                 "frac": achieved / peak, "traffic": None, "kernel": kernel,
-                "slots_per_pair": UNIFORM_SLOTS_PER_PAIR, "pairs_per_launch": pairs}
+                "slots_per_pair": UNIFORM_SLOTS_PER_PAIR, "pairs_per_launch": pairs,
+                "frac_vs_exp_shared_minimum": achieved / peak_shared}
     abytes = algorithmic_bytes(nets)
     achieved = abytes / launch_s / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
-            "algorithmic_bytes_per_launch": abytes}
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+           "algorithmic_bytes_per_launch": abytes}
+    if all(n.conn == "none" for n in nets):
+        # issue-slot use of the compartment update's own arithmetic
+        cells = sum(n.n for n in nets)
+        out["alu_frac"] = CELL_SLOTS * cells / launch_s / LANE_SLOTS_PER_S
+        out["alu_slots_per_cell_step"] = CELL_SLOTS
+    return out
 
 
 def cpu_baseline(nets, budget_s=15.0):
@@ -196,9 +220,21 @@ def cpu_baseline(nets, budget_s=15.0):
         o.run(n, steps, x0=x)
     dt = time.perf_counter() - t0
     cells = sum(n.n for n in nets)
-    return {"value": cells * steps / dt, "unit": "cell-steps/s", "cores": max_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} steps of the same {len(nets)} network(s) ({cells} cells) from the initial state, fp32 oracle, OpenMP over cells"}
+    cores = max_threads()           # before the one-thread leg changes it
+    # the same on one thread, within a third of the budget (skipped when one
+    # step alone would take longer)
+    est1 = dt / steps * cores
+    single, steps1 = None, 0
+    if est1 <= budget_s / 3.0:
+        steps1 = int(max(1, min(steps, (budget_s / 3.0) / est1)))
+        t0 = time.perf_counter()
+        for n, x in zip(nets, x0s):
+            o.run(n, steps1, x0=x, threads=1)
+        single = cells * steps1 / (time.perf_counter() - t0)
+    return {"value": cells * steps / dt, "unit": "cell-steps/s", "cores": cores,
+            "kind": "oracle", "single_thread_value": single,
+            "sample": f"{steps} steps ({steps1} on one thread) of the same {len(nets)} network(s) ({cells} cells) "
+                      "from the initial state, fp32 oracle, OpenMP over cells"}
 
 
 def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
@@ -279,7 +315,7 @@ def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
         "ablation_mlp_no_fallback": {"speedup": t_plain / nofb["ms"], "rmse_mv": nofb["rmse_mv"],
                                      "spike_time_err_ms": nofb["spike_time_err_ms"]},
         "training": {**rep, "wall_s": train_wall},
-        "roofline": roofline(nets, t_plain * 1e-3 / total_steps, step_kernel_name(info)),
+        "roofline": roofline(nets, t_plain * 1e-3 / total_steps, step_kernel_name(info, nets)),
     }
     out["roofline"]["traffic"] = measured_traffic(args.workload)
     if not args.no_cpu_baseline:
@@ -288,14 +324,23 @@ def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
 
 
 def copy_probe(mb, torch):
-    """A plain device copy of known size (counter calibration for rocprofv3)."""
+    """A plain device copy of known size: HBM counter calibration for
+    rocprofv3, and the copy bandwidth this GPU reaches (HIP events)."""
     n = int(mb * 1024 * 1024 // 4)
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(5):
+    for _ in range(2):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / 3
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5,
+                      "copy_GBps_read_plus_write": 8 * n / s / 1e9}))
 
 
 def main():
@@ -369,7 +414,7 @@ def main():
                    "lanes_per_row": info["lanes_per_row"]},
         "gap_pairs_per_s": pairs * steps / wall,
         "device_ms_per_step": dev_ms / steps,
-        "roofline": roofline(nets, launch_s, step_kernel_name(info)),
+        "roofline": roofline(nets, launch_s, step_kernel_name(info, nets)),
     }
     out["roofline"]["traffic"] = measured_traffic(args.workload)
     if not args.no_cpu_baseline:

@@ -27,14 +27,45 @@ struct CellParams {
 };
 static_assert(sizeof(CellParams) == 20 * sizeof(float), "20 parameters");
 
-// x / (exp(x/s) - 1), continuous at x = 0 where it equals s.
-__device__ __forceinline__ float ratio_expm1(float x, float s) {
-    return (x == 0.0f) ? s : x / expm1f(x / s);
+// Arithmetic. Every exponential has an argument affine in one voltage,
+// written (v - v0) * a: it is evaluated as 2^((v - v0) * a log2 e) on the
+// transcendental unit (v_exp_f32, 1 ulp) with log2 e folded into the
+// constant at compile time; the subtraction first keeps the argument's
+// rounding relative to its own size. Divisions by a variable are a
+// reciprocal (v_rcp_f32, 1 ulp) and a multiply, by a constant a multiply by
+// its rounded reciprocal. Each result lies within a few ulp of the
+// correctly rounded one.
+constexpr double kLog2e = 1.4426950408889634074;
+
+// a log2(e), rounded once to fp32 (folded where a is a constant)
+__device__ __forceinline__ constexpr float l2(double a) { return float(a * kLog2e); }
+
+__device__ __forceinline__ float ex2(float t) { return __builtin_amdgcn_exp2f(t); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// exp((v - v0) * a), c = l2(a)
+__device__ __forceinline__ float exp_aff(float v, float v0, float c) { return ex2((v - v0) * c); }
+
+// Steady-state curve 1/(1 + exp(-(v - vh)/k)); c = l2(-1/k), k < 0 for
+// inactivation.
+__device__ __forceinline__ float boltz(float v, float vh, float c) {
+    return rcp(1.0f + exp_aff(v, vh, c));
 }
 
-// Steady-state curve 1/(1 + exp(-(v - vh)/k)); k < 0 for inactivation.
-__device__ __forceinline__ float boltz(float v, float vh, float k) {
-    return 1.0f / (1.0f + expf(-(v - vh) / k));
+// x / (exp(x/s) - 1) = s g(u), u = x/s, g(u) = u / (e^u - 1), continuous at
+// u = 0 where g = 1. For |u| < 1/2, g is its Bernoulli series
+// 1 - u/2 + u^2/12 - u^4/720 + u^6/30240 - u^8/1209600 (the next term is
+// below 1e-10 there), which avoids the cancellation in e^u - 1; else the
+// quotient itself.
+__device__ __forceinline__ float ratio_expm1(float x, float s) {
+    const float u = x * (1.0f / s);
+    const float u2 = u * u;
+    float q = fmaf(u2, -1.0f / 1209600.0f, 1.0f / 30240.0f);
+    q = fmaf(u2, q, -1.0f / 720.0f);
+    q = fmaf(u2, q, 1.0f / 12.0f);
+    const float series = fmaf(u2, q, fmaf(u, -0.5f, 1.0f));
+    const float direct = u * rcp(ex2(u * float(kLog2e)) - 1.0f);
+    return s * (fabsf(u) < 0.5f ? series : direct);
 }
 
 // The update is Jacobi (every derivative from the previous-step state), so
@@ -53,20 +84,21 @@ __device__ __forceinline__ void cell_step_dendrite(const CellParams& p, const fl
     const float ikca = p.gKCa * x[SV_S] * (vd - p.eK);
     const float ih = p.gH * x[SV_Q] * (vd - p.eH);
     const float ild = p.gLd * (vd - p.eL);
-    const float ids = p.gInt / (1.0f - p.p1) * (vd - vs);
+    const float ids = p.gInt * rcp(1.0f - p.p1) * (vd - vs);
     const float dvd = iapp - igap - ids - icah - ikca - ih - ild;
 
     const float dca = -3.0f * icah - 0.075f * x[SV_CA];
 
-    const float ar = 1.7f / (1.0f + expf(-(vd - 5.0f) / 13.9f));
+    const float ar = 1.7f * boltz(vd, 5.0f, l2(-1.0 / 13.9));
     const float br = 0.02f * ratio_expm1(vd + 8.5f, 5.0f);
-    const float dr = (ar - (ar + br) * x[SV_R]) / 5.0f;
+    const float dr = (ar - (ar + br) * x[SV_R]) * 0.2f;                  // tau_r = 5 ms
 
     const float as = fminf(0.00002f * x[SV_CA], 0.01f);
     const float ds = as - (as + 0.015f) * x[SV_S];
 
-    const float qinf = boltz(vd, -80.0f, -4.0f);
-    const float rq = expf(-0.086f * vd - 14.6f) + expf(0.070f * vd - 1.87f);  // 1/tau_q
+    const float qinf = boltz(vd, -80.0f, l2(1.0 / 4.0));
+    // 1/tau_q = exp(-0.086 vd - 14.6) + exp(0.070 vd - 1.87)
+    const float rq = exp_aff(vd, float(-14.6 / 0.086), l2(-0.086)) + exp_aff(vd, float(1.87 / 0.070), l2(0.070));
     const float dq = (qinf - x[SV_Q]) * rq;
 
     // C_m = 1 uF/cm^2: dV/dt equals the net inward current density.
@@ -86,26 +118,29 @@ __device__ __forceinline__ void cell_step_soma(const CellParams& p, const float*
     // rectifier K (n^4), K (x^4), leak, coupling to dendrite and axon.
     const float kk = x[SV_K];
     const float icaL = p.gCaL * kk * kk * kk * x[SV_L] * (vs - p.eCa);
-    const float ms = boltz(vs, -30.0f, 5.5f);
+    const float ms = boltz(vs, -30.0f, l2(-1.0 / 5.5));
     const float inas = p.gNaS * ms * ms * ms * x[SV_H] * (vs - p.eNa);
     const float n2 = x[SV_N] * x[SV_N];
     const float ikdr = p.gKdrS * n2 * n2 * (vs - p.eK);
     const float x2 = x[SV_X] * x[SV_X];
     const float iks = p.gKS * x2 * x2 * (vs - p.eK);
     const float ils = p.gLs * (vs - p.eL);
-    const float isd = p.gInt / p.p1 * (vs - vd);
-    const float isa = p.gInt / (1.0f - p.p2) * (vs - va);
+    const float isd = p.gInt * rcp(p.p1) * (vs - vd);
+    const float isa = p.gInt * rcp(1.0f - p.p2) * (vs - va);
     const float dvs = -(icaL + inas + ikdr + iks + ils + isd + isa);
 
-    const float dk = boltz(vs, -61.0f, 4.2f) - kk;                  // tau_k = 1 ms
-    const float taul = 20.0f * expf((vs + 160.0f) / 30.0f) / (1.0f + expf((vs + 84.0f) / 7.3f)) + 35.0f;
-    const float dl = (boltz(vs, -85.5f, -8.5f) - x[SV_L]) / taul;
-    const float tauh = 3.0f * expf(-(vs + 40.0f) / 33.0f);
-    const float dh = (boltz(vs, -70.0f, -5.8f) - x[SV_H]) / tauh;
-    const float taun = 5.0f + 47.0f * expf((vs + 50.0f) / 900.0f);
-    const float dn = (boltz(vs, -3.0f, 10.0f) - x[SV_N]) / taun;
+    const float dk = boltz(vs, -61.0f, l2(-1.0 / 4.2)) - kk;              // tau_k = 1 ms
+    // tau_l = 20 e1 / (1 + e2) + 35, e1 = exp((vs + 160)/30), e2 = exp((vs + 84)/7.3):
+    // 1/tau_l = (1 + e2) / (20 e1 + 35 (1 + e2))
+    const float e1 = exp_aff(vs, -160.0f, l2(1.0 / 30.0));
+    const float e2p1 = 1.0f + exp_aff(vs, -84.0f, l2(1.0 / 7.3));
+    const float dl = (boltz(vs, -85.5f, l2(1.0 / 8.5)) - x[SV_L]) * e2p1 * rcp(fmaf(20.0f, e1, 35.0f * e2p1));
+    // tau_h = 3 exp(-(vs + 40)/33): 1/tau_h = exp((vs + 40)/33) / 3
+    const float dh = (boltz(vs, -70.0f, l2(1.0 / 5.8)) - x[SV_H]) * (exp_aff(vs, -40.0f, l2(1.0 / 33.0)) * (1.0f / 3.0f));
+    const float taun = fmaf(47.0f, exp_aff(vs, -50.0f, l2(1.0 / 900.0)), 5.0f);
+    const float dn = (boltz(vs, -3.0f, l2(-1.0 / 10.0)) - x[SV_N]) * rcp(taun);
     const float axs = 0.13f * ratio_expm1(-(vs + 25.0f), 10.0f);
-    const float bxs = 1.69f * expf(-0.0125f * (vs + 35.0f));
+    const float bxs = 1.69f * exp_aff(vs, -35.0f, l2(-0.0125));
     const float dx = axs - (axs + bxs) * x[SV_X];
 
     y[SV_VS] = vs + dt * dvs;
@@ -122,18 +157,18 @@ __device__ __forceinline__ void cell_step_axon(const CellParams& p, const float*
     const float vs = x[SV_VS], va = x[SV_VA];
 
     // Axon: Na (instantaneous m^3, h), K (x^4), leak, coupling to the soma.
-    const float ma = boltz(va, -30.0f, 5.5f);
+    const float ma = boltz(va, -30.0f, l2(-1.0 / 5.5));
     const float inaa = p.gNaA * ma * ma * ma * x[SV_HA] * (va - p.eNa);
     const float xa2 = x[SV_XA] * x[SV_XA];
     const float ika = p.gKA * xa2 * xa2 * (va - p.eK);
     const float ila = p.gLa * (va - p.eL);
-    const float ias = p.gInt / p.p2 * (va - vs);
+    const float ias = p.gInt * rcp(p.p2) * (va - vs);
     const float dva = -(ika + ila + inaa + ias);
 
-    const float tauha = 1.5f * expf(-(va + 40.0f) / 33.0f);
-    const float dha = (boltz(va, -60.0f, -5.8f) - x[SV_HA]) / tauha;
+    // tau_ha = 1.5 exp(-(va + 40)/33): 1/tau_ha = exp((va + 40)/33) / 1.5
+    const float dha = (boltz(va, -60.0f, l2(1.0 / 5.8)) - x[SV_HA]) * (exp_aff(va, -40.0f, l2(1.0 / 33.0)) * (1.0f / 1.5f));
     const float axa = 0.13f * ratio_expm1(-(va + 25.0f), 10.0f);
-    const float bxa = 1.69f * expf(-0.0125f * (va + 35.0f));
+    const float bxa = 1.69f * exp_aff(va, -35.0f, l2(-0.0125));
     const float dxa = axa - (axa + bxa) * x[SV_XA];
 
     y[SV_VA] = va + dt * dva;

@@ -727,7 +727,10 @@ __device__ __forceinline__ float evoked_input(const StepArgs& a, const InstDesc&
     return iapp;
 }
 
-template <int BLOCK>
+// NOGAP: a launch whose tiles all belong to networks without gap junctions
+// (the compartment update alone, compiled without the gap paths and their
+// registers, so that more waves per SIMD keep state loads in flight).
+template <int BLOCK, bool NOGAP = false>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restrict__ xin,
                                                 float* __restrict__ xout, int64_t step_arg,
                                                 int32_t step_off) {
@@ -764,16 +767,20 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
         iapp = evoked_input(a, d, step, li, cell);
     }
 
-    switch (d.conn) {
-        case CONN_UNIFORM: gap_uniform<BLOCK>(a, d, t, vd, s_ig, s_v4, s_part, s_red); break;
-        case CONN_DENSE: gap_dense<BLOCK>(a, d, t, vd, s_ig); break;
-        case CONN_CSR:
-            if (d.bitmap) gap_bitmap<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
-            else gap_csr<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
-            break;
-        default:
-            for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
-            break;
+    if constexpr (NOGAP) {
+        for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
+    } else {
+        switch (d.conn) {
+            case CONN_UNIFORM: gap_uniform<BLOCK>(a, d, t, vd, s_ig, s_v4, s_part, s_red); break;
+            case CONN_DENSE: gap_dense<BLOCK>(a, d, t, vd, s_ig); break;
+            case CONN_CSR:
+                if (d.bitmap) gap_bitmap<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
+                else gap_csr<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
+                break;
+            default:
+                for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
+                break;
+        }
     }
     __syncthreads();
 
