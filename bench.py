@@ -162,15 +162,15 @@ def step_kernel_name(info, nets):
     if info["step_mode"] == 3:
         return "infoli::k_persist"
     wide, total = info["n_tiles_wide"], info["n_tiles"]
-    narrow = "infoli::k_step<256, true>" if all(n.conn == "none" for n in nets) else "infoli::k_step<256, false>"
+    narrow = "infoli::k_step<256, 1>" if all(n.conn == "none" for n in nets) else "infoli::k_step<256, 0>"
     if wide == 0:
         return narrow
     if wide == total:
-        return "infoli::k_step<1024, false>"
-    return f"{narrow} + infoli::k_step<1024, false> (concurrent graph branches)"
+        return "infoli::k_step<1024, 0>"
+    return f"{narrow} + infoli::k_step<1024, 0> (concurrent graph branches)"
 
 
-def roofline(nets, launch_s, kernel="infoli::k_step<256, false>"):
+def roofline(nets, launch_s, kernel="infoli::k_step<256, 0>"):
     kinds = {n.conn for n in nets}
     if len(kinds) > 1:
         # mixed batch: issue slots of the pair/edge work against the lane-slot peak

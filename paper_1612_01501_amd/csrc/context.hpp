@@ -64,7 +64,7 @@ struct TileGroup {
     Tile* d_tiles = nullptr;
     size_t cap = 0;                 // tiles d_tiles holds (reused when the tuner re-plans)
     size_t lds = 16;                // dynamic LDS bytes of the launch
-    bool nogap = false;             // every tile's network has no gap junctions
+    int var = 0;                    // step kernel variant for these tiles (kVarAll, kVarNoGap)
 };
 
 struct SurrogateState {
@@ -201,7 +201,7 @@ infoli_status guarded(infoli_ctx* ctx, F&& f) {
 
 StepArgs make_args(const infoli_ctx* c, bool device_step);
 void launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, int block, unsigned ntiles, size_t lds,
-                  int from, int64_t step_arg, int32_t off, bool nogap = false);
+                  int from, int64_t step_arg, int32_t off, int var = 0);
 // Both tile groups of one step (sequential on st, or forked onto the side
 // stream when `fork` and both groups have tiles).
 void launch_groups(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg, int32_t off,

@@ -46,6 +46,22 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 hbf16x8 __attribute__((ext_vector_type(8)));
+
+// D += A B over 32 of K (v_mfma_f32_16x16x32_bf16, one instruction for two
+// 16x16x16 products). Both operands hold, per lane, eight K slots that the
+// instruction pairs up between A and B; the sum over K does not depend on
+// which K each slot carries, so the slots take two 16-wide fragments side by
+// side: (a0, b0) for K rows k0.. and (a1, b1) for K rows k0 + 16.. in the
+// 16x16x16 layout. No activation moves between layers.
+__device__ __forceinline__ f32x4 mfma32(bf16x4 a0, bf16x4 a1, bf16x4 b0, bf16x4 b1, f32x4 c) {
+    const bf16x8s a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const bf16x8s b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(hbf16x8, a),
+                                                   __builtin_bit_cast(hbf16x8, b), c, 0, 0, 0);
+}
+
 __device__ __forceinline__ float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ __forceinline__ float silu_grad_f(float z) {
@@ -143,7 +159,8 @@ __device__ __forceinline__ f32x4 mlp_forward(MlpSmem s, const float* __restrict_
     for (int ob = 0; ob < 8; ++ob) {
         f32x4 z = bias4(params + kOffB2, ob);
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) z = mfma16(a_rows(s.w2, kS2, ob, kb), h1[kb], z);
+        for (int kb = 0; kb < 8; kb += 2)
+            z = mfma32(a_rows(s.w2, kS2, ob, kb), a_rows(s.w2, kS2, ob, kb + 1), h1[kb], h1[kb + 1], z);
         f32x4 h;
 #pragma unroll
         for (int e = 0; e < 4; ++e) h[e] = silu_f(z[e]);
@@ -155,7 +172,8 @@ __device__ __forceinline__ f32x4 mlp_forward(MlpSmem s, const float* __restrict_
     }
     f32x4 y = bias4(params + kOffB3, 0);
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) y = mfma16(a_rows(s.w3, kS3, 0, kb), h2[kb], y);
+    for (int kb = 0; kb < 8; kb += 2)
+        y = mfma32(a_rows(s.w3, kS3, 0, kb), a_rows(s.w3, kS3, 0, kb + 1), h2[kb], h2[kb + 1], y);
     if (h2_out)
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) h2_out[kb] = h2[kb];
@@ -247,7 +265,8 @@ static __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const float* __restr
     for (int ib = 0; ib < 8; ++ib) {
         f32x4 dh = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) dh = mfma16(a_cols(s.w2, kS2, ib, kb), dz2q[kb], dh);
+        for (int kb = 0; kb < 8; kb += 2)
+            dh = mfma32(a_cols(s.w2, kS2, ib, kb), a_cols(s.w2, kS2, ib, kb + 1), dz2q[kb], dz2q[kb + 1], dh);
         f32x4 dz;
 #pragma unroll
         for (int e = 0; e < 4; ++e) dz[e] = dh[e] * silu_grad_f(act.z1[ib][e]);

@@ -153,13 +153,13 @@ int pick_lanes(double mean_degree, int block) {
 }  // namespace
 
 void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, int block, unsigned ntiles,
-                             size_t lds, int from, int64_t step_arg, int32_t off, bool nogap) {
+                             size_t lds, int from, int64_t step_arg, int32_t off, int var) {
     if (ntiles == 0) return;
     if (block == 1024)
         hipLaunchKernelGGL(k_step<1024>, dim3(ntiles), dim3(1024), lds, st, a, c->state[from],
                            c->state[from ^ 1], step_arg, off);
-    else if (nogap)
-        hipLaunchKernelGGL((k_step<256, true>), dim3(ntiles), dim3(256), lds, st, a, c->state[from],
+    else if (var == kVarNoGap)
+        hipLaunchKernelGGL((k_step<256, kVarNoGap>), dim3(ntiles), dim3(256), lds, st, a, c->state[from],
                            c->state[from ^ 1], step_arg, off);
     else
         hipLaunchKernelGGL(k_step<256>, dim3(ntiles), dim3(256), lds, st, a, c->state[from],
@@ -178,7 +178,7 @@ void infoli_rt::launch_groups(infoli_ctx* c, hipStream_t st, const StepArgs& a, 
         StepArgs ag = a;
         ag.tiles = tg.d_tiles;
         hipStream_t s = (fork && both && g == 1) ? c->side_stream : st;
-        launch_tiles(c, s, ag, tg.block, (unsigned)tg.tiles.size(), tg.lds, from, step_arg, off, tg.nogap);
+        launch_tiles(c, s, ag, tg.block, (unsigned)tg.tiles.size(), tg.lds, from, step_arg, off, tg.var);
     }
     if (fork && both) {
         HIPX(hipEventRecord(c->join_ev, c->side_stream));
@@ -240,11 +240,12 @@ void finalize_tiles(infoli_ctx* c) {
         std::stable_sort(planned[g].begin(), planned[g].end(),
                          [](const auto& x, const auto& y) { return x.first > y.first; });
         tg.tiles.clear();
-        tg.nogap = true;
+        bool nogap = true;
         for (const auto& pt : planned[g]) {
             tg.tiles.push_back(pt.second);
-            if (c->inst[pt.second.inst].conn != CONN_NONE) tg.nogap = false;
+            if (c->inst[pt.second.inst].conn != CONN_NONE) nogap = false;
         }
+        tg.var = nogap ? kVarNoGap : kVarAll;
         if (tg.tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
         if (!tg.tiles.empty()) {
             if (tg.tiles.size() > tg.cap) {

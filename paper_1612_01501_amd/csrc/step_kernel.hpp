@@ -727,10 +727,13 @@ __device__ __forceinline__ float evoked_input(const StepArgs& a, const InstDesc&
     return iapp;
 }
 
-// NOGAP: a launch whose tiles all belong to networks without gap junctions
-// (the compartment update alone, compiled without the gap paths and their
-// registers, so that more waves per SIMD keep state loads in flight).
-template <int BLOCK, bool NOGAP = false>
+// Kernel variants by the tiles a launch holds. kVarAll: any tile. kVarNoGap:
+// every tile belongs to a network without gap junctions (the compartment
+// update alone), compiled without the gap paths and their registers, so that
+// more waves per SIMD keep state loads in flight.
+enum : int { kVarAll = 0, kVarNoGap = 1 };
+
+template <int BLOCK, int VAR = kVarAll>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restrict__ xin,
                                                 float* __restrict__ xout, int64_t step_arg,
                                                 int32_t step_off) {
@@ -767,7 +770,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
         iapp = evoked_input(a, d, step, li, cell);
     }
 
-    if constexpr (NOGAP) {
+    if constexpr (VAR == kVarNoGap) {
         for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
     } else {
         switch (d.conn) {
