@@ -44,7 +44,7 @@ def _make_net_struct(real):
         ("pulse_n1", P(ctypes.c_int64)), ("pulse_c0", P(ctypes.c_int32)),
         ("pulse_c1", P(ctypes.c_int32)), ("pulse_amp", P(real)),
         ("i_stream", P(real)), ("i_stream_steps", ctypes.c_int64),
-        ("reverse_j", ctypes.c_int32)]})
+        ("reverse_j", ctypes.c_int32), ("sgj", ctypes.c_int32)]})
 
 
 _NET64 = _make_net_struct(ctypes.c_double)
@@ -126,7 +126,8 @@ class Oracle:
                      pulse_amp=_ptr(keep["p_a"], cr),
                      i_stream=_ptr(keep["i_stream"], cr),
                      i_stream_steps=0 if i_stream is None else int(i_stream.shape[0]),
-                     reverse_j=1 if reverse_j else 0)
+                     reverse_j=1 if reverse_j else 0,
+                     sgj=1 if getattr(net, "gap", "rgj") == "sgj" else 0)
         return s, keep
 
     # ------------------------------------------------------------ API

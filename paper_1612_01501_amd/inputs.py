@@ -84,6 +84,7 @@ class Network:
     pulses: List[Pulse] = dataclasses.field(default_factory=list)
     params: np.ndarray = dataclasses.field(default_factory=lambda: DEFAULT_PARAMS.copy())
     dt: float = DT_MS
+    gap: str = "rgj"                # "rgj": realistic gap junctions | "sgj": simplified (linear)
     label: str = ""
 
     @property

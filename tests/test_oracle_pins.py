@@ -120,6 +120,87 @@ def test_gap_reverse_order_close(o32):
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-5 * np.abs(a).max())
 
 
+# ----------------------------------------------------------------- simplified gap junctions
+# Section 2.3.2 (SGJ): a connection is a weighted accumulator of the voltage
+# difference, I_gap,i = sum_j w_ij (Vd_i - Vd_j).
+
+def test_sgj_is_laplacian_times_vd(o64):
+    """Dense and CSR: I = (diag(W 1) - W) Vd, the weighted graph Laplacian
+    applied to Vd, by a numpy matrix product."""
+    rs = np.random.default_rng(11)
+    for n in (1, 5, 33):
+        w = rs.uniform(0, 0.1, (n, n)) * (rs.uniform(size=(n, n)) < 0.4)
+        v = rs.uniform(-70, -30, n)
+        lap = np.diag(w.sum(axis=1)) - w
+        want = lap @ v
+        got = o64.gap(I.Network(n=n, conn="dense", w_dense=w, gap="sgj"), v)
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+        rows, cols = np.nonzero(w)
+        rp = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))]).astype(np.int64)
+        got = o64.gap(I.Network(n=n, conn="csr", row_ptr=rp, col=cols.astype(np.int32),
+                                w_csr=w[rows, cols], gap="sgj"), v)
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+
+
+def test_sgj_uniform_closed_form(o64):
+    """All-to-all with one conductance g: I_i = g (N Vd_i - sum_j Vd_j)."""
+    n, g = 97, 0.04
+    v = np.random.default_rng(12).uniform(-70, -40, n)
+    got = o64.gap(I.Network(n=n, conn="uniform", g=g, gap="sgj"), v)
+    np.testing.assert_allclose(got, g * (n * v - v.sum()), rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sgj_sum_rule_symmetric(prec, o64, o32):
+    """Symmetric w: the currents sum to zero up to rounding."""
+    o = o64 if prec == "f64" else o32
+    eps = np.finfo(o.np_real).eps
+    n = 40
+    rs = np.random.default_rng(13)
+    w = np.triu(rs.uniform(0, 0.1, (n, n)), 1)
+    w = w + w.T
+    v = rs.uniform(-70, -40, n)
+    ig = o.gap(I.Network(n=n, conn="dense", w_dense=w, gap="sgj"), v).astype(np.float64)
+    assert abs(ig.sum()) <= 4 * n * eps * np.abs(w * (v[:, None] - v[None, :])).sum()
+
+
+def test_sgj_is_small_dv_limit_of_rgj(o64):
+    """The realistic factor 0.8 exp(-dV^2/100) + 0.2 is 1 at dV = 0 and
+    1 - f <= 0.8 dV^2/100: for voltage spreads of 1e-3 mV each row of the two
+    forms differs by at most that times the row's sum of |w dV|; at spreads
+    of 100 mV the realistic one tends to a fifth of the simplified."""
+    n = 20
+    rs = np.random.default_rng(14)
+    w = rs.uniform(0, 0.1, (n, n))
+    v = -60.0 + rs.uniform(-1e-3, 1e-3, n)
+    a = o64.gap(I.Network(n=n, conn="dense", w_dense=w), v)
+    b = o64.gap(I.Network(n=n, conn="dense", w_dense=w, gap="sgj"), v)
+    dv = v[:, None] - v[None, :]
+    bound = 0.8 * (dv ** 2).max() / 100.0 * np.abs(w * dv).sum(axis=1) + 1e-15
+    assert np.all(np.abs(a - b) <= bound)
+    assert np.abs(a - b).max() > 0.0        # the two forms are not the same
+    two = np.array([[0.0, 0.04], [0.04, 0.0]])
+    vv = np.array([100.0, 0.0])
+    ra = o64.gap(I.Network(n=2, conn="dense", w_dense=two), vv)
+    rb = o64.gap(I.Network(n=2, conn="dense", w_dense=two, gap="sgj"), vv)
+    assert ra[0] == pytest.approx(0.2 * rb[0], rel=1e-12)
+
+
+def test_sgj_formats_agree(o64):
+    """Uniform == dense (w = g off-diagonal) == complete CSR, bitwise."""
+    n = 17
+    v = np.random.default_rng(15).uniform(-70, -40, n)
+    g = 0.03
+    wd = np.full((n, n), g)
+    np.fill_diagonal(wd, 0.0)
+    rp, col = I.complete_csr(n)
+    a = o64.gap(I.Network(n=n, conn="uniform", g=g, gap="sgj"), v)
+    b = o64.gap(I.Network(n=n, conn="dense", w_dense=wd, gap="sgj"), v)
+    c = o64.gap(I.Network(n=n, conn="csr", g=g, row_ptr=rp, col=col, gap="sgj"), v)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+
+
 # ----------------------------------------------------------------- network invariants
 @pytest.mark.parametrize("conn", ["uniform", "dense", "csr"])
 def test_identical_cells_stay_in_sync(conn, o64, o32):
