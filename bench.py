@@ -22,6 +22,10 @@ Workloads (--workload):
            steps (the large-CSR, column-blocked gap path)
   ngj16m   2^24 uncoupled cells: the compartment update alone, 1.95 GB of
            state per step (beyond the 256 MB cache), 200 steps
+  sgj65k   the csr65k network with simplified gap junctions (w * dV), 2,000
+           steps
+  sgj16k   the uni16k network with simplified gap junctions (the closed
+           form g (N Vd_i - sum Vd)), 4,000 steps
   batch256 256 independent networks, N_k ~ U{64..2048}, density ~ U{5, 25,
            100 %} (100 % all-to-all, else ER CSR), g_k ~ U[0.01, 0.08],
            pulse amplitude ~ U[2, 10] uA/cm^2, 10,000 steps, one launch per
@@ -81,6 +85,8 @@ WORKLOADS = {
     "surr65k": dict(steps=10000, warmup=100),
     "csr65k": dict(steps=2000, warmup=100),
     "ngj16m": dict(steps=200, warmup=10),
+    "sgj65k": dict(steps=2000, warmup=100),
+    "sgj16k": dict(steps=4000, warmup=200),
 }
 
 
@@ -105,6 +111,16 @@ def build_workload(name):
         nets = [I.config4()]
         desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR), g=3.84e-3 mS/cm^2, "
                 "bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms; plain method")
+    elif name == "sgj65k":
+        nets = [I.config4()]
+        nets[0].gap = "sgj"
+        desc = ("65,536 cells, symmetric ER graph of mean degree 1,000 (CSR), simplified gap junctions "
+                "w*dV, g=3.84e-3 mS/cm^2, bias N(0,0.5), pulse, jitter, FP32, dt=0.05 ms")
+    elif name == "sgj16k":
+        nets = [I.config2()]
+        nets[0].gap = "sgj"
+        desc = ("16,384 cells all-to-all, simplified gap junctions w*dV (closed form g*(N*Vd_i - sum Vd)), "
+                "g=0.04*96/N mS/cm^2, +-1 mV jitter, no input, FP32, dt=0.05 ms")
     elif name == "ngj16m":
         n = 1 << 24
         nets = [I.Network(n=n, conn="none", jitter=I.voltage_jitter(n, 2000), bias=I.input_bias(n, 3000),
@@ -181,7 +197,7 @@ def roofline(nets, launch_s, kernel="infoli::k_step<256, 0>"):
         return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T lane-slots/s",
                 "frac": achieved / peak, "traffic": None, "kernel": kernel,
                 "slots_per_launch": slots}
-    if all(n.conn == "uniform" for n in nets):
+    if all(n.conn == "uniform" and n.gap == "rgj" for n in nets):
         pairs = sum(n.n * n.n for n in nets)       # the kernel evaluates the diagonal too
         achieved = pairs / launch_s / 1e9
         peak = LANE_SLOTS_PER_S / UNIFORM_SLOTS_PER_PAIR / 1e9
@@ -196,7 +212,7 @@ def roofline(nets, launch_s, kernel="infoli::k_step<256, 0>"):
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
            "algorithmic_bytes_per_launch": abytes}
-    if all(n.conn == "none" for n in nets):
+    if all(n.conn == "none" or (n.conn == "uniform" and n.gap == "sgj") for n in nets):
         # issue-slot use of the compartment update's own arithmetic
         cells = sum(n.n for n in nets)
         out["alu_frac"] = CELL_SLOTS * cells / launch_s / LANE_SLOTS_PER_S

@@ -63,6 +63,13 @@ typedef enum infoli_conn {
     INFOLI_CONN_CSR = 3          /* CSR by receiving cell: row i lists the j coupled to i   */
 } infoli_conn;
 
+/* Form of the gap-junction term of one connection (dV = Vd_i - Vd_j). */
+typedef enum infoli_gap_kind {
+    INFOLI_GAP_REALISTIC = 0,    /* w*dV*(0.8*exp(-dV^2/100) + 0.2) (Section 2.3.1, Alg. 1)   */
+    INFOLI_GAP_SIMPLIFIED = 1    /* w*dV, a weighted accumulator (Section 2.3.2, SGJ); for
+                                    UNIFORM_ALL the row sum is g*(n*Vd_i - sum_j Vd_j)      */
+} infoli_gap_kind;
+
 /* Cell state variables (structure-of-arrays order). Voltages in mV. */
 enum {
     INFOLI_VD = 0,  /* dendrite voltage                       */
@@ -121,6 +128,8 @@ typedef struct infoli_network_spec {
                                    added at steps 0 <= n < i_stream_steps (Section 2.4.3) */
     int64_t i_stream_steps;
     int64_t step0;              /* absolute index of the first step (resume); >= 0        */
+    int32_t gap_kind;           /* infoli_gap_kind; 0 (a zeroed spec) is the realistic form */
+    int32_t reserved0;          /* must be 0                                               */
 } infoli_network_spec;
 
 /* How steps are driven on the device. */

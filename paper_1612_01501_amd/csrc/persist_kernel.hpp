@@ -24,6 +24,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_persist(StepArgs a, const flo
                                                            float* __restrict__ xout, int64_t step0,
                                                            int64_t n_steps) {
     __shared__ float s_vd[2][kPersistBlock * kPersistCpt];
+    __shared__ double s_red[kPersistBlock / 64];
     const InstDesc& d = a.inst[blockIdx.x];
     const int n = d.n;
     const int tid = threadIdx.x;
@@ -65,7 +66,21 @@ __global__ __launch_bounds__(kPersistBlock) void k_persist(StepArgs a, const flo
         for (int m = 0; m < kPersistCpt; ++m) ig[m] = 0.0f;
 
         // gap currents of the owned cells from the step-n voltages
-        if (d.conn == CONN_UNIFORM) {
+        if (d.conn == CONN_UNIFORM && d.sgj) {
+            // simplified gap junctions: g (n Vd_i - sum_j Vd_j), the sum in
+            // fp64 in a fixed order (the workgroup's network decides the
+            // branch, so every thread reaches the barriers)
+            double part = 0.0;
+            for (int j = tid; j < n; j += kPersistBlock) part += (double)vcur[j];
+            for (int m = 32; m > 0; m >>= 1) part += __shfl_xor(part, m, 64);
+            if ((tid & 63) == 0) s_red[tid >> 6] = part;
+            __syncthreads();
+            double tot = 0.0;
+            for (int w = 0; w < kPersistBlock / 64; ++w) tot += s_red[w];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < kPersistCpt; ++m) ig[m] = d.g * (float)((double)n * (double)x[m][SV_VD] - tot);
+        } else if (d.conn == CONN_UNIFORM) {
             for (int j = 0; j < n; ++j) {
                 const float vj = vcur[j];
 #pragma unroll
@@ -86,7 +101,8 @@ __global__ __launch_bounds__(kPersistBlock) void k_persist(StepArgs a, const flo
                     for (int64_t k = rp[li]; k < rp[li + 1]; ++k) {
                         const int j = d.col16 ? (int)c16[k] : c32[k];
                         const float dv = vi - vcur[j];
-                        acc += d.has_w ? wv[k] * (dv * gap_factor(dv)) : dv * gap_factor(dv);
+                        const float term = d.sgj ? dv : dv * gap_factor(dv);
+                        acc += d.has_w ? wv[k] * term : term;
                     }
                     ig[m] = d.has_w ? acc : d.g * acc;
                 }
@@ -101,7 +117,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_persist(StepArgs a, const flo
                     const float vi = x[m][SV_VD];
                     for (int j = 0; j < n; ++j) {
                         const float dv = vi - vcur[j];
-                        acc = fmaf(wr[j], dv * gap_factor(dv), acc);
+                        acc = fmaf(wr[j], d.sgj ? dv : dv * gap_factor(dv), acc);
                     }
                     ig[m] = acc;
                 }

@@ -125,6 +125,9 @@ void validate_spec(const infoli_network_spec& s, int k) {
     if (s.init_state && !finite_all(s.init_state, INFOLI_NUM_STATE * n))
         fail(INFOLI_E_INVALID_ARG, "network %d: non-finite initial state", k);
     if (s.i_bias && !finite_all(s.i_bias, n)) fail(INFOLI_E_INVALID_ARG, "network %d: non-finite bias", k);
+    if (s.gap_kind != INFOLI_GAP_REALISTIC && s.gap_kind != INFOLI_GAP_SIMPLIFIED)
+        fail(INFOLI_E_INVALID_ARG, "network %d: gap_kind must be 0 (realistic) or 1 (simplified)", k);
+    if (s.reserved0 != 0) fail(INFOLI_E_INVALID_ARG, "network %d: reserved0 must be 0", k);
     if (s.n_pulses < 0 || s.n_pulses > INFOLI_MAX_PULSES)
         fail(INFOLI_E_INVALID_ARG, "network %d: n_pulses must be in [0, %d]", k, INFOLI_MAX_PULSES);
     if (s.n_pulses > 0 && !s.pulses) fail(INFOLI_E_INVALID_ARG, "network %d: pulses is NULL", k);
@@ -258,15 +261,16 @@ void finalize_tiles(infoli_ctx* c) {
     HIPX(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDesc) * c->n_inst, hipMemcpyHostToDevice));
 }
 
-// Coupling bitmaps of CSR networks with one weight g (the pattern as one bit
-// per pair), for networks of at most 16,384 cells while the bitmaps take at
-// most 1 GiB together; the tuner decides whether the step uses them.
+// Coupling bitmaps of CSR networks with one weight g and the realistic gap
+// form (the pattern as one bit per pair), for networks of at most 16,384
+// cells while the bitmaps take at most 1 GiB together; the tuner decides
+// whether the step uses them.
 void build_bitmaps(infoli_ctx* c, const infoli_network_spec* specs) {
     int64_t words = 0;
     for (int k = 0; k < c->n_inst; ++k) {
         InstDesc& d = c->inst[k];
         d.bits_off = -1;
-        if (d.conn != CONN_CSR || d.has_w || d.n > 16384 || specs[k].nnz == 0) continue;
+        if (d.conn != CONN_CSR || d.has_w || d.sgj || d.n > 16384 || specs[k].nnz == 0) continue;
         const int64_t groups = (d.n + kBitGroup - 1) / kBitGroup;
         const int64_t w = groups * bitmap_rows_pad(d.n) * 4;
         if ((words + w) * 4 > ((int64_t)1 << 30)) continue;
@@ -445,8 +449,8 @@ std::string tune_key(const infoli_ctx* c, const InstDesc& d, double deg) {
     const int nb = (int)std::ceil(std::log2((double)d.n) * 4.0);
     const int db = (int)std::ceil(std::log2(deg + 1.0) * 4.0);
     char buf[128];
-    snprintf(buf, sizeof buf, "gfx950 groups2 c16=%d w=%d bits=%d blk=%d n%d d%d", d.col16, d.has_w,
-             d.bits_off >= 0 ? 1 : 0, d.blk_off >= 0 ? c->blk_cols : 0, nb, db);
+    snprintf(buf, sizeof buf, "gfx950 groups2 c16=%d w=%d bits=%d blk=%d n%d d%d%s", d.col16, d.has_w,
+             d.bits_off >= 0 ? 1 : 0, d.blk_off >= 0 ? c->blk_cols : 0, nb, db, d.sgj ? " sgj" : "");
     return buf;
 }
 
@@ -879,6 +883,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         d.n = s.n_cells;
         d.conn = s.conn;
         d.g = s.g_uniform;
+        d.sgj = s.gap_kind == INFOLI_GAP_SIMPLIFIED ? 1 : 0;
         d.stream_off = -1;
         std::memcpy(&d.p, s.params ? s.params : kDefaultParams, sizeof(CellParams));
         cells += s.n_cells;

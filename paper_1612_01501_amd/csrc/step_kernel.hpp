@@ -70,6 +70,7 @@ struct InstDesc {
     int32_t nblk;          // blocked: number of column blocks
     int32_t wide;          // bitmap: run in the 1024-thread launch group
     int32_t chunked;       // CSR gathers from the chunked rows layout
+    int32_t sgj;           // simplified (linear) gap junctions: term w * dV
     int64_t bits_off;      // bitmap: offset of the network's first word
     int64_t blk_off;       // blocked: offset of the network's [n][nblk] block starts
     int64_t ca_off;        // chunked rows: offset of the [n + 1] row chunk starts, -1 none
@@ -142,6 +143,15 @@ __device__ __forceinline__ float gap_factor_ps(float dvs) {
     return fmaf(0.8f, __builtin_amdgcn_exp2f(-(dvs * dvs)), 0.2f);
 }
 
+// The factor multiplying w * dV: the realistic one (of a prescaled
+// difference when PS), or 1 for simplified gap junctions (Section 2.3.2),
+// which is linear, so a prescaled row sum scales back the same way.
+template <bool SGJ, bool PS>
+__device__ __forceinline__ float pair_factor(float dv) {
+    if constexpr (SGJ) return 1.0f;
+    else return PS ? gap_factor_ps(dv) : gap_factor(dv);
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d, const Tile& t,
                                             const float* __restrict__ vd, float* s_ig,
@@ -157,7 +167,11 @@ __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d
     float* s_v = reinterpret_cast<float*>(s_v4);
     float acc0 = 0.0f, acc1 = 0.0f;
     double vsum = 0.0;
-    for (int c0 = 0; c0 < n; c0 += kChunk) {
+    if (d.sgj) {
+        // simplified: g (n Vd_i - sum_j Vd_j), the sum in fp64
+        for (int k = threadIdx.x; k < n; k += BLOCK) vsum += (double)vd[k];
+    }
+    for (int c0 = 0; c0 < (d.sgj ? 0 : n); c0 += kChunk) {
         const int cn = min(kChunk, n - c0);
         // per-wave share, a multiple of 8 values; the tail is padded with a
         // sentinel whose term is exactly -0
@@ -200,7 +214,7 @@ __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d
         double tot = 0.0;
         for (int w = 0; w < W; ++w) tot += s_red[w];
         const float lin = (float)((double)n * (double)vi - tot);
-        s_ig[lane] = d.g * (0.8f * (e * kInvPreScale) + 0.2f * lin);
+        s_ig[lane] = d.sgj ? d.g * lin : d.g * (0.8f * (e * kInvPreScale) + 0.2f * lin);
     }
 }
 
@@ -215,16 +229,20 @@ __device__ __forceinline__ void gap_dense(const StepArgs& a, const InstDesc& d, 
         const float vi = vd[r];
         const float* wr = a.w + d.w_off + (int64_t)r * n;
         float acc = 0.0f;
-        for (int j = lane; j < n; j += 64) {
-            const float dv = vi - vd[j];
-            acc = fmaf(wr[j], dv * gap_factor(dv), acc);
+        if (d.sgj) {
+            for (int j = lane; j < n; j += 64) acc = fmaf(wr[j], vi - vd[j], acc);
+        } else {
+            for (int j = lane; j < n; j += 64) {
+                const float dv = vi - vd[j];
+                acc = fmaf(wr[j], dv * gap_factor(dv), acc);
+            }
         }
         acc = wave_sum_xor(acc, 64);
         if (lane == 0) s_ig[r - t.row0] = acc;
     }
 }
 
-template <int BLOCK, bool LDS, bool C16, bool HASW>
+template <int BLOCK, bool LDS, bool C16, bool HASW, bool SGJ>
 __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& d, const Tile& t,
                                              const float* __restrict__ vd, const float* s_vd,
                                              float* s_part, float* s_ig) {
@@ -244,7 +262,7 @@ __device__ __forceinline__ void gap_csr_impl(const StepArgs& a, const InstDesc& 
     auto v_at = [&](int j) -> float { return LDS ? s_vd[j] : vd[j]; };
     auto term = [&](float w, float vi, float vj) -> float {
         const float dv = vi - vj;
-        const float f = LDS ? gap_factor_ps(dv) : gap_factor(dv);
+        const float f = pair_factor<SGJ, LDS>(dv);
         return HASW ? w * (dv * f) : dv * f;
     };
     const float back = LDS ? kInvPreScale : 1.0f;
@@ -424,7 +442,7 @@ __device__ __forceinline__ uint4 pad_chunk(uint32_t v) {
 
 // Sixteen edges of a row from two chunks: columns j, voltages from `src`
 // (LDS, prescaled; or global), accumulated into acc0/acc1.
-template <bool PS, bool HASW>
+template <bool PS, bool HASW, bool SGJ>
 __device__ __forceinline__ void chunk_pair_terms(const uint4 q0, const uint4 q1, const float4* w4,
                                                  const float* src, float vi, float& acc0, float& acc1) {
     const uint32_t wd[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
@@ -437,8 +455,8 @@ __device__ __forceinline__ void chunk_pair_terms(const uint4 q0, const uint4 q1,
 #pragma unroll
     for (int e = 0; e < 2 * kChunkCols; e += 2) {
         const float d0 = vi - v[e], d1 = vi - v[e + 1];
-        const float f0 = PS ? gap_factor_ps(d0) : gap_factor(d0);
-        const float f1 = PS ? gap_factor_ps(d1) : gap_factor(d1);
+        const float f0 = pair_factor<SGJ, PS>(d0);
+        const float f1 = pair_factor<SGJ, PS>(d1);
         if (HASW) {
             const float4 wa = w4[e >> 2];
             const float w0 = (e & 3) == 0 ? wa.x : wa.z, w1 = (e & 3) == 0 ? wa.y : wa.w;
@@ -453,7 +471,7 @@ __device__ __forceinline__ void chunk_pair_terms(const uint4 q0, const uint4 q1,
 
 // Gathers over whole rows (networks of at most 65,536 cells): row r's chunks
 // [ca[r], ca[r + 1]), padded with r itself.
-template <int BLOCK, bool LDS, bool HASW>
+template <int BLOCK, bool LDS, bool HASW, bool SGJ>
 __device__ __forceinline__ void gap_chunks(const StepArgs& a, const InstDesc& d, const Tile& t,
                                            const float* __restrict__ vd, const float* s_vd, float* s_part,
                                            float* s_ig) {
@@ -484,7 +502,7 @@ __device__ __forceinline__ void gap_chunks(const StepArgs& a, const InstDesc& d,
                     w4[2] = ok1 ? cw[2 * (int64_t)(c + L)] : make_float4(0.f, 0.f, 0.f, 0.f);
                     w4[3] = ok1 ? cw[2 * (int64_t)(c + L) + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                chunk_pair_terms<LDS, HASW>(q0, q1, w4, src, vi, acc0, acc1);
+                chunk_pair_terms<LDS, HASW, SGJ>(q0, q1, w4, src, vi, acc0, acc1);
             }
         }
         float acc = acc0 + acc1;
@@ -512,7 +530,7 @@ constexpr int kSelfSlots = 256;     // LDS slots after a column block: the tile 
 // Column blocks with chunks: per row and block, the columns relative to the
 // block start, padded with S + (r mod 256), S = min(n, C), the LDS slot
 // holding row r's own (prescaled) voltage; LDS holds S + kSelfSlots floats.
-template <int BLOCK, bool HASW>
+template <int BLOCK, bool HASW, bool SGJ>
 __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const InstDesc& d, const Tile& t,
                                                    const float* __restrict__ vd, float* s_vd, float* s_part,
                                                    float* s_ig) {
@@ -559,7 +577,7 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
                     w4[2] = ok1 ? cw[2 * (int64_t)(c + L)] : make_float4(0.f, 0.f, 0.f, 0.f);
                     w4[3] = ok1 ? cw[2 * (int64_t)(c + L) + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                chunk_pair_terms<true, HASW>(q0, q1, w4, s_vd, vi[q], a0, a1);
+                chunk_pair_terms<true, HASW, SGJ>(q0, q1, w4, s_vd, vi[q], a0, a1);
             }
             acc[q] += a0 + a1;
         }
@@ -587,60 +605,74 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
     }
 }
 
-template <int BLOCK>
-__device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
-                                        const float* __restrict__ vd, float* s_vd, float* s_part,
-                                        float* s_ig) {
+// CSR paths of one gap form (SGJ: simplified). The old column-blocked
+// gathers (no chunked copy of the lists) exist for the realistic form only;
+// a simplified network without chunks takes the plain gathers.
+template <int BLOCK, bool SGJ>
+__device__ __forceinline__ void gap_csr_form(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                             const float* __restrict__ vd, float* s_vd, float* s_part,
+                                             float* s_ig) {
     // column-blocked tiles run in 1024-thread workgroups only (the runtime
     // places them there); elsewhere the same rows take the gathers below
     if constexpr (BLOCK == 1024) {
         if (d.blocked && d.cb_off >= 0) {
-            if (d.has_w) gap_chunks_blocked<BLOCK, true>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_chunks_blocked<BLOCK, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            if (d.has_w) gap_chunks_blocked<BLOCK, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_chunks_blocked<BLOCK, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
             return;
         }
-        if (d.blocked) {
-            if (d.col16) {
-                if (d.has_w) gap_csr_blocked<BLOCK, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
-                else gap_csr_blocked<BLOCK, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
-            } else {
-                if (d.has_w) gap_csr_blocked<BLOCK, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
-                else gap_csr_blocked<BLOCK, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
+        if constexpr (!SGJ) {
+            if (d.blocked) {
+                if (d.col16) {
+                    if (d.has_w) gap_csr_blocked<BLOCK, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
+                    else gap_csr_blocked<BLOCK, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
+                } else {
+                    if (d.has_w) gap_csr_blocked<BLOCK, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
+                    else gap_csr_blocked<BLOCK, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
+                }
+                return;
             }
-            return;
         }
     }
+    const bool lds = d.vd_lds;
     if (d.chunked && d.ca_off >= 0) {
-        if (d.vd_lds) {
+        if (lds) {
             for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k] * kPreScale;
             __syncthreads();
-            if (d.has_w) gap_chunks<BLOCK, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_chunks<BLOCK, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            if (d.has_w) gap_chunks<BLOCK, true, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_chunks<BLOCK, true, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
         } else {
-            if (d.has_w) gap_chunks<BLOCK, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_chunks<BLOCK, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            if (d.has_w) gap_chunks<BLOCK, false, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_chunks<BLOCK, false, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
         }
         return;
     }
-    if (d.vd_lds) {
+    if (lds) {
         for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k] * kPreScale;
         __syncthreads();
         if (d.col16) {
-            if (d.has_w) gap_csr_impl<BLOCK, true, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_csr_impl<BLOCK, true, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            if (d.has_w) gap_csr_impl<BLOCK, true, true, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, true, true, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
         } else {
-            if (d.has_w) gap_csr_impl<BLOCK, true, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_csr_impl<BLOCK, true, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            if (d.has_w) gap_csr_impl<BLOCK, true, false, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, true, false, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
         }
     } else {
         if (d.col16) {
-            if (d.has_w) gap_csr_impl<BLOCK, false, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_csr_impl<BLOCK, false, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            if (d.has_w) gap_csr_impl<BLOCK, false, true, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, false, true, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
         } else {
-            if (d.has_w) gap_csr_impl<BLOCK, false, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_csr_impl<BLOCK, false, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
+            if (d.has_w) gap_csr_impl<BLOCK, false, false, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, false, false, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
         }
     }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                        const float* __restrict__ vd, float* s_vd, float* s_part,
+                                        float* s_ig) {
+    if (d.sgj) gap_csr_form<BLOCK, true>(a, d, t, vd, s_vd, s_part, s_ig);
+    else gap_csr_form<BLOCK, false>(a, d, t, vd, s_vd, s_part, s_ig);
 }
 
 // Bitmap words of a network: group gr (128 senders), row r (padded to a

@@ -63,7 +63,8 @@ class NetworkSpec(ctypes.Structure):
                 ("col", _PI32), ("w_csr", _PF), ("nnz", ctypes.c_int64), ("params", _PF),
                 ("init_state", _PF), ("i_bias", _PF), ("pulses", ctypes.POINTER(Pulse)),
                 ("n_pulses", ctypes.c_int32), ("i_stream", _PF),
-                ("i_stream_steps", ctypes.c_int64), ("step0", ctypes.c_int64)]
+                ("i_stream_steps", ctypes.c_int64), ("step0", ctypes.c_int64),
+                ("gap_kind", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class Options(ctypes.Structure):
@@ -259,6 +260,9 @@ def mlp_adam_step(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e
     return p, mm, vv
 
 
+GAP_KIND = {"rgj": 0, "sgj": 1}
+
+
 class _SpecHolder:
     """Keeps the numpy arrays a NetworkSpec points at alive."""
 
@@ -299,6 +303,7 @@ class _SpecHolder:
             s.i_stream = _fptr(st)
             s.i_stream_steps = st.shape[0]
         s.step0 = step0
+        s.gap_kind = GAP_KIND[net.gap]
         self.spec = s
 
     def _f(self, a):

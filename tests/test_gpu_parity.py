@@ -622,3 +622,110 @@ def test_blocked_path_trajectory(infoli, o32, o64):
     compare_spikes(c_b, t_b, ref["counts"], ref["times"], 64)
     compare_spikes(c_b, t_b, c_g, t_g, 64)
     print("blocked vs gathers (spiking run), per variable:", per_var_error(got_b, got_g))
+
+
+# ------------------------------------------------------------------ simplified gap junctions
+def _sgj(net):
+    net.gap = "sgj"
+    net.label = (net.label or net.conn) + "_sgj"
+    return net
+
+
+@pytest.mark.parametrize("case", ["uni96_persistent", "uni96_graph", "uni777", "dense200", "csr_p0.01", "csr_p0.1"])
+def test_sgj_trajectories(infoli, o32, o64, case):
+    """Simplified gap junctions (Section 2.3.2): 1,000 steps against the
+    oracle, all-to-all (closed form, persistent and tiled kernels), dense and
+    CSR."""
+    mode = "auto"
+    if case.startswith("uni96"):
+        net = _sgj(I.config0())
+        mode = "persistent" if case.endswith("persistent") else "graph"
+    elif case == "uni777":
+        net = _sgj(I.config2(seed=1, n=777, pulse=True))
+        net.pulses = [I.Pulse(100, 600, 6.0)]
+    elif case == "dense200":
+        rs = I.rng(7)
+        w = rs.uniform(0, 0.002, (200, 200)).astype(np.float32)
+        net = _sgj(I.Network(n=200, conn="dense", w_dense=(w + w.T) / 2, jitter=I.voltage_jitter(200, 8),
+                             pulses=[I.Pulse(200, 400, 5.0)], label="dense200"))
+    else:
+        net = _sgj(I.config1(float(case.split("p")[-1]), seed=3, n=1000))
+    x0 = infoli.initial_state(net)
+    got, c, t = gpu_trace(infoli, net, 1000, 50, x0, step_mode=mode)
+    ref = o32.run(net, 1000, x0=x0, trace_every=50, trace_cells=net.n)
+    r64 = o64.run(net, 1000, x0=x0.astype(np.float64), trace_every=50, trace_cells=net.n)
+    e32 = per_var_error(got, ref["trace"])
+    floor = per_var_error(ref["trace"], r64["trace"])
+    print(f"{net.label}: max err vs f32 oracle {e32.max():.2e}, f32-oracle floor {floor.max():.2e}")
+    assert np.all(e32 <= np.maximum(TOL_STATE, 2 * floor)), e32
+    compare_spikes(c, t, ref["counts"], ref["times"], 64)
+
+
+@pytest.mark.parametrize("conn", ["uniform", "dense", "csr"])
+@pytest.mark.parametrize("n", [1, 65, 4500])
+def test_sgj_gap_current(infoli, o64, conn, n):
+    """Simplified gap currents of a spread of voltages against the fp64
+    oracle (the all-to-all closed form sums Vd in fp64)."""
+    rs = I.rng(n + 21)
+    kw = {}
+    if conn == "dense":
+        kw["w_dense"] = rs.uniform(0, 0.05, (n, n)).astype(np.float32)
+    if conn == "csr":
+        kw["row_ptr"], kw["col"] = I.erdos_renyi_csr(n, 0.3, n)
+    net = I.Network(n=n, conn=conn, g=0.04, jitter=rs.uniform(-15, 15, (3, n)), gap="sgj", **kw)
+    x0 = infoli.initial_state(net)
+    sim = infoli.Simulator(net, init_states=[x0])
+    got = sim.read_gap_current(0).astype(np.float64)
+    sim.close()
+    ref = o64.gap(net, x0[0].astype(np.float64))
+    tol = gap_bound(net, x0[0])
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
+@pytest.mark.parametrize("csr_path", [1, 2, 3, 4])
+def test_sgj_csr_paths(infoli, o32, o64, csr_path):
+    """A 20,000-cell simplified network (two column blocks) on each CSR path
+    the option can ask for: edge gathers, the bitmap (not built for the
+    simplified form: the request falls back), column blocks, chunked
+    gathers. Gap currents against fp64 and one step against the oracle,
+    after 100 steps."""
+    net = _sgj(I.config4(seed=5, n=20000, degree=150))
+    net.g = 0.002
+    x0 = infoli.initial_state(net)
+    sim = infoli.Simulator(net, init_states=[x0], csr_path=csr_path, step_mode="graph", graph_chunk=50)
+    info = sim.info()
+    sim.step(100)
+    xk = sim.read_state(0)
+    ig = sim.read_gap_current(0).astype(np.float64)
+    sim.step(1)
+    xk1 = sim.read_state(0)
+    sim.close()
+    assert info["n_bitmap"] == 0
+    ref_ig = o64.gap(net, xk[0].astype(np.float64))
+    tol = gap_bound(net, xk[0])
+    assert np.all(np.abs(ig - ref_ig) <= tol), np.max(np.abs(ig - ref_ig) / tol)
+    ref = o32.run(net, 1, x0=xk, step0=100)["x"]
+    assert per_var_error(xk1[None], ref[None]).max() <= 1e-5
+
+
+def test_sgj_mixed_batch_matches_standalone_bitwise(infoli):
+    """Realistic and simplified networks stepped in one batch give the bits
+    each gives alone."""
+    nets = [
+        I.Network(n=70, conn="uniform", g=0.05, jitter=I.voltage_jitter(70, 1), pulses=[I.Pulse(50, 300, 7.0)]),
+        _sgj(I.Network(n=70, conn="uniform", g=0.05, jitter=I.voltage_jitter(70, 1), pulses=[I.Pulse(50, 300, 7.0)])),
+        _sgj(I.config1(0.25, seed=4, n=130)),
+        I.config1(0.25, seed=4, n=130),
+        _sgj(I.config1(0.05, seed=5, n=300)),
+    ]
+    x0s = [infoli.initial_state(n) for n in nets]
+    sim = infoli.Simulator(nets, init_states=x0s, step_mode="graph", graph_chunk=50, autotune=0)
+    sim.step(300)
+    batch = [sim.read_state(k) for k in range(len(nets))]
+    sim.close()
+    assert not np.array_equal(batch[0], batch[1])      # the two forms differ
+    for k, net in enumerate(nets):
+        s = infoli.Simulator(net, init_states=[x0s[k]], step_mode="graph", graph_chunk=50, autotune=0)
+        s.step(300)
+        np.testing.assert_array_equal(s.read_state(0), batch[k])
+        s.close()

@@ -143,6 +143,17 @@ def test_validation_rejects_bad_dense_and_inputs():
     assert _init_status(I.Network(n=n, conn="none", params=p))[0] == 1
 
 
+def test_validation_rejects_bad_gap_kind():
+    net = I.Network(n=3, conn="uniform", g=0.04, gap="sgj")
+    st, msg = _init_status(net, gap_kind=2)
+    assert st == 1 and "gap_kind" in msg
+    st, msg = _init_status(net, reserved0=1)
+    assert st == 1 and "reserved0" in msg
+    h = infoli._SpecHolder(net, init_state=np.zeros((14, 3), np.float32) - 60.0)
+    assert h.spec.gap_kind == 1
+    assert infoli._SpecHolder(I.Network(n=3, conn="none"), init_state=np.zeros((14, 3), np.float32)).spec.gap_kind == 0
+
+
 def test_bad_options_rejected():
     net = I.Network(n=4, conn="none")
     h = infoli._SpecHolder(net, init_state=np.zeros((14, 4), np.float32) - 60.0)
