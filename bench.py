@@ -22,6 +22,8 @@ Workloads (--workload):
            steps (the large-CSR, column-blocked gap path)
   ngj16m   2^24 uncoupled cells: the compartment update alone, 1.95 GB of
            state per step (beyond the 256 MB cache), 200 steps
+  valid120k the paper's validation run: 96 cells, 25 ms pulse, 120,000 steps
+           (6 s) with every step's axon voltages streamed to the host
   sgj65k   the csr65k network with simplified gap junctions (w * dV), 2,000
            steps
   sgj16k   the uni16k network with simplified gap junctions (the closed
@@ -85,6 +87,7 @@ WORKLOADS = {
     "surr65k": dict(steps=10000, warmup=100),
     "csr65k": dict(steps=2000, warmup=100),
     "ngj16m": dict(steps=200, warmup=10),
+    "valid120k": dict(steps=120000, warmup=1000),
     "sgj65k": dict(steps=2000, warmup=100),
     "sgj16k": dict(steps=4000, warmup=200),
 }
@@ -111,6 +114,12 @@ def build_workload(name):
         nets = [I.config4()]
         desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR), g=3.84e-3 mS/cm^2, "
                 "bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms; plain method")
+    elif name == "valid120k":
+        nets = [I.config0()]
+        nets[0].pulses = [I.Pulse(400, 900, 6.0)]
+        desc = ("the paper's validation run: 96 cells all-to-all, g=0.04 mS/cm^2, jitter, 25 ms pulse of "
+                "6 uA/cm^2 at t=20 ms, 120,000 steps (6 s), the axon voltage of every cell streamed to "
+                "pinned host memory every 1,000 steps while later steps compute")
     elif name == "sgj65k":
         nets = [I.config4()]
         nets[0].gap = "sgj"
@@ -253,6 +262,62 @@ def cpu_baseline(nets, budget_s=15.0):
                       "from the initial state, fp32 oracle, OpenMP over cells"}
 
 
+def run_validation(nets, desc, steps, warmup, args, torch, infoli):
+    """The long run with per-step output streaming (output ring, copies of
+    each 1,000-step chunk queued on the library's copy stream into pinned
+    host memory) against the same run without it."""
+    net = nets[0]
+    x0 = infoli.initial_state(net)
+    chunk, ring = 1000, 2000
+    host = torch.zeros((steps, net.n), dtype=torch.float32, pin_memory=True)
+    hv = host.numpy()
+    times = {}
+    for streamed in (False, True):
+        opt = {"output_ring_steps": ring} if streamed else {}
+        sim = infoli.Simulator(net, init_states=[x0], step_mode=args.mode, **opt)
+        mode = sim.info()["step_mode"]
+        sim.step(warmup)
+        sim.sync()
+        sim.write_state(0, x0, 0)
+        sim.clear_spikes()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s0 in range(0, steps, chunk):
+            sim.step(chunk)
+            if streamed:
+                view = hv[s0:s0 + chunk]
+                sim.output_copy_async(s0, chunk, view.ctypes.data, view.size)
+        if streamed:
+            sim.output_wait()
+        sim.sync()
+        times[streamed] = time.perf_counter() - t0
+        counts, _ = sim.read_spikes(0)
+        last = sim.read_state(0)
+        sim.close()
+    va = hv
+    crossings = ((va[:-1] < 0.0) & (va[1:] >= 0.0)).sum(axis=0) + ((x0[I.IDX_VA] < 0.0) & (va[0] >= 0.0))
+    out = {
+        "metric": "cell-steps/sec (plain InfOli step) with per-step output streamed to the host",
+        "value": net.n * steps / times[True],
+        "unit": "cell-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": times[True] * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"valid120k: {desc}", "cells": net.n, "step_mode": mode,
+                   "chunk_steps": chunk, "ring_steps": ring},
+        "us_per_step_streamed": times[True] * 1e6 / steps,
+        "us_per_step_not_streamed": times[False] * 1e6 / steps,
+        "streaming_overhead": times[True] / times[False] - 1.0,
+        "real_time_factor": (steps * net.dt * 1e-3) / times[True],
+        "output_bytes_streamed": int(steps * net.n * 4),
+        "spikes_counted_by_library": int(counts.sum()),
+        "spikes_in_streamed_output": int(crossings.sum()),
+        "streamed_last_step_equals_state": bool(np.array_equal(va[-1], last[I.IDX_VA])),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
     """Plain run vs trained surrogate on the same network and initial state."""
     net = nets[0]
@@ -359,6 +424,80 @@ def copy_probe(mb, torch):
                       "copy_GBps_read_plus_write": 8 * n / s / 1e9}))
 
 
+# Table 3 of the paper (largest network run in real time, 50 us of simulated
+# time per step, on its three platforms), quoted as context.
+PAPER_TABLE3 = {
+    "hardware": {"DFE": "Maxeler Maia DFE (Altera Stratix V 5SGSD8)", "Xeon Phi": "Intel Xeon Phi 5110P",
+                 "GPU": "NVIDIA Titan X (Maxwell)"},
+    "RGJ 100%": {"DFE": 310}, "RGJ 75%": {"DFE": 310}, "RGJ 50%": {"DFE": 310}, "RGJ 25%": {"DFE": 310},
+    "SGJ 100%": {"DFE": 400}, "SGJ 75%": {"DFE": 400}, "SGJ 50%": {"DFE": 400, "GPU": 96},
+    "SGJ 25%": {"DFE": 400, "GPU": 96}, "NGJ": {"DFE": 7680, "Xeon Phi": 96, "GPU": 500},
+}
+
+
+def rt_network(case, n):
+    """One network of the real-time sweep: 100 % density is all-to-all,
+    lower densities symmetric ER graphs as CSR, NGJ uncoupled; conductance
+    0.04 * 96 / (density * N) (the summed coupling of the 96-cell network),
+    jitter, bias N(0, 0.5)."""
+    kind, dens = case.split()[0].lower(), case.split()[-1]
+    jit, bias = I.voltage_jitter(n, 2000), I.input_bias(n, 3000)
+    if kind == "ngj":
+        return I.Network(n=n, conn="none", jitter=jit, bias=bias)
+    d = float(dens.rstrip("%")) / 100.0
+    g = 0.04 * 96.0 / (d * n)
+    if d >= 1.0:
+        return I.Network(n=n, conn="uniform", g=g, jitter=jit, bias=bias, gap=kind)
+    rp, col = I.erdos_renyi_csr(n, d, 1000)
+    return I.Network(n=n, conn="csr", g=g, row_ptr=rp, col=col, jitter=jit, bias=bias, gap=kind)
+
+
+def rt_sweep(args, torch, infoli):
+    """Largest network per use case and density whose steps take at most
+    the real-time budget (Section 2.2: 50 us of simulated time per step):
+    sizes on a grid of ratio sqrt(2) (multiples of 32) from 96 up to the
+    first size over budget; each size timed over 300 steps after 50 warm-up
+    steps in the library's automatic launch mode."""
+    budget = args.rt_budget_us
+    cases = ["RGJ 100%", "RGJ 75%", "RGJ 50%", "RGJ 25%", "SGJ 100%", "SGJ 75%", "SGJ 50%", "SGJ 25%", "NGJ"]
+    max_edges = 2.6e8
+    out = []
+    for case in cases:
+        points, best, first_over = [], None, None
+        k = 0
+        while True:
+            n = int(round(96 * 2 ** (k / 2) / 32.0)) * 32
+            k += 1
+            dens = 1.0 if case == "NGJ" else float(case.split()[-1].rstrip("%")) / 100.0
+            if case != "NGJ" and 0 < dens < 1.0 and dens * n * n > max_edges:
+                break
+            if n > (1 << 24):
+                break
+            net = rt_network(case, n)
+            sim = infoli.Simulator([net], init_states=[infoli.initial_state(net)], step_mode="auto")
+            sim.step(50)
+            sim.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(300)
+            torch.cuda.synchronize()
+            us = (time.perf_counter() - t0) / 300 * 1e6
+            mode = sim.info()["step_mode"]
+            sim.close()
+            points.append([n, round(us, 2)])
+            print(f"rt {case} n={n} {us:.2f} us/step (mode {mode})", file=sys.stderr, flush=True)
+            if us <= budget:
+                best = [n, round(us, 2)]
+            else:
+                first_over = [n, round(us, 2)]
+                break
+        out.append({"case": case, "max_cells": best[0] if best else 0,
+                    "us_per_step_at_max": best[1] if best else None,
+                    "first_over_budget": first_over, "points": points})
+    print(json.dumps({"rt_sweep": {"budget_us": budget, "cases": out,
+                                   "paper_table3_context": PAPER_TABLE3}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +508,9 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--rt-sweep", action="store_true",
+                    help="only run the real-time size sweep (largest network per use case within the budget)")
+    ap.add_argument("--rt-budget-us", type=float, default=50.0)
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -386,9 +528,15 @@ def main():
     if args.copy_probe_mb > 0:
         copy_probe(args.copy_probe_mb, torch)
         return
+    if args.rt_sweep:
+        rt_sweep(args, torch, infoli)
+        return
     nets, desc = build_workload(args.workload)
     if args.workload == "surr65k":
         run_surrogate(nets, desc, steps, warmup, args, torch, infoli)
+        return
+    if args.workload == "valid120k":
+        run_validation(nets, desc, steps, warmup, args, torch, infoli)
         return
     x0s = [infoli.initial_state(n) for n in nets]
     stream = torch.cuda.current_stream().cuda_stream

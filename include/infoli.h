@@ -157,6 +157,10 @@ typedef struct infoli_options {
                                     3 => Vd staged in LDS by column blocks (> 8,192 cells);
                                     4 => edge gathers from 16-byte column chunks
                                     (<= 65,536 cells); other networks keep the default   */
+    int32_t output_ring_steps;   /* 0 => off; R > 0 => every plain step also writes the axon
+                                    voltage of every cell into a device ring of R steps,
+                                    read out with infoli_output_copy_async                 */
+    int32_t reserved1;           /* must be 0                                              */
 } infoli_options;
 
 typedef struct infoli_ctx infoli_ctx;
@@ -223,6 +227,32 @@ infoli_status infoli_read_spikes(infoli_ctx *ctx, int32_t instance, int32_t *cou
 infoli_status infoli_clear_spikes(infoli_ctx *ctx);
 
 /* Description of what the context runs. */
+/* Output streaming (Section 2.4.3: the host receives each step's output, the
+ * axon voltages, while later steps compute, over a second stream). Requires
+ * options.output_ring_steps = R > 0. The output of step s is Va of every cell
+ * after step s (the state of step s + 1), held in ring slot s mod R until
+ * step s + R overwrites it.
+ *
+ * infoli_output_copy_async queues, on the context's copy stream, the copy of
+ * the outputs of steps [step_begin, step_begin + n_steps) into
+ * host[n_steps][total_cells] (cells in batch order: instance 0's cells, then
+ * instance 1's, ...), ordered after the steps that produce them; it returns
+ * before the copy is done. Steps queued later that would overwrite slots of
+ * a pending copy wait for it on the device. host must hold
+ * cap_floats >= n_steps * total_cells floats and stay valid until
+ * infoli_output_wait returns; pinned memory (hipHostMalloc) lets the copy
+ * overlap the compute, pageable memory works but is staged. Errors
+ * (INFOLI_E_INVALID_ARG): no ring, n_steps < 1 or > R, steps not yet queued
+ * (step_begin + n_steps > the context's step count), steps already
+ * overwritten (step_begin < step count - R) or before the context's first
+ * step, host NULL or too small. The surrogate's macro steps do not write the
+ * ring (infoli_step_surrogate refuses a context that has one). */
+infoli_status infoli_output_copy_async(infoli_ctx *ctx, int64_t step_begin, int64_t n_steps, float *host,
+                                       int64_t cap_floats);
+
+/* Block the calling thread until every queued output copy has completed. */
+infoli_status infoli_output_wait(infoli_ctx *ctx);
+
 typedef struct infoli_info {
     int32_t n_instances;
     int64_t total_cells;

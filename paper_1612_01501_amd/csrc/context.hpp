@@ -142,6 +142,15 @@ struct infoli_ctx {
     int64_t* d_step = nullptr;
 
     int64_t step = 0;               // absolute index of the next step to run
+    // output streaming: Va after each step in a device ring, copied out on
+    // out_stream; out_first: oldest step whose output the ring can hold
+    float* out_ring = nullptr;
+    int32_t out_slots = 0;
+    int64_t out_first = 0;
+    hipStream_t out_stream = nullptr;
+    hipEvent_t out_ready = nullptr, out_done = nullptr;
+    bool out_pending = false;       // a copy queued since the compute stream last waited for copies
+    int64_t out_pending_begin = 0;  // smallest first step of those copies
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by starting buffer parity
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
@@ -165,12 +174,17 @@ struct infoli_ctx {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (stream) (void)hipStreamSynchronize(stream);
+        if (out_stream) (void)hipStreamSynchronize(out_stream);
         for (void* p : allocs) (void)hipFree(p);
         allocs.clear();
         if (fork_ev) (void)hipEventDestroy(fork_ev);
         if (join_ev) (void)hipEventDestroy(join_ev);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (side_stream) (void)hipStreamDestroy(side_stream);
+        if (out_stream) (void)hipStreamSynchronize(out_stream);
+        if (out_ready) (void)hipEventDestroy(out_ready);
+        if (out_done) (void)hipEventDestroy(out_done);
+        if (out_stream) (void)hipStreamDestroy(out_stream);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };

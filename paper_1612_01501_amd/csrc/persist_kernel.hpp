@@ -4,6 +4,7 @@
 // in LDS. The workgroup barrier at the end of each step is the step barrier
 // of Section 2.2 (step n+1 sees only step-n voltages); no cross-workgroup
 // synchronisation exists, so every workgroup always runs to completion.
+// Dry runs (timing) write the final state only: no spikes, outputs or flags.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -139,8 +140,9 @@ __global__ __launch_bounds__(kPersistBlock) void k_persist(StepArgs a, const flo
                     iapp += a.i_stream[d.stream_off + step * (int64_t)n + li];
                 float y[NSV];
                 cell_step(d.p, x[m], ig[m], iapp, a.dt, y);
+                if (a.out_slots && !a.dry) a.out_ring[out_slot(a, step) + cell] = y[SV_VA];
                 if (x[m][SV_VA] < 0.0f && y[SV_VA] >= 0.0f) {
-                    if (a.spike_cap > 0) {
+                    if (a.spike_cap > 0 && !a.dry) {
                         const float frac = (0.0f - x[m][SV_VA]) / (y[SV_VA] - x[m][SV_VA]);
                         a.spike_times[cell * a.spike_cap + (count[m] % a.spike_cap)] =
                             ((float)step + frac) * a.dt;
@@ -167,10 +169,10 @@ __global__ __launch_bounds__(kPersistBlock) void k_persist(StepArgs a, const flo
                 chk += x[m][v];
             }
             bad |= !isfinite(chk);
-            a.spike_count[cell] = count[m];
+            if (!a.dry) a.spike_count[cell] = count[m];
         }
     }
-    if (bad) atomicOr(a.flags, 1);
+    if (bad && !a.dry) atomicOr(a.flags, 1);
 }
 
 }  // namespace infoli

@@ -158,15 +158,18 @@ int pick_lanes(double mean_degree, int block) {
 void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, int block, unsigned ntiles,
                              size_t lds, int from, int64_t step_arg, int32_t off, int var) {
     if (ntiles == 0) return;
-    if (block == 1024)
-        hipLaunchKernelGGL(k_step<1024>, dim3(ntiles), dim3(1024), lds, st, a, c->state[from],
-                           c->state[from ^ 1], step_arg, off);
+    const float* xin = c->state[from];
+    float* xout = c->state[from ^ 1];
+    if (block == 1024 && var == kVarNoW)
+        hipLaunchKernelGGL((k_step<1024, kVarNoW>), dim3(ntiles), dim3(1024), lds, st, a, xin, xout, step_arg, off);
+    else if (block == 1024)
+        hipLaunchKernelGGL((k_step<1024, kVarAll>), dim3(ntiles), dim3(1024), lds, st, a, xin, xout, step_arg, off);
     else if (var == kVarNoGap)
-        hipLaunchKernelGGL((k_step<256, kVarNoGap>), dim3(ntiles), dim3(256), lds, st, a, c->state[from],
-                           c->state[from ^ 1], step_arg, off);
+        hipLaunchKernelGGL((k_step<256, kVarNoGap>), dim3(ntiles), dim3(256), lds, st, a, xin, xout, step_arg, off);
+    else if (var == kVarNoW)
+        hipLaunchKernelGGL((k_step<256, kVarNoW>), dim3(ntiles), dim3(256), lds, st, a, xin, xout, step_arg, off);
     else
-        hipLaunchKernelGGL(k_step<256>, dim3(ntiles), dim3(256), lds, st, a, c->state[from],
-                           c->state[from ^ 1], step_arg, off);
+        hipLaunchKernelGGL((k_step<256, kVarAll>), dim3(ntiles), dim3(256), lds, st, a, xin, xout, step_arg, off);
 }
 
 void infoli_rt::launch_groups(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
@@ -243,12 +246,14 @@ void finalize_tiles(infoli_ctx* c) {
         std::stable_sort(planned[g].begin(), planned[g].end(),
                          [](const auto& x, const auto& y) { return x.first > y.first; });
         tg.tiles.clear();
-        bool nogap = true;
+        bool nogap = true, now = true;
         for (const auto& pt : planned[g]) {
             tg.tiles.push_back(pt.second);
-            if (c->inst[pt.second.inst].conn != CONN_NONE) nogap = false;
+            const InstDesc& d = c->inst[pt.second.inst];
+            if (d.conn != CONN_NONE) nogap = false;
+            if (d.has_w) now = false;
         }
-        tg.var = nogap ? kVarNoGap : kVarAll;
+        tg.var = nogap ? kVarNoGap : now ? kVarNoW : kVarAll;
         if (tg.tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
         if (!tg.tiles.empty()) {
             if (tg.tiles.size() > tg.cap) {
@@ -511,8 +516,10 @@ void append_tune_cache(const std::string& path, const std::string& key, const Tu
 float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t, Tile* d_tmp) {
     std::vector<std::pair<double, Tile>> planned;
     size_t lds = 16;
+    int var = kVarNoW;          // the variant the step will launch these tiles with
     for (int k : ks) {
         InstDesc d = c->inst[k];
+        if (d.has_w) var = kVarAll;
         d.lanes_per_row = t.L;
         d.vd_lds = t.lds;
         d.bitmap = t.bm == 1;
@@ -532,11 +539,12 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
     a.tiles = d_tmp;
     a.dry = 1;
     const int block = t.block;
-    for (int w = 0; w < 2; ++w) launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0);
+    for (int w = 0; w < 2; ++w)
+        launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0, var);
     HIPX(hipEventRecord(c->ev0, c->stream));
     const int reps = 8;
     for (int w = 0; w < reps; ++w)
-        launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0);
+        launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0, var);
     HIPX(hipEventRecord(c->ev1, c->stream));
     HIPX(hipGetLastError());
     HIPX(hipEventSynchronize(c->ev1));
@@ -824,6 +832,36 @@ void autotune(infoli_ctx* c) {
     c->fork_groups = !(mode & 2);
 }
 
+void launch_persistent(infoli_ctx* c, int64_t n_steps, bool dry = false);
+
+// Dry timing of one persistent launch of kTimedSteps steps against as many
+// tiled step launches (launch mode: an upper bound of a graph replay); true
+// when the persistent kernel is faster. State buffers are rewritten by the
+// first real step, nothing else is touched.
+bool time_persistent_vs_tiles(infoli_ctx* c) {
+    constexpr int kTimedSteps = 40;
+    StepArgs a = make_args(c, false);
+    a.dry = 1;
+    float best_p = 1e30f, best_t = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+        HIPX(hipEventRecord(c->ev0, c->stream));
+        launch_persistent(c, kTimedSteps, true);
+        HIPX(hipEventRecord(c->ev1, c->stream));
+        HIPX(hipEventSynchronize(c->ev1));
+        float ms = 0.0f;
+        HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        best_p = std::min(best_p, ms);
+        HIPX(hipEventRecord(c->ev0, c->stream));
+        for (int k = 0; k < kTimedSteps; ++k) launch_groups(c, c->stream, a, c->cur, c->step, 0, false);
+        HIPX(hipEventRecord(c->ev1, c->stream));
+        HIPX(hipEventSynchronize(c->ev1));
+        HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        best_t = std::min(best_t, ms);
+    }
+    HIPX(hipGetLastError());
+    return best_p <= best_t;
+}
+
 void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t ninst,
                    const infoli_options* opt) {
     if (!specs || ninst < 1) fail(INFOLI_E_INVALID_ARG, "need at least one network spec");
@@ -845,6 +883,9 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         fail(INFOLI_E_INVALID_ARG, "csr_path must be 0, 1, 2, 3 or 4");
     if (c->opt.tile_rows < 0 || c->opt.tile_rows > kMaxTileRows)
         fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
+    if (c->opt.output_ring_steps < 0 || c->opt.output_ring_steps > (1 << 20))
+        fail(INFOLI_E_INVALID_ARG, "output_ring_steps must be in [0, 2^20]");
+    if (c->opt.reserved1 != 0) fail(INFOLI_E_INVALID_ARG, "reserved1 must be 0");
     for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
     for (int k = 1; k < ninst; ++k) {
         if (specs[k].step0 != specs[0].step0) fail(INFOLI_E_INVALID_ARG, "all networks must share step0");
@@ -919,8 +960,17 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     if (c->opt.step_mode == INFOLI_MODE_PERSISTENT && max_n > kPersistCells)
         fail(INFOLI_E_UNSUPPORTED, "PERSISTENT mode holds networks of at most %d cells (largest: %d)",
              kPersistCells, max_n);
-    if (c->opt.step_mode == INFOLI_MODE_AUTO && ninst == 1 && max_n <= 1024)
-        c->opt.step_mode = INFOLI_MODE_PERSISTENT;   // real-time sized network: one workgroup
+    // AUTO with one real-time sized network: one persistent workgroup or the
+    // tiled launches, whichever steps faster (timed below when autotuning,
+    // else persistent only where a row is cheap for one thread to walk)
+    bool persist_candidate = false;
+    if (c->opt.step_mode == INFOLI_MODE_AUTO && ninst == 1 && max_n <= 1024) {
+        const infoli_network_spec& s0 = specs[0];
+        const bool cheap_rows = s0.conn == INFOLI_CONN_NONE || s0.conn == INFOLI_CONN_UNIFORM_ALL ||
+                                (s0.conn == INFOLI_CONN_CSR && s0.nnz <= 8 * (int64_t)s0.n_cells);
+        if (c->opt.autotune) persist_candidate = true;
+        else if (cheap_rows) c->opt.step_mode = INFOLI_MODE_PERSISTENT;
+    }
     c->persist_cpt = 1;
     while (c->persist_cpt * kPersistBlock < max_n) c->persist_cpt *= 2;
     c->total_cells = cells;
@@ -966,6 +1016,11 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     HIPX(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
     HIPX(hipEventCreate(&c->ev0));
     HIPX(hipEventCreate(&c->ev1));
+    if (c->opt.output_ring_steps > 0) {
+        HIPX(hipStreamCreateWithFlags(&c->out_stream, hipStreamNonBlocking));
+        HIPX(hipEventCreateWithFlags(&c->out_ready, hipEventDisableTiming));
+        HIPX(hipEventCreateWithFlags(&c->out_done, hipEventDisableTiming));
+    }
 
     // ---- host staging of everything, then one copy each (Section 2.4.3)
     const int64_t S = c->stride;
@@ -1032,6 +1087,11 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->d_spk_times = c->alloc<float>((size_t)S * std::max(cap, 1));
     c->d_flags = c->alloc<int32_t>(4);
     c->d_step = c->alloc<int64_t>(1);
+    if (c->opt.output_ring_steps > 0) {
+        c->out_slots = c->opt.output_ring_steps;
+        c->out_ring = c->alloc<float>((size_t)c->out_slots * S);
+        c->out_first = c->step;
+    }
 
     HIPX(hipMemcpy(c->state[0], h_state.data(), sizeof(float) * h_state.size(), hipMemcpyHostToDevice));
     HIPX(hipMemcpy(c->state[1], h_state.data(), sizeof(float) * h_state.size(), hipMemcpyHostToDevice));
@@ -1071,6 +1131,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
             }
     finalize_tiles(c);
     HIPX(hipDeviceSynchronize());
+    if (persist_candidate && time_persistent_vs_tiles(c)) c->opt.step_mode = INFOLI_MODE_PERSISTENT;
 }
 
 }  // namespace
@@ -1103,6 +1164,8 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     a.dt = c->dt;
     a.spike_cap = c->opt.max_spikes_per_cell;
     a.gap_only = 0;
+    a.out_slots = c->out_slots;
+    a.out_ring = c->out_ring;
     return a;
 }
 
@@ -1128,8 +1191,9 @@ hipGraphExec_t get_graph(infoli_ctx* c, int parity) {
     return ex;
 }
 
-void launch_persistent(infoli_ctx* c, int64_t n_steps) {
-    const StepArgs a = make_args(c, false);
+void launch_persistent(infoli_ctx* c, int64_t n_steps, bool dry) {
+    StepArgs a = make_args(c, false);
+    a.dry = dry ? 1 : 0;
     const dim3 grid((unsigned)c->n_inst), block(kPersistBlock);
     const float* xin = c->state[c->cur];
     float* xout = c->state[c->cur ^ 1];
@@ -1139,12 +1203,18 @@ void launch_persistent(infoli_ctx* c, int64_t n_steps) {
         case 4: hipLaunchKernelGGL(k_persist<4>, grid, block, 0, c->stream, a, xin, xout, c->step, n_steps); break;
         default: hipLaunchKernelGGL(k_persist<8>, grid, block, 0, c->stream, a, xin, xout, c->step, n_steps); break;
     }
+    if (dry) return;
     c->cur ^= 1;
     c->step += n_steps;
 }
 
 void run_steps(infoli_ctx* c, int64_t n_steps) {
     if (n_steps < 0) fail(INFOLI_E_INVALID_ARG, "n_steps must be >= 0");
+    // steps that would overwrite ring slots of a queued output copy wait for it
+    if (c->out_pending && c->step + n_steps - c->out_slots > c->out_pending_begin) {
+        HIPX(hipStreamWaitEvent(c->stream, c->out_done, 0));
+        c->out_pending = false;
+    }
     HIPX(hipEventRecord(c->ev0, c->stream));
     int64_t left = n_steps;
     const int mode = c->opt.step_mode;
@@ -1321,6 +1391,12 @@ infoli_status infoli_write_state(infoli_ctx* ctx, int32_t instance, const float*
         HIPX(hipMemcpy2D(ctx->state[ctx->cur] + d.cell_off, sizeof(float) * ctx->stride, host_soa,
                          sizeof(float) * d.n, sizeof(float) * d.n, INFOLI_NUM_STATE,
                          hipMemcpyHostToDevice));
+        if (step != ctx->step && ctx->out_stream) {
+            // a new step count: the ring's outputs belong to the old one
+            HIPX(hipStreamSynchronize(ctx->out_stream));
+            ctx->out_pending = false;
+            ctx->out_first = step;
+        }
         ctx->step = step;
     });
 }
@@ -1362,6 +1438,51 @@ infoli_status infoli_read_spikes(infoli_ctx* ctx, int32_t instance, int32_t* cou
         if (times_ms && cap > 0)
             HIPX(hipMemcpy(times_ms, ctx->d_spk_times + d.cell_off * cap, sizeof(float) * d.n * cap,
                            hipMemcpyDeviceToHost));
+    });
+}
+
+infoli_status infoli_output_copy_async(infoli_ctx* ctx, int64_t step_begin, int64_t n_steps, float* host,
+                                       int64_t cap_floats) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        const int64_t R = ctx->out_slots;
+        if (R == 0) fail(INFOLI_E_INVALID_ARG, "the context has no output ring (output_ring_steps = 0)");
+        if (n_steps < 1 || n_steps > R) fail(INFOLI_E_INVALID_ARG, "n_steps must be in [1, %lld]", (long long)R);
+        if (!host) fail(INFOLI_E_INVALID_ARG, "host is NULL");
+        const int64_t cells = ctx->total_cells;
+        if (cap_floats < n_steps * cells) fail(INFOLI_E_INVALID_ARG, "host capacity too small");
+        if (step_begin + n_steps > ctx->step)
+            fail(INFOLI_E_INVALID_ARG, "steps %lld..%lld are not queued yet (next step %lld)",
+                 (long long)step_begin, (long long)(step_begin + n_steps - 1), (long long)ctx->step);
+        if (step_begin < ctx->out_first || step_begin < ctx->step - R)
+            fail(INFOLI_E_INVALID_ARG, "the output of step %lld is no longer in the ring", (long long)step_begin);
+        HIPX(hipEventRecord(ctx->out_ready, ctx->stream));
+        HIPX(hipStreamWaitEvent(ctx->out_stream, ctx->out_ready, 0));
+        int64_t done = 0;
+        while (done < n_steps) {
+            const int64_t slot = (step_begin + done) % R;
+            const int64_t len = std::min(n_steps - done, R - slot);
+            HIPX(hipMemcpy2DAsync(host + done * cells, sizeof(float) * cells, ctx->out_ring + slot * ctx->stride,
+                                  sizeof(float) * ctx->stride, sizeof(float) * cells, len, hipMemcpyDeviceToHost,
+                                  ctx->out_stream));
+            done += len;
+        }
+        HIPX(hipEventRecord(ctx->out_done, ctx->out_stream));
+        if (!ctx->out_pending || step_begin < ctx->out_pending_begin) ctx->out_pending_begin = step_begin;
+        ctx->out_pending = true;
+    });
+}
+
+infoli_status infoli_output_wait(infoli_ctx* ctx) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(ctx, [&] {
+        if (ctx->out_stream) HIPX(hipStreamSynchronize(ctx->out_stream));
     });
 }
 

@@ -31,6 +31,7 @@
 // Every reduction has a fixed order: results are bitwise reproducible.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 #include "cell_model.hpp"
@@ -122,8 +123,14 @@ struct StepArgs {
     int32_t spike_cap;
     int32_t gap_only;
     int32_t dry;               // timing runs: write the next state only
-    int32_t pad1;
+    int32_t out_slots;         // output ring: slots (steps), 0 => none
+    float* out_ring;           // [out_slots][stride]: Va after step s in slot s mod out_slots
 };
+
+// Output ring slot of step s (s >= 0).
+__device__ __forceinline__ int64_t out_slot(const StepArgs& a, int64_t s) {
+    return (s % a.out_slots) * a.stride;
+}
 
 __device__ __forceinline__ float wave_sum_xor(float v, int width) {
     // butterfly over `width` consecutive lanes (power of two <= 64)
@@ -605,10 +612,23 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
     }
 }
 
+// f(std::true_type) for a network with per-edge weights when the launch
+// compiles those paths (W), else f(std::false_type).
+template <bool W, typename F>
+__device__ __forceinline__ void by_weights(const InstDesc& d, F&& f) {
+    if constexpr (W) {
+        if (d.has_w) {
+            f(std::true_type{});
+            return;
+        }
+    }
+    f(std::false_type{});
+}
+
 // CSR paths of one gap form (SGJ: simplified). The old column-blocked
 // gathers (no chunked copy of the lists) exist for the realistic form only;
 // a simplified network without chunks takes the plain gathers.
-template <int BLOCK, bool SGJ>
+template <int BLOCK, bool SGJ, bool W>
 __device__ __forceinline__ void gap_csr_form(const StepArgs& a, const InstDesc& d, const Tile& t,
                                              const float* __restrict__ vd, float* s_vd, float* s_part,
                                              float* s_ig) {
@@ -616,63 +636,48 @@ __device__ __forceinline__ void gap_csr_form(const StepArgs& a, const InstDesc& 
     // places them there); elsewhere the same rows take the gathers below
     if constexpr (BLOCK == 1024) {
         if (d.blocked && d.cb_off >= 0) {
-            if (d.has_w) gap_chunks_blocked<BLOCK, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_chunks_blocked<BLOCK, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            by_weights<W>(d, [&](auto hw) {
+                gap_chunks_blocked<BLOCK, decltype(hw)::value, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            });
             return;
         }
         if constexpr (!SGJ) {
             if (d.blocked) {
-                if (d.col16) {
-                    if (d.has_w) gap_csr_blocked<BLOCK, true, true>(a, d, t, vd, s_vd, s_part, s_ig);
-                    else gap_csr_blocked<BLOCK, true, false>(a, d, t, vd, s_vd, s_part, s_ig);
-                } else {
-                    if (d.has_w) gap_csr_blocked<BLOCK, false, true>(a, d, t, vd, s_vd, s_part, s_ig);
-                    else gap_csr_blocked<BLOCK, false, false>(a, d, t, vd, s_vd, s_part, s_ig);
-                }
+                by_weights<W>(d, [&](auto hw) {
+                    if (d.col16) gap_csr_blocked<BLOCK, true, decltype(hw)::value>(a, d, t, vd, s_vd, s_part, s_ig);
+                    else gap_csr_blocked<BLOCK, false, decltype(hw)::value>(a, d, t, vd, s_vd, s_part, s_ig);
+                });
                 return;
             }
         }
     }
-    const bool lds = d.vd_lds;
-    if (d.chunked && d.ca_off >= 0) {
-        if (lds) {
-            for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k] * kPreScale;
-            __syncthreads();
-            if (d.has_w) gap_chunks<BLOCK, true, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_chunks<BLOCK, true, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-        } else {
-            if (d.has_w) gap_chunks<BLOCK, false, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_chunks<BLOCK, false, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-        }
-        return;
-    }
-    if (lds) {
+    if (d.vd_lds) {
         for (int k = threadIdx.x; k < d.n; k += BLOCK) s_vd[k] = vd[k] * kPreScale;
         __syncthreads();
-        if (d.col16) {
-            if (d.has_w) gap_csr_impl<BLOCK, true, true, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_csr_impl<BLOCK, true, true, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-        } else {
-            if (d.has_w) gap_csr_impl<BLOCK, true, false, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_csr_impl<BLOCK, true, false, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-        }
-    } else {
-        if (d.col16) {
-            if (d.has_w) gap_csr_impl<BLOCK, false, true, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_csr_impl<BLOCK, false, true, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-        } else {
-            if (d.has_w) gap_csr_impl<BLOCK, false, false, true, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-            else gap_csr_impl<BLOCK, false, false, false, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
-        }
     }
+    by_weights<W>(d, [&](auto hw) {
+        constexpr bool HW = decltype(hw)::value;
+        if (d.chunked && d.ca_off >= 0) {
+            if (d.vd_lds) gap_chunks<BLOCK, true, HW, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_chunks<BLOCK, false, HW, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+        } else if (d.vd_lds) {
+            if (d.col16) gap_csr_impl<BLOCK, true, true, HW, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, true, false, HW, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+        } else {
+            if (d.col16) gap_csr_impl<BLOCK, false, true, HW, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+            else gap_csr_impl<BLOCK, false, false, HW, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);
+        }
+    });
 }
 
-template <int BLOCK>
+// W: the launch may hold networks with per-edge weights (their paths are
+// compiled in; they hold a batch of weights in registers).
+template <int BLOCK, bool W>
 __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, const Tile& t,
                                         const float* __restrict__ vd, float* s_vd, float* s_part,
                                         float* s_ig) {
-    if (d.sgj) gap_csr_form<BLOCK, true>(a, d, t, vd, s_vd, s_part, s_ig);
-    else gap_csr_form<BLOCK, false>(a, d, t, vd, s_vd, s_part, s_ig);
+    if (d.sgj) gap_csr_form<BLOCK, true, W>(a, d, t, vd, s_vd, s_part, s_ig);
+    else gap_csr_form<BLOCK, false, W>(a, d, t, vd, s_vd, s_part, s_ig);
 }
 
 // Bitmap words of a network: group gr (128 senders), row r (padded to a
@@ -761,9 +766,11 @@ __device__ __forceinline__ float evoked_input(const StepArgs& a, const InstDesc&
 
 // Kernel variants by the tiles a launch holds. kVarAll: any tile. kVarNoGap:
 // every tile belongs to a network without gap junctions (the compartment
-// update alone), compiled without the gap paths and their registers, so that
-// more waves per SIMD keep state loads in flight.
-enum : int { kVarAll = 0, kVarNoGap = 1 };
+// update alone). kVarNoW: no network has per-edge weights. The narrow
+// variants are compiled without the paths they exclude and their registers
+// (kVarNoW: 85 VGPRs against 124 in 256-thread workgroups), so that more
+// waves per SIMD keep loads in flight.
+enum : int { kVarAll = 0, kVarNoGap = 1, kVarNoW = 2 };
 
 template <int BLOCK, int VAR = kVarAll>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restrict__ xin,
@@ -810,7 +817,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
             case CONN_DENSE: gap_dense<BLOCK>(a, d, t, vd, s_ig); break;
             case CONN_CSR:
                 if (d.bitmap) gap_bitmap<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
-                else gap_csr<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
+                else gap_csr<BLOCK, VAR != kVarNoW>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);
                 break;
             default:
                 for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
@@ -844,6 +851,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
         }
         if (a.dry) return;
         if (!isfinite(chk)) atomicOr(a.flags, 1);
+        if (part == 0 && a.out_slots) a.out_ring[out_slot(a, step) + cell] = y[SV_VA];
         // axon output (wave 0): upward 0 mV crossing, time interpolated within the step
         if (part == 0 && x[SV_VA] < 0.0f && y[SV_VA] >= 0.0f) {
             const int c = a.spike_count[cell];
@@ -864,6 +872,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
         }
         if (a.dry) return;
         if (!isfinite(chk)) atomicOr(a.flags, 1);
+        if (a.out_slots) a.out_ring[out_slot(a, step) + cell] = y[SV_VA];
         // axon output: upward 0 mV crossing, time interpolated within the step
         if (x[SV_VA] < 0.0f && y[SV_VA] >= 0.0f) {
             const int c = a.spike_count[cell];

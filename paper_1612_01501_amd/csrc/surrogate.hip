@@ -349,6 +349,9 @@ infoli_status infoli_step_surrogate(infoli_ctx* ctx, int64_t n_macro, const info
         infoli_default_drift_cfg(&dc);
         if (cfg) dc = *cfg;
         if (n_macro < 0) fail(INFOLI_E_INVALID_ARG, "n_macro must be >= 0");
+        if (ctx->out_slots > 0)
+            fail(INFOLI_E_INVALID_ARG, "surrogate macro steps do not write the output ring; "
+                                       "use a context without output_ring_steps");
         if (dc.mode != INFOLI_SURROGATE_MLP && dc.mode != INFOLI_SURROGATE_PLAIN_HOLD)
             fail(INFOLI_E_INVALID_ARG, "unknown surrogate mode %d", dc.mode);
         if (dc.sample_every < 0 || dc.hold_steps < 0 || !(dc.theta_mv >= 0.0f) || std::isnan(dc.v_max) ||

@@ -30,7 +30,8 @@ EXPORTS = (
     "infoli_default_options", "infoli_default_params", "infoli_rest_state", "infoli_init",
     "infoli_batch_init", "infoli_step", "infoli_sync", "infoli_read_state",
     "infoli_read_state_device", "infoli_write_state", "infoli_read_gap_current",
-    "infoli_read_spikes", "infoli_clear_spikes", "infoli_get_info", "infoli_last_step_ms",
+    "infoli_read_spikes", "infoli_clear_spikes", "infoli_output_copy_async", "infoli_output_wait",
+    "infoli_get_info", "infoli_last_step_ms",
     "infoli_state_var_name", "infoli_last_error", "infoli_destroy",
     "infoli_default_train_cfg", "infoli_default_drift_cfg", "infoli_surrogate_train",
     "infoli_surrogate_get", "infoli_surrogate_set", "infoli_step_surrogate",
@@ -72,7 +73,8 @@ class Options(ctypes.Structure):
                 ("graph_chunk", ctypes.c_int32), ("max_spikes_per_cell", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("csr_path", ctypes.c_int32)]
+                ("csr_path", ctypes.c_int32), ("output_ring_steps", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -141,6 +143,8 @@ def lib():
     L.infoli_read_gap_current.argtypes = [vp, ctypes.c_int32, _PF, ctypes.c_int64]
     L.infoli_read_spikes.argtypes = [vp, ctypes.c_int32, _PI32, ctypes.c_int64, _PF, ctypes.c_int64]
     L.infoli_clear_spikes.argtypes = [vp]
+    L.infoli_output_copy_async.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64]
+    L.infoli_output_wait.argtypes = [vp]
     L.infoli_get_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.infoli_last_step_ms.argtypes = [vp, _PF]
     L.infoli_state_var_name.argtypes = [ctypes.c_int32]
@@ -376,6 +380,17 @@ class Simulator:
         _check(lib().infoli_read_spikes(self._ctx, k, counts.ctypes.data_as(_PI32), n,
                                         _fptr(times), 0 if times is None else times.size), self._ctx)
         return counts, times
+
+    # ----------------------------------------------------------- output streaming
+    def output_copy_async(self, step_begin: int, n_steps: int, host_ptr: int, cap_floats: int):
+        """Queue the copy of the axon voltages after steps [step_begin,
+        step_begin + n_steps) into host memory at host_ptr ([n_steps][total
+        cells] fp32; pinned memory for overlap); needs output_ring_steps."""
+        _check(lib().infoli_output_copy_async(self._ctx, int(step_begin), int(n_steps),
+                                              ctypes.c_void_p(host_ptr), int(cap_floats)), self._ctx)
+
+    def output_wait(self):
+        _check(lib().infoli_output_wait(self._ctx), self._ctx)
 
     def clear_spikes(self):
         _check(lib().infoli_clear_spikes(self._ctx), self._ctx)
