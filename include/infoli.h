@@ -130,6 +130,10 @@ typedef struct infoli_network_spec {
     int64_t step0;              /* absolute index of the first step (resume); >= 0        */
     int32_t gap_kind;           /* infoli_gap_kind; 0 (a zeroed spec) is the realistic form */
     int32_t reserved0;          /* must be 0                                               */
+    const float *cell_params;   /* optional [n][INFOLI_NUM_PARAMS]: each cell's own values
+                                   (Section 2.2: 20 per neuron), checked like params;
+                                   NULL => params (or the defaults) for every cell. Not with
+                                   PERSISTENT mode or the surrogate (INFOLI_E_UNSUPPORTED) */
 } infoli_network_spec;
 
 /* How steps are driven on the device. */

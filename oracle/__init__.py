@@ -44,7 +44,7 @@ def _make_net_struct(real):
         ("pulse_n1", P(ctypes.c_int64)), ("pulse_c0", P(ctypes.c_int32)),
         ("pulse_c1", P(ctypes.c_int32)), ("pulse_amp", P(real)),
         ("i_stream", P(real)), ("i_stream_steps", ctypes.c_int64),
-        ("reverse_j", ctypes.c_int32), ("sgj", ctypes.c_int32)]})
+        ("reverse_j", ctypes.c_int32), ("sgj", ctypes.c_int32), ("cell_params", P(real))]})
 
 
 _NET64 = _make_net_struct(ctypes.c_double)
@@ -114,6 +114,8 @@ class Oracle:
                                  for p in net.pulses] or [0], np.int32)
         keep["p_a"] = np.array([p.amplitude for p in net.pulses] or [0], R)
         keep["i_stream"] = self._arr(i_stream)
+        cp = getattr(net, "cell_params", None)
+        keep["cell_params"] = None if cp is None else np.ascontiguousarray(cp, dtype=R).reshape(net.n, 20)
         cr = self.c_real
         s = self.Net(n=net.n, conn=CONN[net.conn], g=net.g, dt=net.dt,
                      w_dense=_ptr(keep["w_dense"], cr), row_ptr=_ptr(keep["row_ptr"], ctypes.c_int64),
@@ -127,7 +129,8 @@ class Oracle:
                      i_stream=_ptr(keep["i_stream"], cr),
                      i_stream_steps=0 if i_stream is None else int(i_stream.shape[0]),
                      reverse_j=1 if reverse_j else 0,
-                     sgj=1 if getattr(net, "gap", "rgj") == "sgj" else 0)
+                     sgj=1 if getattr(net, "gap", "rgj") == "sgj" else 0,
+                     cell_params=_ptr(keep["cell_params"], cr))
         return s, keep
 
     # ------------------------------------------------------------ API
@@ -139,9 +142,14 @@ class Oracle:
         return x
 
     def initial_state(self, net, v0: float = -60.0) -> np.ndarray:
-        """Rest state for every cell plus the network's voltage jitter, [S][n]."""
-        r = self.rest(net.params, v0).astype(np.float64)
-        x = np.repeat(r[:, None], net.n, axis=1)
+        """Rest state for every cell (each cell's own, when the network has
+        per-cell parameters) plus the network's voltage jitter, [S][n]."""
+        cp = getattr(net, "cell_params", None)
+        if cp is None:
+            r = self.rest(net.params, v0).astype(np.float64)
+            x = np.repeat(r[:, None], net.n, axis=1)
+        else:
+            x = np.stack([self.rest(cp[i], v0).astype(np.float64) for i in range(net.n)], axis=1)
         if net.jitter is not None:
             for row, v in enumerate((0, 5, 11)):
                 x[v] += net.jitter[row]

@@ -27,6 +27,11 @@ struct CellParams {
 };
 static_assert(sizeof(CellParams) == 20 * sizeof(float), "20 parameters");
 
+// Floating-point contraction inside the compartment functions is limited
+// to single expressions (the pragma below), so a cell's arithmetic is the
+// same in every kernel that inlines it; the Euler updates are explicit
+// fused multiply-adds.
+//
 // Arithmetic. Every exponential has an argument affine in one voltage,
 // written (v - v0) * a: it is evaluated as 2^((v - v0) * a log2 e) on the
 // transcendental unit (v_exp_f32, 1 ulp) with log2 e folded into the
@@ -76,18 +81,21 @@ __device__ __forceinline__ float ratio_expm1(float x, float s) {
 // iapp: evoked input into the dendrite, dt in ms.
 __device__ __forceinline__ void cell_step_dendrite(const CellParams& p, const float* __restrict__ x,
                                                    float igap, float iapp, float dt, float* __restrict__ y) {
+#pragma clang fp contract(on)
     const float vd = x[SV_VD], vs = x[SV_VS];
 
     // Dendrite: high-threshold Ca (r^2), Ca-activated K (s), h current (q),
     // leak, coupling to the soma, gap junctions and the evoked input.
+    // (each current's conductance factor times its driving force, the net
+    // current accumulated with fused multiply-adds)
     const float icah = p.gCaH * x[SV_R] * x[SV_R] * (vd - p.eCa);
-    const float ikca = p.gKCa * x[SV_S] * (vd - p.eK);
-    const float ih = p.gH * x[SV_Q] * (vd - p.eH);
-    const float ild = p.gLd * (vd - p.eL);
-    const float ids = p.gInt * rcp(1.0f - p.p1) * (vd - vs);
-    const float dvd = iapp - igap - ids - icah - ikca - ih - ild;
+    float dvd = iapp - igap - icah;
+    dvd = fmaf(-(p.gInt * rcp(1.0f - p.p1)), vd - vs, dvd);       // to the soma
+    dvd = fmaf(-(p.gKCa * x[SV_S]), vd - p.eK, dvd);                // Ca-activated K
+    dvd = fmaf(-(p.gH * x[SV_Q]), vd - p.eH, dvd);                  // h current
+    dvd = fmaf(-p.gLd, vd - p.eL, dvd);                             // leak
 
-    const float dca = -3.0f * icah - 0.075f * x[SV_CA];
+    const float dca = fmaf(-3.0f, icah, -0.075f * x[SV_CA]);
 
     const float ar = 1.7f * boltz(vd, 5.0f, l2(-1.0 / 13.9));
     const float br = 0.02f * ratio_expm1(vd + 8.5f, 5.0f);
@@ -102,32 +110,31 @@ __device__ __forceinline__ void cell_step_dendrite(const CellParams& p, const fl
     const float dq = (qinf - x[SV_Q]) * rq;
 
     // C_m = 1 uF/cm^2: dV/dt equals the net inward current density.
-    y[SV_VD] = vd + dt * dvd;
-    y[SV_CA] = x[SV_CA] + dt * dca;
-    y[SV_R] = x[SV_R] + dt * dr;
-    y[SV_S] = x[SV_S] + dt * ds;
-    y[SV_Q] = x[SV_Q] + dt * dq;
+    y[SV_VD] = fmaf(dt, dvd, vd);
+    y[SV_CA] = fmaf(dt, dca, x[SV_CA]);
+    y[SV_R] = fmaf(dt, dr, x[SV_R]);
+    y[SV_S] = fmaf(dt, ds, x[SV_S]);
+    y[SV_Q] = fmaf(dt, dq, x[SV_Q]);
 }
 
 // Soma part: y[Vs, k, l, h, n, x].
 __device__ __forceinline__ void cell_step_soma(const CellParams& p, const float* __restrict__ x, float dt,
                                                float* __restrict__ y) {
+#pragma clang fp contract(on)
     const float vd = x[SV_VD], vs = x[SV_VS], va = x[SV_VA];
 
     // Soma: low-threshold Ca (k^3 l), Na (instantaneous m^3, h), delayed
     // rectifier K (n^4), K (x^4), leak, coupling to dendrite and axon.
     const float kk = x[SV_K];
-    const float icaL = p.gCaL * kk * kk * kk * x[SV_L] * (vs - p.eCa);
     const float ms = boltz(vs, -30.0f, l2(-1.0 / 5.5));
-    const float inas = p.gNaS * ms * ms * ms * x[SV_H] * (vs - p.eNa);
     const float n2 = x[SV_N] * x[SV_N];
-    const float ikdr = p.gKdrS * n2 * n2 * (vs - p.eK);
     const float x2 = x[SV_X] * x[SV_X];
-    const float iks = p.gKS * x2 * x2 * (vs - p.eK);
-    const float ils = p.gLs * (vs - p.eL);
-    const float isd = p.gInt * rcp(p.p1) * (vs - vd);
-    const float isa = p.gInt * rcp(1.0f - p.p2) * (vs - va);
-    const float dvs = -(icaL + inas + ikdr + iks + ils + isd + isa);
+    float dvs = -(p.gCaL * kk * kk * kk * x[SV_L]) * (vs - p.eCa);   // low-threshold Ca
+    dvs = fmaf(-(p.gNaS * ms * ms * ms * x[SV_H]), vs - p.eNa, dvs);  // Na
+    dvs = fmaf(-(p.gKdrS * n2 * n2 + p.gKS * x2 * x2), vs - p.eK, dvs); // delayed rectifier K, K
+    dvs = fmaf(-p.gLs, vs - p.eL, dvs);                                // leak
+    dvs = fmaf(-(p.gInt * rcp(p.p1)), vs - vd, dvs);                   // to the dendrite
+    dvs = fmaf(-(p.gInt * rcp(1.0f - p.p2)), vs - va, dvs);            // to the axon
 
     const float dk = boltz(vs, -61.0f, l2(-1.0 / 4.2)) - kk;              // tau_k = 1 ms
     // tau_l = 20 e1 / (1 + e2) + 35, e1 = exp((vs + 160)/30), e2 = exp((vs + 84)/7.3):
@@ -143,27 +150,27 @@ __device__ __forceinline__ void cell_step_soma(const CellParams& p, const float*
     const float bxs = 1.69f * exp_aff(vs, -35.0f, l2(-0.0125));
     const float dx = axs - (axs + bxs) * x[SV_X];
 
-    y[SV_VS] = vs + dt * dvs;
-    y[SV_K] = kk + dt * dk;
-    y[SV_L] = x[SV_L] + dt * dl;
-    y[SV_H] = x[SV_H] + dt * dh;
-    y[SV_N] = x[SV_N] + dt * dn;
-    y[SV_X] = x[SV_X] + dt * dx;
+    y[SV_VS] = fmaf(dt, dvs, vs);
+    y[SV_K] = fmaf(dt, dk, kk);
+    y[SV_L] = fmaf(dt, dl, x[SV_L]);
+    y[SV_H] = fmaf(dt, dh, x[SV_H]);
+    y[SV_N] = fmaf(dt, dn, x[SV_N]);
+    y[SV_X] = fmaf(dt, dx, x[SV_X]);
 }
 
 // Axon part: y[Va, ha, xa].
 __device__ __forceinline__ void cell_step_axon(const CellParams& p, const float* __restrict__ x, float dt,
                                                float* __restrict__ y) {
+#pragma clang fp contract(on)
     const float vs = x[SV_VS], va = x[SV_VA];
 
     // Axon: Na (instantaneous m^3, h), K (x^4), leak, coupling to the soma.
     const float ma = boltz(va, -30.0f, l2(-1.0 / 5.5));
-    const float inaa = p.gNaA * ma * ma * ma * x[SV_HA] * (va - p.eNa);
     const float xa2 = x[SV_XA] * x[SV_XA];
-    const float ika = p.gKA * xa2 * xa2 * (va - p.eK);
-    const float ila = p.gLa * (va - p.eL);
-    const float ias = p.gInt * rcp(p.p2) * (va - vs);
-    const float dva = -(ika + ila + inaa + ias);
+    float dva = -(p.gKA * xa2 * xa2) * (va - p.eK);                    // K
+    dva = fmaf(-p.gLa, va - p.eL, dva);                                // leak
+    dva = fmaf(-(p.gNaA * ma * ma * ma * x[SV_HA]), va - p.eNa, dva);  // Na
+    dva = fmaf(-(p.gInt * rcp(p.p2)), va - vs, dva);                   // to the soma
 
     // tau_ha = 1.5 exp(-(va + 40)/33): 1/tau_ha = exp((va + 40)/33) / 1.5
     const float dha = (boltz(va, -60.0f, l2(1.0 / 5.8)) - x[SV_HA]) * (exp_aff(va, -40.0f, l2(1.0 / 33.0)) * (1.0f / 1.5f));
@@ -171,9 +178,9 @@ __device__ __forceinline__ void cell_step_axon(const CellParams& p, const float*
     const float bxa = 1.69f * exp_aff(va, -35.0f, l2(-0.0125));
     const float dxa = axa - (axa + bxa) * x[SV_XA];
 
-    y[SV_VA] = va + dt * dva;
-    y[SV_HA] = x[SV_HA] + dt * dha;
-    y[SV_XA] = x[SV_XA] + dt * dxa;
+    y[SV_VA] = fmaf(dt, dva, va);
+    y[SV_HA] = fmaf(dt, dha, x[SV_HA]);
+    y[SV_XA] = fmaf(dt, dxa, x[SV_XA]);
 }
 
 // Next state of one cell. x: previous state, igap: gap current leaving the

@@ -140,6 +140,7 @@ struct infoli_ctx {
     float* d_spk_times = nullptr;
     int32_t* d_flags = nullptr;
     int64_t* d_step = nullptr;
+    float* d_cparams = nullptr;     // per-cell parameters [20][stride], networks that have them
 
     int64_t step = 0;               // absolute index of the next step to run
     // output streaming: Va after each step in a device ring, copied out on

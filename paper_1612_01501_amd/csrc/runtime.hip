@@ -122,6 +122,16 @@ void validate_spec(const infoli_network_spec& s, int k) {
     if (s.params && (s.params[13] <= 0.0f || s.params[13] >= 1.0f || s.params[14] <= 0.0f ||
                      s.params[14] >= 1.0f))
         fail(INFOLI_E_INVALID_ARG, "network %d: area ratios p1, p2 must lie in (0, 1)", k);
+    if (s.cell_params) {
+        if (!finite_all(s.cell_params, (int64_t)INFOLI_NUM_PARAMS * n))
+            fail(INFOLI_E_INVALID_ARG, "network %d: non-finite per-cell parameter", k);
+        for (int64_t i = 0; i < n; ++i) {
+            const float* q = s.cell_params + i * INFOLI_NUM_PARAMS;
+            if (q[13] <= 0.0f || q[13] >= 1.0f || q[14] <= 0.0f || q[14] >= 1.0f)
+                fail(INFOLI_E_INVALID_ARG, "network %d: cell %lld: area ratios p1, p2 must lie in (0, 1)", k,
+                     (long long)i);
+        }
+    }
     if (s.init_state && !finite_all(s.init_state, INFOLI_NUM_STATE * n))
         fail(INFOLI_E_INVALID_ARG, "network %d: non-finite initial state", k);
     if (s.i_bias && !finite_all(s.i_bias, n)) fail(INFOLI_E_INVALID_ARG, "network %d: non-finite bias", k);
@@ -250,8 +260,8 @@ void finalize_tiles(infoli_ctx* c) {
         for (const auto& pt : planned[g]) {
             tg.tiles.push_back(pt.second);
             const InstDesc& d = c->inst[pt.second.inst];
-            if (d.conn != CONN_NONE) nogap = false;
-            if (d.has_w) now = false;
+            if (d.conn != CONN_NONE || d.pcell) nogap = false;
+            if (d.has_w || d.pcell) now = false;
         }
         tg.var = nogap ? kVarNoGap : now ? kVarNoW : kVarAll;
         if (tg.tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
@@ -519,7 +529,7 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
     int var = kVarNoW;          // the variant the step will launch these tiles with
     for (int k : ks) {
         InstDesc d = c->inst[k];
-        if (d.has_w) var = kVarAll;
+        if (d.has_w || d.pcell) var = kVarAll;
         d.lanes_per_row = t.L;
         d.vd_lds = t.lds;
         d.bitmap = t.bm == 1;
@@ -925,6 +935,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         d.conn = s.conn;
         d.g = s.g_uniform;
         d.sgj = s.gap_kind == INFOLI_GAP_SIMPLIFIED ? 1 : 0;
+        d.pcell = s.cell_params ? 1 : 0;
         d.stream_off = -1;
         std::memcpy(&d.p, s.params ? s.params : kDefaultParams, sizeof(CellParams));
         cells += s.n_cells;
@@ -960,11 +971,15 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     if (c->opt.step_mode == INFOLI_MODE_PERSISTENT && max_n > kPersistCells)
         fail(INFOLI_E_UNSUPPORTED, "PERSISTENT mode holds networks of at most %d cells (largest: %d)",
              kPersistCells, max_n);
+    bool cparams = false;
+    for (int k = 0; k < ninst; ++k) cparams = cparams || specs[k].cell_params;
+    if (c->opt.step_mode == INFOLI_MODE_PERSISTENT && cparams)
+        fail(INFOLI_E_UNSUPPORTED, "PERSISTENT mode takes per-network parameters only");
     // AUTO with one real-time sized network: one persistent workgroup or the
     // tiled launches, whichever steps faster (timed below when autotuning,
     // else persistent only where a row is cheap for one thread to walk)
     bool persist_candidate = false;
-    if (c->opt.step_mode == INFOLI_MODE_AUTO && ninst == 1 && max_n <= 1024) {
+    if (c->opt.step_mode == INFOLI_MODE_AUTO && ninst == 1 && max_n <= 1024 && !cparams) {
         const infoli_network_spec& s0 = specs[0];
         const bool cheap_rows = s0.conn == INFOLI_CONN_NONE || s0.conn == INFOLI_CONN_UNIFORM_ALL ||
                                 (s0.conn == INFOLI_CONN_CSR && s0.nnz <= 8 * (int64_t)s0.n_cells);
@@ -1031,15 +1046,25 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     std::vector<float> h_w((size_t)std::max<int64_t>(std::max(w_total, col_total), 1));
     std::vector<float> h_stream((size_t)std::max<int64_t>(stream_total, 1));
     std::vector<DevPulse> h_pulses((size_t)std::max(pulses_total, 1));
+    bool any_cparams = false;
+    for (int k = 0; k < ninst; ++k) any_cparams = any_cparams || specs[k].cell_params;
+    std::vector<float> h_cparams(any_cparams ? (size_t)INFOLI_NUM_PARAMS * S : 1, 0.0f);
     for (int k = 0; k < ninst; ++k) {
         const infoli_network_spec& s = specs[k];
         const InstDesc& d = c->inst[k];
         const int64_t n = s.n_cells;
         float rest[INFOLI_NUM_STATE];
         rest_state_host(s.params ? s.params : kDefaultParams, -60.0f, rest);
-        for (int v = 0; v < INFOLI_NUM_STATE; ++v)
-            for (int64_t i = 0; i < n; ++i)
+        for (int64_t i = 0; i < n; ++i) {
+            if (!s.init_state && s.cell_params)    // each cell's own rest state
+                rest_state_host(s.cell_params + i * INFOLI_NUM_PARAMS, -60.0f, rest);
+            for (int v = 0; v < INFOLI_NUM_STATE; ++v)
                 h_state[v * S + d.cell_off + i] = s.init_state ? s.init_state[v * n + i] : rest[v];
+        }
+        if (s.cell_params)
+            for (int v = 0; v < INFOLI_NUM_PARAMS; ++v)
+                for (int64_t i = 0; i < n; ++i)
+                    h_cparams[v * S + d.cell_off + i] = s.cell_params[i * INFOLI_NUM_PARAMS + v];
         if (s.i_bias)
             for (int64_t i = 0; i < n; ++i) h_bias[d.cell_off + i] = s.i_bias[i];
         if (s.conn == INFOLI_CONN_DENSE)
@@ -1087,6 +1112,10 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->d_spk_times = c->alloc<float>((size_t)S * std::max(cap, 1));
     c->d_flags = c->alloc<int32_t>(4);
     c->d_step = c->alloc<int64_t>(1);
+    if (any_cparams) {
+        c->d_cparams = c->alloc<float>(h_cparams.size());
+        HIPX(hipMemcpy(c->d_cparams, h_cparams.data(), sizeof(float) * h_cparams.size(), hipMemcpyHostToDevice));
+    }
     if (c->opt.output_ring_steps > 0) {
         c->out_slots = c->opt.output_ring_steps;
         c->out_ring = c->alloc<float>((size_t)c->out_slots * S);
@@ -1166,6 +1195,7 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     a.gap_only = 0;
     a.out_slots = c->out_slots;
     a.out_ring = c->out_ring;
+    a.cparams = c->d_cparams;
     return a;
 }
 

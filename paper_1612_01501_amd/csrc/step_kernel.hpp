@@ -72,6 +72,7 @@ struct InstDesc {
     int32_t wide;          // bitmap: run in the 1024-thread launch group
     int32_t chunked;       // CSR gathers from the chunked rows layout
     int32_t sgj;           // simplified (linear) gap junctions: term w * dV
+    int32_t pcell;         // per-cell parameters in StepArgs::cparams
     int64_t bits_off;      // bitmap: offset of the network's first word
     int64_t blk_off;       // blocked: offset of the network's [n][nblk] block starts
     int64_t ca_off;        // chunked rows: offset of the [n + 1] row chunk starts, -1 none
@@ -125,7 +126,19 @@ struct StepArgs {
     int32_t dry;               // timing runs: write the next state only
     int32_t out_slots;         // output ring: slots (steps), 0 => none
     float* out_ring;           // [out_slots][stride]: Va after step s in slot s mod out_slots
+    const float* cparams;      // [20][stride]: per-cell parameters (networks with pcell)
 };
+
+// The parameters of one cell: the network's, or the cell's own (SoA rows).
+__device__ __forceinline__ CellParams cell_params_of(const StepArgs& a, const InstDesc& d, int64_t cell) {
+    CellParams p = d.p;
+    if (d.pcell) {
+        float* f = reinterpret_cast<float*>(&p);
+#pragma unroll
+        for (int v = 0; v < 20; ++v) f[v] = a.cparams[v * a.stride + cell];
+    }
+    return p;
+}
 
 // Output ring slot of step s (s >= 0).
 __device__ __forceinline__ int64_t out_slot(const StepArgs& a, int64_t s) {
@@ -830,19 +843,25 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
         for (int k = threadIdx.x; k < nrows; k += BLOCK) a.igap_out[d.cell_off + t.row0 + k] = s_ig[k];
         return;
     }
+    // per-cell parameters exist in the general variant only (the runtime
+    // launches networks that have them with it)
+    CellParams pc = d.p;
+    if constexpr (VAR == kVarAll) {
+        if (own) pc = cell_params_of(a, d, cell);
+    }
     if (own && split) {
         float y[NSV];
         float chk = 0.0f;
         if (part == 0) {
-            cell_step_dendrite(d.p, x, s_ig[k_own], iapp, a.dt, y);
-            cell_step_axon(d.p, x, a.dt, y);
+            cell_step_dendrite(pc, x, s_ig[k_own], iapp, a.dt, y);
+            cell_step_axon(pc, x, a.dt, y);
 #pragma unroll
             for (int v : {SV_VD, SV_CA, SV_R, SV_S, SV_Q, SV_VA, SV_HA, SV_XA}) {
                 xout[v * a.stride + cell] = y[v];
                 chk += y[v];
             }
         } else {
-            cell_step_soma(d.p, x, a.dt, y);
+            cell_step_soma(pc, x, a.dt, y);
 #pragma unroll
             for (int v : {SV_VS, SV_K, SV_L, SV_H, SV_N, SV_X}) {
                 xout[v * a.stride + cell] = y[v];
@@ -863,7 +882,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
         }
     } else if (own) {
         float y[NSV];
-        cell_step(d.p, x, s_ig[k_own], iapp, a.dt, y);
+        cell_step(pc, x, s_ig[k_own], iapp, a.dt, y);
         float chk = 0.0f;
 #pragma unroll
         for (int v = 0; v < NSV; ++v) {

@@ -184,6 +184,8 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
     return guarded(ctx, [&] {
         if (!cfg) fail(INFOLI_E_INVALID_ARG, "cfg is NULL");
         if (ctx->n_inst != 1) fail(INFOLI_E_UNSUPPORTED, "the surrogate runs on single-network contexts");
+        if (ctx->inst[0].pcell)
+            fail(INFOLI_E_UNSUPPORTED, "the surrogate learns one parameter set: no per-cell parameters");
         if (cfg->batch < 16 || cfg->batch % 64 != 0 || cfg->batch > (1 << 20))
             fail(INFOLI_E_INVALID_ARG, "batch must be a positive multiple of 64 up to 2^20");
         if (cfg->steps < 0 || cfg->n_trajectories < 1 || cfg->n_transitions < cfg->batch ||
@@ -352,6 +354,9 @@ infoli_status infoli_step_surrogate(infoli_ctx* ctx, int64_t n_macro, const info
         if (ctx->out_slots > 0)
             fail(INFOLI_E_INVALID_ARG, "surrogate macro steps do not write the output ring; "
                                        "use a context without output_ring_steps");
+        for (int k = 0; k < ctx->n_inst; ++k)
+            if (ctx->inst[k].pcell)
+                fail(INFOLI_E_UNSUPPORTED, "the surrogate learns one parameter set: no per-cell parameters");
         if (dc.mode != INFOLI_SURROGATE_MLP && dc.mode != INFOLI_SURROGATE_PLAIN_HOLD)
             fail(INFOLI_E_INVALID_ARG, "unknown surrogate mode %d", dc.mode);
         if (dc.sample_every < 0 || dc.hold_steps < 0 || !(dc.theta_mv >= 0.0f) || std::isnan(dc.v_max) ||

@@ -65,7 +65,8 @@ class NetworkSpec(ctypes.Structure):
                 ("init_state", _PF), ("i_bias", _PF), ("pulses", ctypes.POINTER(Pulse)),
                 ("n_pulses", ctypes.c_int32), ("i_stream", _PF),
                 ("i_stream_steps", ctypes.c_int64), ("step0", ctypes.c_int64),
-                ("gap_kind", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("gap_kind", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("cell_params", ctypes.POINTER(ctypes.c_float))]
 
 
 class Options(ctypes.Structure):
@@ -206,9 +207,13 @@ def rest_state(params: Optional[np.ndarray] = None, v0: float = _inputs.REST_MV)
 
 
 def initial_state(net: "_inputs.Network", v0: float = _inputs.REST_MV) -> np.ndarray:
-    """The library's rest state for every cell plus the network's jitter."""
-    r = rest_state(net.params, v0).astype(np.float64)
-    x = np.repeat(r[:, None], net.n, axis=1)
+    """The library's rest state for every cell (each cell's own with
+    per-cell parameters) plus the network's jitter."""
+    if net.cell_params is None:
+        r = rest_state(net.params, v0).astype(np.float64)
+        x = np.repeat(r[:, None], net.n, axis=1)
+    else:
+        x = np.stack([rest_state(net.cell_params[i], v0).astype(np.float64) for i in range(net.n)], axis=1)
     if net.jitter is not None:
         for row, v in enumerate((_inputs.IDX_VD, _inputs.IDX_VS, _inputs.IDX_VA)):
             x[v] += net.jitter[row]
@@ -308,6 +313,10 @@ class _SpecHolder:
             s.i_stream_steps = st.shape[0]
         s.step0 = step0
         s.gap_kind = GAP_KIND[net.gap]
+        if net.cell_params is not None:
+            cp = self._f(net.cell_params)
+            assert cp.size == net.n * NUM_PARAMS, cp.shape
+            s.cell_params = _fptr(cp)
         self.spec = s
 
     def _f(self, a):

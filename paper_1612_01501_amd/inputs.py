@@ -85,6 +85,7 @@ class Network:
     params: np.ndarray = dataclasses.field(default_factory=lambda: DEFAULT_PARAMS.copy())
     dt: float = DT_MS
     gap: str = "rgj"                # "rgj": realistic gap junctions | "sgj": simplified (linear)
+    cell_params: Optional[np.ndarray] = None  # [n, 20]: per-cell values, else params for every cell
     label: str = ""
 
     @property

@@ -729,3 +729,73 @@ def test_sgj_mixed_batch_matches_standalone_bitwise(infoli):
         s.step(300)
         np.testing.assert_array_equal(s.read_state(0), batch[k])
         s.close()
+
+
+# ------------------------------------------------------------------ per-cell parameters
+def _het(n, seed):
+    rs = I.rng(seed)
+    cp = np.tile(I.DEFAULT_PARAMS, (n, 1)).astype(np.float32)
+    for name in ("g_CaL", "g_h", "g_KCa"):
+        cp[:, I.PARAM_NAMES.index(name)] *= rs.uniform(0.7, 1.3, n)
+    return cp
+
+
+@pytest.mark.parametrize("case", ["csr1000", "uni777", "dense200"])
+def test_cell_params_trajectories(infoli, o32, o64, case):
+    """Each cell with its own conductances (Section 2.2: 20 values per
+    neuron): 1,000 steps against the oracle."""
+    if case == "csr1000":
+        net = I.config1(0.1, seed=3, n=1000)
+    elif case == "uni777":
+        net = I.config2(seed=1, n=777, pulse=True)
+        net.pulses = [I.Pulse(100, 600, 6.0)]
+    else:
+        rs = I.rng(9)
+        w = rs.uniform(0, 0.002, (200, 200)).astype(np.float32)
+        net = I.Network(n=200, conn="dense", w_dense=(w + w.T) / 2, jitter=I.voltage_jitter(200, 8),
+                        pulses=[I.Pulse(200, 400, 5.0)])
+    net.cell_params = _het(net.n, 17)
+    net.label = case + "_cellparams"
+    _check_run(infoli, o32, o64, net, 1000, 50)
+
+
+def test_cell_params_all_equal_is_bitwise_the_network_run(infoli):
+    net = I.config1(0.1, seed=3, n=600)
+    x0 = infoli.initial_state(net)
+    out = []
+    for cp in (None, np.tile(net.params, (net.n, 1))):
+        net.cell_params = cp
+        sim = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=50, autotune=0)
+        sim.step(300)
+        out.append(sim.read_state(0))
+        sim.close()
+    np.testing.assert_array_equal(out[0], out[1])
+
+
+def test_cell_params_batch_matches_standalone_bitwise(infoli):
+    nets = [I.config1(0.25, seed=4, n=130), I.config1(0.25, seed=4, n=130),
+            I.Network(n=50, conn="none", jitter=I.voltage_jitter(50, 2))]
+    nets[1].cell_params = _het(130, 3)
+    nets[2].cell_params = _het(50, 4)
+    x0s = [infoli.initial_state(n) for n in nets]
+    sim = infoli.Simulator(nets, init_states=x0s, step_mode="graph", graph_chunk=50, autotune=0)
+    sim.step(300)
+    batch = [sim.read_state(k) for k in range(len(nets))]
+    sim.close()
+    assert not np.array_equal(batch[0], batch[1])
+    for k, net in enumerate(nets):
+        s = infoli.Simulator(net, init_states=[x0s[k]], step_mode="graph", graph_chunk=50, autotune=0)
+        s.step(300)
+        np.testing.assert_array_equal(s.read_state(0), batch[k])
+        s.close()
+
+
+def test_cell_params_refused_where_unsupported(infoli):
+    net = I.Network(n=64, conn="uniform", g=0.04, cell_params=_het(64, 5))
+    with pytest.raises(RuntimeError, match="PERSISTENT"):
+        infoli.Simulator(net, step_mode="persistent")
+    sim = infoli.Simulator(net)
+    assert sim.info()["step_mode"] != 3         # AUTO does not take the persistent kernel
+    with pytest.raises(RuntimeError, match="per-cell"):
+        sim.surrogate_train(np.zeros(infoli.MLP_PARAMS, np.float32), steps=1)
+    sim.close()

@@ -201,6 +201,47 @@ def test_sgj_formats_agree(o64):
     np.testing.assert_array_equal(a, c)
 
 
+# ----------------------------------------------------------------- per-cell parameters
+# Section 2.2: each neuron carries its own 20 conductances and reversal
+# potentials.
+
+def _het_params(n, seed):
+    """Per-cell values: the defaults with gCaL, gH and gKCa scaled by U[0.7, 1.3]."""
+    rs = np.random.default_rng(seed)
+    cp = np.tile(I.DEFAULT_PARAMS, (n, 1))
+    for name in ("g_CaL", "g_h", "g_KCa"):
+        cp[:, P[name]] *= rs.uniform(0.7, 1.3, n)
+    return cp
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cell_params_all_equal_is_the_network_run(prec, o64, o32):
+    o = o64 if prec == "f64" else o32
+    net = I.config1(0.1, seed=2, n=80)
+    a = o.run(net, 300)
+    net.cell_params = np.tile(net.params, (net.n, 1))
+    b = o.run(net, 300)
+    np.testing.assert_array_equal(a["x"], b["x"])
+    np.testing.assert_array_equal(a["counts"], b["counts"])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_uncoupled_heterogeneous_cells_are_their_own_networks(prec, o64, o32):
+    """Cell i of an uncoupled network with per-cell values evolves exactly as
+    a one-cell network with cell i's values (its own rest state, the pulse)."""
+    o = o64 if prec == "f64" else o32
+    n = 6
+    cp = _het_params(n, 5)
+    net = I.Network(n=n, conn="none", cell_params=cp, pulses=[I.Pulse(50, 250, 5.0)])
+    x0 = o.initial_state(net)
+    got = o.run(net, 400, x0=x0)["x"]
+    for i in range(n):
+        one = I.Network(n=1, conn="none", params=cp[i], pulses=[I.Pulse(50, 250, 5.0)])
+        want = o.run(one, 400, x0=o.initial_state(one))["x"]
+        np.testing.assert_array_equal(got[:, i], want[:, 0])
+    assert np.unique(got[0]).size == n          # the cells differ
+
+
 # ----------------------------------------------------------------- network invariants
 @pytest.mark.parametrize("conn", ["uniform", "dense", "csr"])
 def test_identical_cells_stay_in_sync(conn, o64, o32):
