@@ -223,7 +223,7 @@ void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int r
 // Launch group of a network: 1024-thread workgroups for bitmap tiles and
 // large all-to-all networks, 256-thread workgroups otherwise.
 int group_for(const InstDesc& d) {
-    if (d.conn == CONN_CSR && (d.blocked || (d.bitmap && d.wide))) return 1;
+    if (d.conn == CONN_CSR && (d.blocked || d.wide)) return 1;
     if (d.conn == CONN_UNIFORM && d.n >= 4096) return 1;
     return 0;
 }
@@ -456,7 +456,7 @@ std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v8.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v9.txt";
     return "";
 }
 
@@ -631,6 +631,7 @@ void autotune(infoli_ctx* c) {
     constexpr int kAlts = 3;
     struct ClassChoice {
         TuneChoice best, best256, best256nc;   // overall; in 256 threads; in 256 threads, not chunked
+        TuneChoice best1024;                   // in 1024 threads (block 0: none timed)
         TuneChoice alt[kAlts];                 // the fastest distinct 256-thread shapes, fastest first
         int nalt = 0;
     };
@@ -639,17 +640,21 @@ void autotune(infoli_ctx* c) {
         const std::string& key = kv.first;
         const std::vector<int>& ks = kv.second;
         TuneChoice best{0, 0, 0, 0, 256}, best256{0, 0, 0, 0, 256}, best256nc{0, 0, 0, 0, 256};
+        TuneChoice best1024{0, 0, 0, 0, 0};
         ClassChoice cc;
         auto hit = cache.find(key);
         auto hit256 = cache.find(key + "#256");
         auto hitnc = cache.find(key + "#256nc");
         auto hita = cache.find(key + "#a0");
+        auto hit1024 = cache.find(key + "#1024");
         if (hit != cache.end() && hit256 != cache.end() && hitnc != cache.end() && hita != cache.end() &&
+            hit1024 != cache.end() && hit1024->second.L <= 256 &&
             hit->second.L <= 256 && hit256->second.L <= 256 && hit256->second.block == 256 &&
             hitnc->second.L <= 256 && hitnc->second.block == 256 && hitnc->second.bm != 3) {
             best = hit->second;
             best256 = hit256->second;
             best256nc = hitnc->second;
+            best1024 = hit1024->second;
             for (int a = 0; a < kAlts; ++a) {
                 auto h = cache.find(key + "#a" + std::to_string(a));
                 if (h == cache.end() || h->second.block != 256 || h->second.L > 256) break;
@@ -665,7 +670,7 @@ void autotune(infoli_ctx* c) {
                 n = std::max(n, c->inst[k].n);
                 deg = std::max(deg, c->deg_of[k]);
             }
-            float best_ms = 1e30f, best256_ms = 1e30f, best256nc_ms = 1e30f;
+            float best_ms = 1e30f, best256_ms = 1e30f, best256nc_ms = 1e30f, best1024_ms = 1e30f;
             std::vector<std::pair<float, TuneChoice>> timed;
             bool all_rows = c->d_ca != nullptr;    // every network of the class has the chunked rows layout
             for (int k : ks) all_rows = all_rows && c->inst[k].ca_off >= 0;
@@ -684,6 +689,10 @@ void autotune(infoli_ctx* c) {
                     best256nc_ms = ms;
                     best256nc = t;
                 }
+                if (t.block == 1024 && ms < best1024_ms) {
+                    best1024_ms = ms;
+                    best1024 = t;
+                }
             };
             for (int L = 4; L <= 256; L *= 2) {
                 if (L > 4 && L > 2.0 * deg) break;
@@ -695,6 +704,18 @@ void autotune(infoli_ctx* c) {
                         consider(TuneChoice{L, R, lds, 0, 256});
                         if (all_rows) consider(TuneChoice{L, R, lds, 3, 256});
                     }
+                }
+            }
+            // the gathers in 1024-thread workgroups (at the best 256-thread
+            // lane count and twice it), so that a step whose other networks
+            // want 1024 threads can run as one launch
+            for (int L : {best256.L, 2 * best256.L}) {
+                if (L > 256 || (L > 4 && L > 2.0 * deg)) continue;
+                for (int m = 1; m <= 2; m *= 2) {
+                    const int R = std::max(1, 1024 / L) * m;
+                    if (R > kMaxTileRows) continue;
+                    consider(TuneChoice{L, R, best256.lds, 0, 1024});
+                    if (all_rows) consider(TuneChoice{L, R, best256.lds, 3, 1024});
                 }
             }
             // the bitmap path, when every network of the class has one
@@ -723,12 +744,14 @@ void autotune(infoli_ctx* c) {
             append_tune_cache(path, key, best);
             append_tune_cache(path, key + "#256", best256);
             append_tune_cache(path, key + "#256nc", best256nc);
+            append_tune_cache(path, key + "#1024", best1024);
             for (int a = 0; a < cc.nalt; ++a) append_tune_cache(path, key + "#a" + std::to_string(a), cc.alt[a]);
             c->tuned += (int)ks.size();
         }
         cc.best = best;
         cc.best256 = best256;
         cc.best256nc = best256nc;
+        cc.best1024 = best1024;
         chosen[key] = cc;
     }
 
@@ -746,11 +769,12 @@ void autotune(infoli_ctx* c) {
     char ctx_key[64];
     snprintf(ctx_key, sizeof ctx_key, "ctx %016llx", (unsigned long long)fnv1a(sig));
     // variant of the per-class choices: bit 0, each class in its best
-    // 256-thread shape; bit 2, chunked gathers replaced by the best
+    // 256-thread shape; bit 3, each class in its best 1024-thread shape;
+    // bit 2, chunked gathers in 256 threads replaced by the best
     // non-chunked 256-thread shape
     auto pick = [&](const ClassChoice& ch, int m) {
-        TuneChoice t = (m & 1) ? ch.best256 : ch.best;
-        if ((m & 4) && t.bm == 3) t = ch.best256nc;
+        TuneChoice t = (m & 8) && ch.best1024.block == 1024 ? ch.best1024 : (m & 1) ? ch.best256 : ch.best;
+        if ((m & 4) && t.bm == 3 && t.block == 256) t = ch.best256nc;
         return t;
     };
     auto apply_all = [&](int m) {
@@ -765,24 +789,25 @@ void autotune(infoli_ctx* c) {
         mode = mh->second[0];
         for (int i = 0; i < ncls; ++i) refine[i] = mh->second[1 + i];
     } else {
-        bool wide = false, chunk = false;   // variants that change something
+        bool wide = false, chunk = false, narrow = false;   // variants that change something
         for (const auto& kv : chosen) {
             wide = wide || kv.second.best.block != 256;
+            narrow = narrow || (kv.second.best.block == 256 && kv.second.best1024.block == 1024);
             chunk = chunk || kv.second.best.bm == 3 || kv.second.best256.bm == 3;
         }
         // every variant timed in two interleaved rounds, the smaller kept
-        float mode_ms[8];
+        float mode_ms[16];
         for (float& v : mode_ms) v = 1e30f;
         for (int round = 0; round < 2; ++round)
-            for (int m = 0; m < 8; ++m) {
-                if (((m & 1) && !wide) || ((m & 4) && !chunk)) continue;
+            for (int m = 0; m < 16; ++m) {
+                if (((m & 1) && !wide) || ((m & 4) && !chunk) || ((m & 8) && (!narrow || (m & 1)))) continue;
                 apply_all(m);
                 finalize_tiles(c);
                 const bool both = !c->grp[0].tiles.empty() && !c->grp[1].tiles.empty();
                 if ((m & 2) && !both) continue;
                 mode_ms[m] = std::min(mode_ms[m], time_step(c, !(m & 2)));
             }
-        for (int m = 1; m < 8; ++m)
+        for (int m = 1; m < 16; ++m)
             if (mode_ms[m] < mode_ms[mode]) mode = m;
         // Refinement in the whole step: a class timed alone can rank shapes
         // differently from the full step. Every class with at least 5 % of
