@@ -182,20 +182,28 @@ CSR_SLOTS_PER_EDGE = 9
 
 
 def step_kernel_name(info, nets):
-    """The kernel(s) one step launches, from the context's launch groups
-    (networks without gap junctions alone take the compartment-only variant)."""
+    """The kernel(s) one step launches, from the context's launch groups and
+    the variant the runtime picks for them: 1 when no network has gap
+    junctions, 2 when none has per-edge weights or per-cell parameters,
+    else 0."""
     if info["step_mode"] == 3:
         return "infoli::k_persist"
+    if all(n.conn == "none" and n.cell_params is None for n in nets):
+        var = 1
+    elif all(n.w_csr is None and n.cell_params is None for n in nets):
+        var = 2
+    else:
+        var = 0
     wide, total = info["n_tiles_wide"], info["n_tiles"]
-    narrow = "infoli::k_step<256, 1>" if all(n.conn == "none" for n in nets) else "infoli::k_step<256, 0>"
+    narrow = f"infoli::k_step<256, {var}>"
     if wide == 0:
         return narrow
     if wide == total:
-        return "infoli::k_step<1024, 0>"
-    return f"{narrow} + infoli::k_step<1024, 0> (concurrent graph branches)"
+        return f"infoli::k_step<1024, {2 if var == 2 else 0}>"
+    return f"{narrow} + infoli::k_step<1024, {2 if var == 2 else 0}> (concurrent graph branches)"
 
 
-def roofline(nets, launch_s, kernel="infoli::k_step<256, 0>"):
+def roofline(nets, launch_s, kernel="infoli::k_step<256, 2>"):
     kinds = {n.conn for n in nets}
     if len(kinds) > 1:
         # mixed batch: issue slots of the pair/edge work against the lane-slot peak
