@@ -164,7 +164,9 @@ typedef struct infoli_options {
     int32_t output_ring_steps;   /* 0 => off; R > 0 => every plain step also writes the axon
                                     voltage of every cell into a device ring of R steps,
                                     read out with infoli_output_copy_async                 */
-    int32_t reserved1;           /* must be 0                                              */
+    int32_t wide_threads;        /* workgroup size of the wide launch group (all-to-all
+                                    networks of >= 4,096 cells, column blocks, wide bitmap
+                                    tiles): 0 => timed by the tuner (else 1024); 512 or 1024 */
 } infoli_options;
 
 typedef struct infoli_ctx infoli_ctx;

@@ -170,7 +170,11 @@ void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, i
     if (ntiles == 0) return;
     const float* xin = c->state[from];
     float* xout = c->state[from ^ 1];
-    if (block == 1024 && var == kVarNoW)
+    if (block == 512 && var == kVarNoW)
+        hipLaunchKernelGGL((k_step<512, kVarNoW>), dim3(ntiles), dim3(512), lds, st, a, xin, xout, step_arg, off);
+    else if (block == 512)
+        hipLaunchKernelGGL((k_step<512, kVarAll>), dim3(ntiles), dim3(512), lds, st, a, xin, xout, step_arg, off);
+    else if (block == 1024 && var == kVarNoW)
         hipLaunchKernelGGL((k_step<1024, kVarNoW>), dim3(ntiles), dim3(1024), lds, st, a, xin, xout, step_arg, off);
     else if (block == 1024)
         hipLaunchKernelGGL((k_step<1024, kVarAll>), dim3(ntiles), dim3(1024), lds, st, a, xin, xout, step_arg, off);
@@ -247,7 +251,10 @@ void finalize_tiles(infoli_ctx* c) {
         const InstDesc& d = c->inst[k];
         const int g = group_for(d);
         c->group_of[k] = g;
-        append_tiles(planned[g], k, d.n, c->rows_of[k], c->deg_of[k]);
+        int rows = c->rows_of[k];
+        if (d.conn == CONN_CSR && d.blocked)   // rows the column-blocked passes of this workgroup size cover
+            rows = std::min(rows, kBlkPasses * std::max(1, c->grp[g].block / std::max(1, d.lanes_per_row)));
+        append_tiles(planned[g], k, d.n, rows, c->deg_of[k]);
         floats[g] = std::max(floats[g], lds_floats_for(c, d, c->grp[g].block));
     }
     for (int g = 0; g < 2; ++g) {
@@ -777,10 +784,14 @@ void autotune(infoli_ctx* c) {
         if ((m & 4) && t.bm == 3 && t.block == 256) t = ch.best256nc;
         return t;
     };
+    // the wide group's workgroup size under mode m (an explicit option wins)
+    auto wide_block = [&](int m) { return c->opt.wide_threads ? c->opt.wide_threads : (m & 16) ? 512 : 1024; };
     auto apply_all = [&](int m) {
         for (const auto& kv : classes) apply_choice(c, kv.second, pick(chosen[kv.first], m));
     };
-    // bit 0 and bit 2 as above; bit 1: the two launch groups one after the other
+    // bits 0, 2 and 3 as above; bit 1: the two launch groups one after the
+    // other; bit 4: the wide launch group in 512-thread workgroups (two per
+    // compute unit, so one can stage a column block while the other gathers)
     int mode = 0;
     const int ncls = (int)classes.size();
     std::vector<int> refine(ncls, -1);   // per class: -1 its mode choice, else that alternative
@@ -796,24 +807,28 @@ void autotune(infoli_ctx* c) {
             chunk = chunk || kv.second.best.bm == 3 || kv.second.best256.bm == 3;
         }
         // every variant timed in two interleaved rounds, the smaller kept
-        float mode_ms[16];
+        float mode_ms[32];
         for (float& v : mode_ms) v = 1e30f;
         for (int round = 0; round < 2; ++round)
-            for (int m = 0; m < 16; ++m) {
+            for (int m = 0; m < 32; ++m) {
                 if (((m & 1) && !wide) || ((m & 4) && !chunk) || ((m & 8) && (!narrow || (m & 1)))) continue;
+                if ((m & 16) && c->opt.wide_threads) continue;
                 apply_all(m);
+                c->grp[1].block = wide_block(m);
                 finalize_tiles(c);
                 const bool both = !c->grp[0].tiles.empty() && !c->grp[1].tiles.empty();
                 if ((m & 2) && !both) continue;
+                if ((m & 16) && c->grp[1].tiles.empty()) continue;
                 mode_ms[m] = std::min(mode_ms[m], time_step(c, !(m & 2)));
             }
-        for (int m = 1; m < 16; ++m)
+        for (int m = 1; m < 32; ++m)
             if (mode_ms[m] < mode_ms[mode]) mode = m;
         // Refinement in the whole step: a class timed alone can rank shapes
         // differently from the full step. Every class with at least 5 % of
         // the step's pairs tries its fastest 256-thread alternatives with
         // the others fixed; a change stays when the step is 2 % faster.
         apply_all(mode);
+        c->grp[1].block = wide_block(mode);
         finalize_tiles(c);
         double total = 0.0;
         std::vector<std::pair<double, int>> order;
@@ -857,6 +872,7 @@ void autotune(infoli_ctx* c) {
         append_tune_line(path, line);
     }
     apply_all(mode);
+    c->grp[1].block = wide_block(mode);
     {
         int i = 0;
         for (const auto& kv : classes) {
@@ -920,7 +936,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
     if (c->opt.output_ring_steps < 0 || c->opt.output_ring_steps > (1 << 20))
         fail(INFOLI_E_INVALID_ARG, "output_ring_steps must be in [0, 2^20]");
-    if (c->opt.reserved1 != 0) fail(INFOLI_E_INVALID_ARG, "reserved1 must be 0");
+    if (c->opt.wide_threads != 0 && c->opt.wide_threads != 512 && c->opt.wide_threads != 1024)
+        fail(INFOLI_E_INVALID_ARG, "wide_threads must be 0, 512 or 1024");
     for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
     for (int k = 1; k < ninst; ++k) {
         if (specs[k].step0 != specs[0].step0) fail(INFOLI_E_INVALID_ARG, "all networks must share step0");
@@ -939,7 +956,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     c->dt = specs[0].dt_ms;
     c->step = specs[0].step0;
     c->grp[0].block = 256;
-    c->grp[1].block = 1024;
+    c->grp[1].block = c->opt.wide_threads ? c->opt.wide_threads : 1024;
     {
         int lds_max = 0;
         HIPX(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

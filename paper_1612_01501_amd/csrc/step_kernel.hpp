@@ -645,9 +645,10 @@ template <int BLOCK, bool SGJ, bool W>
 __device__ __forceinline__ void gap_csr_form(const StepArgs& a, const InstDesc& d, const Tile& t,
                                              const float* __restrict__ vd, float* s_vd, float* s_part,
                                              float* s_ig) {
-    // column-blocked tiles run in 1024-thread workgroups only (the runtime
-    // places them there); elsewhere the same rows take the gathers below
-    if constexpr (BLOCK == 1024) {
+    // column-blocked tiles run in the wide launch group only (512- or
+    // 1024-thread workgroups; the runtime places them there); elsewhere the
+    // same rows take the gathers below
+    if constexpr (BLOCK >= 512) {
         if (d.blocked && d.cb_off >= 0) {
             by_weights<W>(d, [&](auto hw) {
                 gap_chunks_blocked<BLOCK, decltype(hw)::value, SGJ>(a, d, t, vd, s_vd, s_part, s_ig);

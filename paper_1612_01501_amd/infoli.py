@@ -75,7 +75,7 @@ class Options(ctypes.Structure):
                 ("tile_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("csr_path", ctypes.c_int32), ("output_ring_steps", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32)]
+                ("wide_threads", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

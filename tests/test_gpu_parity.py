@@ -800,3 +800,36 @@ def test_cell_params_refused_where_unsupported(infoli):
     with pytest.raises(RuntimeError, match="per-cell"):
         sim.surrogate_train(np.zeros(infoli.MLP_PARAMS, np.float32), steps=1)
     sim.close()
+
+
+# ------------------------------------------------------------------ wide group in 512-thread workgroups
+@pytest.mark.parametrize("n", [9000, 20000])
+def test_blocked_path_in_512_thread_workgroups(infoli, o32, o64, n):
+    """Column blocks in 512-thread workgroups (two per compute unit): gap
+    currents against fp64 and one step against the oracle after 100 steps."""
+    net = I.config4(seed=n, n=n, degree=150)
+    x0 = infoli.initial_state(net)
+    sim = infoli.Simulator(net, init_states=[x0], csr_path=3, wide_threads=512, step_mode="graph", graph_chunk=50)
+    info = sim.info()
+    sim.step(100)
+    xk = sim.read_state(0)
+    ig = sim.read_gap_current(0).astype(np.float64)
+    sim.step(1)
+    xk1 = sim.read_state(0)
+    sim.close()
+    assert info["n_blocked"] == 1 and info["n_tiles_wide"] == info["n_tiles"]
+    ref_ig = o64.gap(net, xk[0].astype(np.float64))
+    tol = gap_bound(net, xk[0])
+    assert np.all(np.abs(ig - ref_ig) <= tol), np.max(np.abs(ig - ref_ig) / tol)
+    ref = o32.run(net, 1, x0=xk, step0=100)["x"]
+    assert per_var_error(xk1[None], ref[None]).max() <= 1e-5
+
+
+def test_large_all_to_all_in_512_thread_workgroups(infoli, o32, o64):
+    """An all-to-all network of 4,500 cells (the wide group) in 512-thread
+    workgroups: 300 steps against the oracle."""
+    net = I.config2(seed=2, n=4500)
+    x0 = infoli.initial_state(net)
+    got, c, t = gpu_trace(infoli, net, 300, 50, x0, wide_threads=512, step_mode="graph", graph_chunk=50)
+    ref = o32.run(net, 300, x0=x0, trace_every=50, trace_cells=net.n)
+    assert per_var_error(got, ref["trace"]).max() <= TOL_STATE

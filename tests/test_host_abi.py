@@ -158,7 +158,8 @@ def test_bad_options_rejected():
     net = I.Network(n=4, conn="none")
     h = infoli._SpecHolder(net, init_state=np.zeros((14, 4), np.float32) - 60.0)
     for kw in ({"graph_chunk": 3}, {"lanes_per_row": 3}, {"tile_rows": 1000},
-               {"step_mode": 7}, {"max_spikes_per_cell": -1}):
+               {"step_mode": 7}, {"max_spikes_per_cell": -1}, {"wide_threads": 300},
+               {"output_ring_steps": -1}):
         opt = infoli.default_options(**kw)
         ctx = ctypes.c_void_p()
         st = infoli.lib().infoli_init(ctypes.byref(h.spec), ctypes.byref(opt), ctypes.byref(ctx))
