@@ -390,7 +390,7 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
             }
             if (ch > INT32_MAX) continue;
             d.cb_off = ncb;
-            ncb += (int64_t)d.n * (d.nblk + 1);
+            ncb += (int64_t)d.nblk * (d.n + 1);
             d.chkb_off = nchunks;
             nchunks += ch;
         }
@@ -417,15 +417,27 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
             ha[(size_t)(d.ca_off + d.n)] = (int32_t)pos;
         }
         if (d.cb_off >= 0) {
-            int64_t pos = 0;
+            // block-major: every row's segment of column block 0, then of
+            // block 1, ...; a tile's pass over one block reads one contiguous
+            // run, and no cache line is shared between two passes. Table
+            // [nblk][n + 1]: the start of row i's segment in block b; row
+            // i + 1's start ends it.
+            std::vector<int64_t> bnd((size_t)d.n * (d.nblk + 1));   // per row, edge index at each block start
             for (int i = 0; i < d.n; ++i) {
                 int64_t e = s.row_ptr[i];
-                const uint16_t pad = (uint16_t)(std::min(d.n, C) + (i & (kSelfSlots - 1)));
                 for (int b = 0; b < d.nblk; ++b) {
-                    hb[(size_t)(d.cb_off + (int64_t)i * (d.nblk + 1) + b)] = (int32_t)pos;
-                    const int64_t e0 = e;
+                    bnd[(size_t)i * (d.nblk + 1) + b] = e;
                     while (e < s.row_ptr[i + 1] && s.col[e] < (int64_t)(b + 1) * C) ++e;
-                    const int64_t cnt = e - e0;
+                }
+                bnd[(size_t)i * (d.nblk + 1) + d.nblk] = e;
+            }
+            int64_t pos = 0;
+            for (int b = 0; b < d.nblk; ++b) {
+                for (int i = 0; i < d.n; ++i) {
+                    hb[(size_t)(d.cb_off + (int64_t)b * (d.n + 1) + i)] = (int32_t)pos;
+                    const uint16_t pad = (uint16_t)(std::min(d.n, C) + (i & (kSelfSlots - 1)));
+                    const int64_t e0 = bnd[(size_t)i * (d.nblk + 1) + b];
+                    const int64_t cnt = bnd[(size_t)i * (d.nblk + 1) + b + 1] - e0;
                     const int64_t base = (d.chkb_off + pos) * kChunkCols;
                     for (int64_t x = 0; x < chunks_of(cnt) * kChunkCols; ++x) {
                         hc[(size_t)(base + x)] = x < cnt ? (uint16_t)(s.col[e0 + x] - (int64_t)b * C) : pad;
@@ -433,7 +445,7 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
                     }
                     pos += chunks_of(cnt);
                 }
-                hb[(size_t)(d.cb_off + (int64_t)i * (d.nblk + 1) + d.nblk)] = (int32_t)pos;
+                hb[(size_t)(d.cb_off + (int64_t)b * (d.n + 1) + d.n)] = (int32_t)pos;
             }
         }
     }

@@ -559,8 +559,8 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
     const int grp = threadIdx.x / L;
     const int lig = threadIdx.x % L;
     const int C = a.blk_cols;
-    const int nb1 = d.nblk + 1;
-    const int32_t* cb = a.cb + d.cb_off;
+    const int64_t n1 = d.n + 1;
+    const int32_t* cb = a.cb + d.cb_off;   // [nblk][n + 1]: block-major chunk starts
     const uint4* ch = a.chk + d.chkb_off;
     const float4* cw = reinterpret_cast<const float4*>(a.chkw) + 2 * d.chkb_off;
     const int S = min(d.n, C);     // own-voltage slots follow the largest block
@@ -584,9 +584,9 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
             const int r = t.row0 + q * groups + grp;
             if (r >= t.row1) continue;
             const uint4 padc = pad_chunk((uint32_t)(S + (r & (kSelfSlots - 1))));
-            const int ce = cb[(int64_t)r * nb1 + b + 1];
+            const int ce = cb[b * n1 + r + 1];
             float a0 = 0.0f, a1 = 0.0f;
-            for (int c = cb[(int64_t)r * nb1 + b] + lig; c < ce; c += 2 * L) {
+            for (int c = cb[b * n1 + r] + lig; c < ce; c += 2 * L) {
                 const bool ok1 = c + L < ce;
                 const uint4 q0 = ch[c];
                 const uint4 q1 = ok1 ? ch[c + L] : padc;
