@@ -506,6 +506,58 @@ def rt_sweep(args, torch, infoli):
                                    "paper_table3_context": PAPER_TABLE3}}), flush=True)
 
 
+# Table 4's scenario (Section 3.3): per network size a batch of five
+# realistic-gap experiments at 100, 75, 50, 25 and 0 % density, 40 s of
+# brain time (800,000 steps) each. The average time per step that BrainFrame
+# (the best fabric per experiment) reaches there, derived from Table 4's
+# savings, is quoted as context.
+PAPER_TABLE4_BRAINFRAME_US_PER_STEP = {384: 58.0, 960: 303.0, 5760: 2210.0, 7680: 13300.0}
+
+
+def paper_batches(args, torch, infoli):
+    """Table 4's batches on one MI355X: every experiment alone (one after
+    the other, as on one accelerator) and all five in one batched context
+    (one launch per step), each timed over 500 steps after 50 warm-up
+    steps; batch time = steps per experiment x the per-step times."""
+    steps_per_exp = 800000
+    out = []
+    for n in (384, 960, 5760, 7680):
+        nets = [rt_network(c, n) for c in ("RGJ 100%", "RGJ 75%", "RGJ 50%", "RGJ 25%")]
+        nets.append(I.Network(n=n, conn="none", jitter=I.voltage_jitter(n, 2000), bias=I.input_bias(n, 3000)))
+
+        def per_step(group):
+            sim = infoli.Simulator(group, init_states=[infoli.initial_state(x) for x in group])
+            sim.step(50)
+            sim.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(500)
+            torch.cuda.synchronize()
+            us = (time.perf_counter() - t0) / 500 * 1e6
+            sim.close()
+            return us
+
+        alone = [per_step([x]) for x in nets]
+        together = per_step(nets)
+        seq_s = sum(alone) * 1e-6 * steps_per_exp
+        bat_s = together * 1e-6 * steps_per_exp
+        paper_s = PAPER_TABLE4_BRAINFRAME_US_PER_STEP[n] * 1e-6 * 5 * steps_per_exp
+        row = {"cells": n, "us_per_step_alone": [round(u, 2) for u in alone],
+               "us_per_step_five_batched": round(together, 2),
+               "batch_seconds_one_after_another": round(seq_s, 2), "batch_seconds_batched": round(bat_s, 2),
+               "paper_brainframe_batch_seconds": round(paper_s, 1),
+               "speedup_vs_brainframe_batched": round(paper_s / bat_s, 1)}
+        print(f"paper batch n={n}: alone {row['us_per_step_alone']} us, batched {together:.2f} us per step",
+              file=sys.stderr, flush=True)
+        out.append(row)
+    print(json.dumps({"paper_batches": {
+        "scenario": "Table 4: five RGJ experiments (100/75/50/25/0 % density) of 800,000 steps per network size",
+        "densities": ["100% (all-to-all)", "75% (ER CSR)", "50%", "25%", "0% (no gap junctions)"],
+        "paper_context": "BrainFrame's average time per step (derived from Table 4's savings) on its three "
+                         "fabrics (Maxeler Maia DFE, Xeon Phi 5110P, Titan X), the best fabric per experiment",
+        "sizes": out}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -519,6 +571,8 @@ def main():
     ap.add_argument("--rt-sweep", action="store_true",
                     help="only run the real-time size sweep (largest network per use case within the budget)")
     ap.add_argument("--rt-budget-us", type=float, default=50.0)
+    ap.add_argument("--paper-batches", action="store_true",
+                    help="only run Table 4's experiment batches (per size, five densities)")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -538,6 +592,9 @@ def main():
         return
     if args.rt_sweep:
         rt_sweep(args, torch, infoli)
+        return
+    if args.paper_batches:
+        paper_batches(args, torch, infoli)
         return
     nets, desc = build_workload(args.workload)
     if args.workload == "surr65k":
