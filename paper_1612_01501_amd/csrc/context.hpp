@@ -106,8 +106,10 @@ struct infoli_ctx {
     float dt = 0.05f;
     int persist_cpt = 1;            // cells per thread of the persistent kernel
     // tiles of one step, in two launches: [0] 256-thread workgroups (edge
-    // gathers, small networks), [1] 1024-thread workgroups (bitmaps, large
-    // all-to-all networks); captured as two parallel graph branches
+    // gathers, small networks), [1] the wide group, 1024- or 512-thread
+    // workgroups (column blocks, wide bitmaps, large all-to-all networks, or
+    // every CSR class when the tuner finds one wide launch faster); captured
+    // as parallel graph branches or one after the other
     infoli_rt::TileGroup grp[2];
     std::vector<int> group_of;      // launch group of each network
     std::vector<int> rows_of;       // tile rows per network

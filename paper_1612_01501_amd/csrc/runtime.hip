@@ -468,7 +468,7 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
 struct TuneChoice {
     int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS,
                            // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers)
-    int block;             // workgroup size of the launch group (256 or 1024)
+    int block;             // workgroup size timed (256 or 1024; the wide group may run 512)
 };
 
 std::string tune_cache_path() {

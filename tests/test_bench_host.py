@@ -1,0 +1,89 @@
+"""Host-side checks of bench.py's accounting (no GPU): algorithmic bytes of
+small networks by hand, the roofline's bound and units per workload kind,
+the step-kernel variant names, and the one-GPU refusal."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+from paper_1612_01501_amd import inputs as I  # noqa: E402
+
+
+def _csr(n, edges):
+    rows = np.zeros(n + 1, np.int64)
+    for i, _ in edges:
+        rows[i + 1] += 1
+    return np.cumsum(rows), np.array([j for _, j in sorted(edges)], np.int32)
+
+
+def test_algorithmic_bytes_by_hand():
+    rp, col = _csr(3, [(0, 1), (1, 0), (1, 2), (2, 1)])
+    csr = I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)
+    # 116 B per cell (14 state floats in and out, bias), 2 B per uint16
+    # column, 8 B per row pointer
+    assert bench.algorithmic_bytes([csr]) == 116 * 3 + 2 * 4 + 8 * 3
+    csr_w = I.Network(n=3, conn="csr", row_ptr=rp, col=col, w_csr=np.full(4, 0.04, np.float32))
+    assert bench.algorithmic_bytes([csr_w]) == 116 * 3 + (2 + 4) * 4 + 8 * 3
+    dense = I.Network(n=2, conn="dense", w_dense=np.ones((2, 2), np.float32))
+    assert bench.algorithmic_bytes([dense]) == 116 * 2 + 4 * 4
+    assert bench.algorithmic_bytes([I.Network(n=5, conn="uniform", g=0.1)]) == 116 * 5
+    assert bench.algorithmic_bytes([I.Network(n=7, conn="none")]) == 116 * 7
+
+
+def test_roofline_bound_per_workload_kind():
+    uni = bench.roofline([I.Network(n=100, conn="uniform", g=0.1)], 1e-6)
+    assert uni["bound"] == "alu" and uni["unit"] == "Gpair/s"
+    assert uni["achieved"] == pytest.approx(100 * 100 / 1e-6 / 1e9)
+    assert uni["frac"] == pytest.approx(uni["achieved"] / uni["peak"])
+    assert uni["frac_vs_exp_shared_minimum"] < uni["frac"]
+    rp, col = _csr(3, [(0, 1), (1, 0)])
+    csr = bench.roofline([I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)], 1e-6)
+    assert csr["bound"] == "hbm" and csr["unit"] == "GB/s" and csr["peak"] == 8000.0
+    assert csr["achieved"] == pytest.approx(bench.algorithmic_bytes(
+        [I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)]) / 1e-6 / 1e9)
+    sgj = bench.roofline([I.Network(n=100, conn="uniform", g=0.1, gap="sgj")], 1e-6)
+    assert sgj["bound"] == "hbm" and "alu_frac" in sgj
+    ngj = bench.roofline([I.Network(n=64, conn="none")], 1e-6)
+    assert ngj["alu_slots_per_cell_step"] == bench.CELL_SLOTS
+    mixed = bench.roofline([I.Network(n=10, conn="uniform", g=0.1),
+                            I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)], 1e-6)
+    assert mixed["bound"] == "alu" and mixed["unit"] == "T lane-slots/s"
+
+
+def test_step_kernel_variant_names():
+    info = {"step_mode": 0, "n_tiles_wide": 0, "n_tiles": 4}
+    rp, col = _csr(3, [(0, 1), (1, 0)])
+    plain = I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)
+    weighted = I.Network(n=3, conn="csr", row_ptr=rp, col=col, w_csr=np.ones(2, np.float32))
+    assert bench.step_kernel_name(info, [I.Network(n=8, conn="none")]) == "infoli::k_step<256, 1>"
+    assert bench.step_kernel_name(info, [plain]) == "infoli::k_step<256, 2>"
+    assert bench.step_kernel_name(info, [weighted]) == "infoli::k_step<256, 0>"
+    assert bench.step_kernel_name({**info, "n_tiles_wide": 4}, [plain]) == "infoli::k_step<1024, 2>"
+    assert bench.step_kernel_name({**info, "step_mode": 3}, [plain]) == "infoli::k_persist"
+
+
+def test_measured_traffic_needs_matching_sources():
+    assert bench.measured_traffic("no-such-workload") is None
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if os.path.exists(path):
+        d = json.load(open(path))
+        for w, v in d.items():
+            if w == "calibration":
+                continue
+            got = bench.measured_traffic(w)
+            if v.get("kernel_sources_sha256") == bench.kernel_source_hash():
+                assert got == v["bytes_per_launch"]
+            else:
+                assert got is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
