@@ -206,14 +206,21 @@ def step_kernel_name(info, nets):
 def roofline(nets, launch_s, kernel="infoli::k_step<256, 2>"):
     kinds = {n.conn for n in nets}
     if len(kinds) > 1:
-        # mixed batch: issue slots of the pair/edge work against the lane-slot peak
-        slots = sum(UNIFORM_SLOTS_PER_PAIR * n.n * n.n if n.conn == "uniform"
-                    else CSR_SLOTS_PER_EDGE * n.pairs_per_step() for n in nets)
+        # mixed batch: issue slots of the pair/edge work against the lane-slot
+        # peak; and the composite bound, per network the larger of its bytes
+        # at the HBM peak and its issue slots at the lane-slot peak, summed
+        def slots_of(n):
+            return (UNIFORM_SLOTS_PER_PAIR * n.n * n.n if n.conn == "uniform"
+                    else CSR_SLOTS_PER_EDGE * n.pairs_per_step())
+        slots = sum(slots_of(n) for n in nets)
         achieved = slots / launch_s / 1e12
         peak = LANE_SLOTS_PER_S / 1e12
+        t_roof = sum(max(algorithmic_bytes([n]) / (HBM_PEAK_GBS * 1e9), slots_of(n) / LANE_SLOTS_PER_S)
+                     for n in nets)
         return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T lane-slots/s",
                 "frac": achieved / peak, "traffic": None, "kernel": kernel,
-                "slots_per_launch": slots}
+                "slots_per_launch": slots, "composite_roofline_us": t_roof * 1e6,
+                "composite_frac": t_roof / launch_s}
     if all(n.conn == "uniform" and n.gap == "rgj" for n in nets):
         pairs = sum(n.n * n.n for n in nets)       # the kernel evaluates the diagonal too
         achieved = pairs / launch_s / 1e9

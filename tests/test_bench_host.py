@@ -54,6 +54,13 @@ def test_roofline_bound_per_workload_kind():
     mixed = bench.roofline([I.Network(n=10, conn="uniform", g=0.1),
                             I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)], 1e-6)
     assert mixed["bound"] == "alu" and mixed["unit"] == "T lane-slots/s"
+    # composite: per network the larger of bytes at the HBM peak and slots at
+    # the lane-slot peak, summed
+    u = 5 * 10 * 10 / bench.LANE_SLOTS_PER_S
+    c_bytes = (116 * 3 + 2 * 2 + 8 * 3) / 8e12
+    c_slots = bench.CSR_SLOTS_PER_EDGE * 2 / bench.LANE_SLOTS_PER_S
+    assert mixed["composite_roofline_us"] == pytest.approx((max(116 * 10 / 8e12, u) + max(c_bytes, c_slots)) * 1e6)
+    assert mixed["composite_frac"] == pytest.approx(mixed["composite_roofline_us"] * 1e-6 / 1e-6)
 
 
 def test_step_kernel_variant_names():

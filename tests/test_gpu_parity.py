@@ -656,8 +656,10 @@ def test_sgj_trajectories(infoli, o32, o64, case):
     ref = o32.run(net, 1000, x0=x0, trace_every=50, trace_cells=net.n)
     r64 = o64.run(net, 1000, x0=x0.astype(np.float64), trace_every=50, trace_cells=net.n)
     e32 = per_var_error(got, ref["trace"])
+    e64 = per_var_error(got, r64["trace"])
     floor = per_var_error(ref["trace"], r64["trace"])
-    print(f"{net.label}: max err vs f32 oracle {e32.max():.2e}, f32-oracle floor {floor.max():.2e}")
+    print(f"{net.label}: max err vs f32 oracle {e32.max():.2e}, vs f64 {e64.max():.2e}, "
+          f"f32-oracle floor {floor.max():.2e}")
     assert np.all(e32 <= np.maximum(TOL_STATE, 2 * floor)), e32
     compare_spikes(c, t, ref["counts"], ref["times"], 64)
 
