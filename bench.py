@@ -195,12 +195,13 @@ def step_kernel_name(info, nets):
     else:
         var = 0
     wide, total = info["n_tiles_wide"], info["n_tiles"]
+    wblock = info.get("wide_threads", 1024)
     narrow = f"infoli::k_step<256, {var}>"
     if wide == 0:
         return narrow
     if wide == total:
-        return f"infoli::k_step<1024, {2 if var == 2 else 0}>"
-    return f"{narrow} + infoli::k_step<1024, {2 if var == 2 else 0}> (concurrent graph branches)"
+        return f"infoli::k_step<{wblock}, {2 if var == 2 else 0}>"
+    return f"{narrow} + infoli::k_step<{wblock}, {2 if var == 2 else 0}> (concurrent graph branches)"
 
 
 def roofline(nets, launch_s, kernel="infoli::k_step<256, 2>"):
@@ -398,7 +399,7 @@ def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
         "config": {"workload": f"surr65k: {desc}", "cells": cells, "gap_pairs_per_step": net.pairs_per_step(),
-                   "tiles": info["n_tiles"], "tiles_1024": info["n_tiles_wide"],
+                   "tiles": info["n_tiles"], "tiles_wide": info["n_tiles_wide"], "wide_threads": info["wide_threads"],
                    "csr_bitmap_networks": info["n_bitmap"], "csr_blocked_networks": info["n_blocked"],
                    "lanes_per_row": info["lanes_per_row"]},
         "plain_cell_steps_per_s": cells * total_steps / (t_plain * 1e-3),
@@ -645,7 +646,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "cells": cells,
                    "gap_pairs_per_step": pairs, "step_mode": args.mode,
-                   "tiles": info["n_tiles"], "tiles_1024": info["n_tiles_wide"],
+                   "tiles": info["n_tiles"], "tiles_wide": info["n_tiles_wide"], "wide_threads": info["wide_threads"],
                    "csr_bitmap_networks": info["n_bitmap"], "csr_blocked_networks": info["n_blocked"],
                    "lanes_per_row": info["lanes_per_row"]},
         "gap_pairs_per_s": pairs * steps / wall,

@@ -155,9 +155,10 @@ typedef struct infoli_options {
     int32_t check_finite;        /* 1 => a NaN/Inf state makes infoli_sync fail            */
     int32_t autotune;            /* CSR tile shapes: 0 => built-in rule; 1 => timed on the
                                     device at init, cached on disk (INFOLI_TUNE_CACHE, else
-                                    ~/.cache/infoli-tune-v9.txt); 2 => timed, cache ignored */
+                                    ~/.cache/infoli-tune-v10.txt); 2 => timed, cache ignored */
     int32_t csr_path;            /* CSR networks: 0 => tuned choice; 1 => edge gathers;
-                                    2 => coupling bitmap (one weight g, <= 16,384 cells);
+                                    2 => coupling bitmap (one weight g, <= 16,384 cells;
+                                    in the wide group when wide_threads is set);
                                     3 => Vd staged in LDS by column blocks (> 8,192 cells);
                                     4 => edge gathers from 16-byte column chunks
                                     (<= 65,536 cells); other networks keep the default   */
@@ -275,6 +276,7 @@ typedef struct infoli_info {
                                    launch per step, concurrent with the first)          */
     int32_t n_bitmap;           /* CSR networks on the coupling-bitmap path             */
     int32_t n_blocked;          /* CSR networks on the column-blocked path              */
+    int32_t wide_threads;       /* workgroup size of the wide launch group (512 or 1024) */
 } infoli_info;
 infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
 

@@ -475,7 +475,7 @@ std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v9.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v10.txt";
     return "";
 }
 
@@ -647,7 +647,7 @@ void autotune(infoli_ctx* c) {
         classes[tune_key(c, d, c->deg_of[k])].push_back(k);
     }
     Tile* d_tmp = nullptr;
-    constexpr int kAlts = 3;
+    constexpr int kAlts = 8;
     struct ClassChoice {
         TuneChoice best, best256, best256nc;   // overall; in 256 threads; in 256 threads, not chunked
         TuneChoice best1024;                   // in 1024 threads (block 0: none timed)
@@ -1209,7 +1209,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         for (int k = 0; k < ninst; ++k)
             if (c->inst[k].bits_off >= 0) {
                 c->inst[k].bitmap = 1;
-                c->inst[k].wide = 0;
+                c->inst[k].wide = c->opt.wide_threads ? 1 : 0;   // in the wide group when its size is given
                 c->rows_of[k] = kBitRows;
             }
     finalize_tiles(c);
@@ -1606,6 +1606,7 @@ infoli_status infoli_get_info(const infoli_ctx* ctx, infoli_info* info) {
     info->tuned = ctx->tuned;
     info->tune_cached = ctx->tune_cached;
     info->n_tiles_wide = (int32_t)ctx->grp[1].tiles.size();
+    info->wide_threads = ctx->grp[1].block;
     for (const InstDesc& d : ctx->inst) {
         info->n_bitmap += d.conn == CONN_CSR && d.bitmap;
         info->n_blocked += d.conn == CONN_CSR && d.blocked;

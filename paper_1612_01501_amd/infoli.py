@@ -85,7 +85,8 @@ class Info(ctypes.Structure):
                 ("tile_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("tuned", ctypes.c_int32),
                 ("tune_cached", ctypes.c_int32), ("n_tiles_wide", ctypes.c_int32),
-                ("n_bitmap", ctypes.c_int32), ("n_blocked", ctypes.c_int32)]
+                ("n_bitmap", ctypes.c_int32), ("n_blocked", ctypes.c_int32),
+                ("wide_threads", ctypes.c_int32)]
 
 
 class TrainCfg(ctypes.Structure):

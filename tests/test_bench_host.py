@@ -72,6 +72,7 @@ def test_step_kernel_variant_names():
     assert bench.step_kernel_name(info, [plain]) == "infoli::k_step<256, 2>"
     assert bench.step_kernel_name(info, [weighted]) == "infoli::k_step<256, 0>"
     assert bench.step_kernel_name({**info, "n_tiles_wide": 4}, [plain]) == "infoli::k_step<1024, 2>"
+    assert bench.step_kernel_name({**info, "n_tiles_wide": 4, "wide_threads": 512}, [plain]) == "infoli::k_step<512, 2>"
     assert bench.step_kernel_name({**info, "step_mode": 3}, [plain]) == "infoli::k_persist"
 
 
