@@ -224,11 +224,13 @@ void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int r
     }
 }
 
-// Launch group of a network: 1024-thread workgroups for bitmap tiles and
-// large all-to-all networks, 256-thread workgroups otherwise.
+// Launch group of a network: the wide group (1024- or 512-thread
+// workgroups) for column blocks, CSR or all-to-all networks the tuner marked
+// wide, and all-to-all networks of >= 4,096 cells; 256-thread workgroups
+// otherwise.
 int group_for(const InstDesc& d) {
     if (d.conn == CONN_CSR && (d.blocked || d.wide)) return 1;
-    if (d.conn == CONN_UNIFORM && d.n >= 4096) return 1;
+    if (d.conn == CONN_UNIFORM && (d.n >= 4096 || d.wide)) return 1;
     return 0;
 }
 
@@ -800,6 +802,9 @@ void autotune(infoli_ctx* c) {
     auto wide_block = [&](int m) { return c->opt.wide_threads ? c->opt.wide_threads : (m & 16) ? 512 : 1024; };
     auto apply_all = [&](int m) {
         for (const auto& kv : classes) apply_choice(c, kv.second, pick(chosen[kv.first], m));
+        // bit 3 also moves every all-to-all network into the wide group
+        for (int k = 0; k < c->n_inst; ++k)
+            if (c->inst[k].conn == CONN_UNIFORM) c->inst[k].wide = (m & 8) ? 1 : 0;
     };
     // bits 0, 2 and 3 as above; bit 1: the two launch groups one after the
     // other; bit 4: the wide launch group in 512-thread workgroups (two per
