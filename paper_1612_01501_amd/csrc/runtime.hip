@@ -466,7 +466,7 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
 // candidate tile shapes (lanes per row, rows per tile, LDS staging of Vd) are
 // timed on the network's own device data with dry launches (they write only
 // the next-state buffer) and the fastest is kept, in memory and in an
-// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v8.txt).
+// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v10.txt).
 struct TuneChoice {
     int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS,
                            // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers)
@@ -490,6 +490,9 @@ std::string tune_key(const infoli_ctx* c, const InstDesc& d, double deg) {
     return buf;
 }
 
+// Whole-step launch modes: five bits (see the tuner below), so 0..31.
+constexpr int kStepModes = 32;
+
 // Lines "<class key>|L R lds bm block" (the class's best shape),
 // "<class key>#256|..." (its best shape in 256-thread workgroups) and
 // "ctx <hash>|mode" (the whole-step launch choice of one mix of networks).
@@ -512,7 +515,7 @@ std::map<std::string, TuneChoice> read_tune_cache(const std::string& path,
                 v.push_back((int)x);
                 p = end;
             }
-            if (!v.empty() && v[0] >= 0 && v[0] <= 7) (*modes)[line] = v;
+            if (!v.empty() && v[0] >= 0 && v[0] < kStepModes) (*modes)[line] = v;
             continue;
         }
         TuneChoice t;
@@ -824,10 +827,10 @@ void autotune(infoli_ctx* c) {
             chunk = chunk || kv.second.best.bm == 3 || kv.second.best256.bm == 3;
         }
         // every variant timed in two interleaved rounds, the smaller kept
-        float mode_ms[32];
+        float mode_ms[kStepModes];
         for (float& v : mode_ms) v = 1e30f;
         for (int round = 0; round < 2; ++round)
-            for (int m = 0; m < 32; ++m) {
+            for (int m = 0; m < kStepModes; ++m) {
                 if (((m & 1) && !wide) || ((m & 4) && !chunk) || ((m & 8) && (!narrow || (m & 1)))) continue;
                 if ((m & 16) && c->opt.wide_threads) continue;
                 apply_all(m);
@@ -838,7 +841,7 @@ void autotune(infoli_ctx* c) {
                 if ((m & 16) && c->grp[1].tiles.empty()) continue;
                 mode_ms[m] = std::min(mode_ms[m], time_step(c, !(m & 2)));
             }
-        for (int m = 1; m < 32; ++m)
+        for (int m = 1; m < kStepModes; ++m)
             if (mode_ms[m] < mode_ms[mode]) mode = m;
         // Refinement in the whole step: a class timed alone can rank shapes
         // differently from the full step. Every class with at least 5 % of

@@ -471,6 +471,36 @@ def test_autotuner_times_caches_and_stays_exact(infoli, o32, tmp_path, monkeypat
         assert per_var_error(out[0][k][None], ref[None]).max() <= TOL_STATE
 
 
+def test_cached_wide_step_mode_is_read_back(infoli, o32, tmp_path, monkeypatch):
+    """A whole-step choice with the high mode bits set (wide group in
+    512-thread workgroups) is taken from the cache as stored: the second
+    context times nothing, appends no line and runs the cached launch."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("INFOLI_TUNE_CACHE", str(path))
+    net = I.config1(0.3, seed=21, n=1200)
+    x0 = infoli.initial_state(net)
+    infoli.Simulator(net, init_states=[x0], autotune=2, step_mode="launch").close()
+    lines = path.read_text().strip().splitlines()
+    ctx = [i for i, l in enumerate(lines) if l.startswith("ctx ")]
+    assert len(ctx) == 1
+    key, vals = lines[ctx[0]].split("|")
+    vals = vals.split()
+    vals[0] = str(int(vals[0]) | 16)
+    lines[ctx[0]] = key + "|" + " ".join(vals)
+    path.write_text("\n".join(lines) + "\n")
+    sim = infoli.Simulator(net, init_states=[x0], autotune=1, step_mode="launch")
+    info = sim.info()
+    sim.step(300)
+    got = sim.read_state(0)
+    sim.close()
+    assert info["tuned"] == 0 and info["tune_cached"] == 1
+    assert info["wide_threads"] == 512
+    after = path.read_text().strip().splitlines()
+    assert len(after) == len(lines) and sum(l.startswith("ctx ") for l in after) == 1
+    ref = o32.run(net, 300, x0=x0)["x"]
+    assert per_var_error(got[None], ref[None]).max() <= TOL_STATE
+
+
 # ------------------------------------------------------------------ batches of uneven networks
 def test_uneven_batch_against_oracle(infoli, o32, o64):
     """The 256-network batch recipe at reduced size: 24 networks of 64-600
