@@ -158,18 +158,23 @@ UNIFORM_SLOTS_PER_PAIR = 3 + EXP_SLOTS
 CELL_SLOTS = 278 + 39
 
 
-def algorithmic_bytes(nets):
-    """Bytes one step launch must move at minimum: per cell 14 state floats in
-    and out plus the bias (116 B); per CSR edge its column in the streamed
-    format (uint16 when every network has <= 65,536 cells, else int32) plus
-    its fp32 weight when the network has per-edge weights; per CSR row its
-    row pointer (8 B). Gathered neighbour voltages are cache hits and not
+def algorithmic_bytes(nets, paths=None):
+    """Bytes one step launch must move at minimum, in the format each network
+    is streamed in (`paths`: the library's gap path per network; None takes
+    the CSR gather format): per cell 14 state floats in and out plus the bias
+    (116 B); per CSR edge its column (uint16 when every CSR network has
+    <= 65,536 cells, else int32) plus its fp32 weight when the network has
+    per-edge weights, and per CSR row its row pointer (8 B); for a network on
+    the coupling bitmap instead, one bit per (row, column) pair in rows of
+    whole 32-bit words. Gathered neighbour voltages are cache hits and not
     counted."""
     col_b = 2 if all(n.n <= 65536 for n in nets if n.conn == "csr") else 4
     b = 0
-    for n in nets:
+    for k, n in enumerate(nets):
         b += 116 * n.n
-        if n.conn == "csr":
+        if n.conn == "csr" and paths is not None and paths[k] == "csr_bitmap":
+            b += 4 * n.n * ((n.n + 31) // 32)
+        elif n.conn == "csr":
             b += (col_b + (4 if n.w_csr is not None else 0)) * int(n.row_ptr[-1]) + 8 * n.n
         elif n.conn == "dense":
             b += 4 * n.n * n.n
@@ -179,6 +184,26 @@ def algorithmic_bytes(nets):
 # CSR edge: v_sub, v_mul, v_mul, v_exp_f32 (2 slots), v_fma, v_add and two
 # address operations for the 16-bit column gather.
 CSR_SLOTS_PER_EDGE = 9
+# Simplified gap junctions, per CSR edge: v_sub, v_fma and the two address
+# operations.
+SGJ_SLOTS_PER_EDGE = 4
+# Coupling bitmap: every (row, column) pair is evaluated and masked by its
+# bit: v_and, v_cmp, v_cndmask, then v_sub, v_mul, v_exp_f32 (2 slots), v_fma
+# and v_fmac.
+BITMAP_SLOTS_PER_PAIR = 9
+
+
+def slots_of(n, path=None):
+    """Issue slots of one network's step: its compartment updates plus its
+    pair or edge work in the form the path evaluates it."""
+    s = CELL_SLOTS * n.n
+    if n.conn == "uniform":
+        s += UNIFORM_SLOTS_PER_PAIR * n.n * n.n
+    elif n.conn == "csr" and path == "csr_bitmap":
+        s += BITMAP_SLOTS_PER_PAIR * n.n * n.n
+    elif n.conn in ("csr", "dense"):
+        s += (SGJ_SLOTS_PER_EDGE if n.gap == "sgj" else CSR_SLOTS_PER_EDGE) * n.pairs_per_step()
+    return s
 
 
 def step_kernel_name(info, nets):
@@ -204,20 +229,21 @@ def step_kernel_name(info, nets):
     return f"{narrow} + infoli::k_step<{wblock}, {2 if var == 2 else 0}> (concurrent graph branches)"
 
 
-def roofline(nets, launch_s, kernel="infoli::k_step<256, 2>"):
+def roofline(nets, launch_s, kernel="infoli::k_step<256, 2>", paths=None):
+    """The roofline of one step launch. `paths`: the library's gap path per
+    network (bytes and pair work are counted in the form it streams and
+    evaluates); None takes the CSR gather format."""
+    paths = paths if paths is not None else [None] * len(nets)
     kinds = {n.conn for n in nets}
     if len(kinds) > 1:
-        # mixed batch: issue slots of the pair/edge work against the lane-slot
-        # peak; and the composite bound, per network the larger of its bytes
-        # at the HBM peak and its issue slots at the lane-slot peak, summed
-        def slots_of(n):
-            return (UNIFORM_SLOTS_PER_PAIR * n.n * n.n if n.conn == "uniform"
-                    else CSR_SLOTS_PER_EDGE * n.pairs_per_step())
-        slots = sum(slots_of(n) for n in nets)
+        # mixed batch: issue slots against the lane-slot peak; and the
+        # composite bound, per network the larger of its bytes at the HBM
+        # peak and its issue slots at the lane-slot peak, summed
+        slots = sum(slots_of(n, p) for n, p in zip(nets, paths))
         achieved = slots / launch_s / 1e12
         peak = LANE_SLOTS_PER_S / 1e12
-        t_roof = sum(max(algorithmic_bytes([n]) / (HBM_PEAK_GBS * 1e9), slots_of(n) / LANE_SLOTS_PER_S)
-                     for n in nets)
+        t_roof = sum(max(algorithmic_bytes([n], [p]) / (HBM_PEAK_GBS * 1e9), slots_of(n, p) / LANE_SLOTS_PER_S)
+                     for n, p in zip(nets, paths))
         return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T lane-slots/s",
                 "frac": achieved / peak, "traffic": None, "kernel": kernel,
                 "slots_per_launch": slots, "composite_roofline_us": t_roof * 1e6,
@@ -232,7 +258,25 @@ def roofline(nets, launch_s, kernel="infoli::k_step<256, 2>"):
                 "frac": achieved / peak, "traffic": None, "kernel": kernel,
                 "slots_per_pair": UNIFORM_SLOTS_PER_PAIR, "pairs_per_launch": pairs,
                 "frac_vs_exp_shared_minimum": achieved / peak_shared}
-    abytes = algorithmic_bytes(nets)
+    abytes = algorithmic_bytes(nets, paths)
+    if all(n.conn == "csr" for n in nets):
+        # the larger of the two bounds: bytes at the HBM peak or issue slots
+        # at the lane-slot peak (a network on the coupling bitmap streams few
+        # bytes and evaluates every pair)
+        slots = sum(slots_of(n, p) for n, p in zip(nets, paths))
+        t_hbm = abytes / (HBM_PEAK_GBS * 1e9)
+        t_alu = slots / LANE_SLOTS_PER_S
+        extra = {"algorithmic_bytes_per_launch": abytes, "slots_per_launch": slots,
+                 "hbm_frac": t_hbm / launch_s, "alu_frac": t_alu / launch_s,
+                 "gap_paths": sorted(set(p or "csr_gather" for p in paths))}
+        if t_alu > t_hbm:
+            achieved = slots / launch_s / 1e12
+            peak = LANE_SLOTS_PER_S / 1e12
+            return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T lane-slots/s",
+                    "frac": achieved / peak, "traffic": None, "kernel": kernel, **extra}
+        achieved = abytes / launch_s / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel, **extra}
     achieved = abytes / launch_s / 1e9
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
@@ -345,6 +389,7 @@ def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
     # plain method
     plain = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
     info = plain.info()
+    paths = [plain.gap_path(0)[0]]
     ref, t_plain = [], 0.0
     for _ in range(samples):
         plain.step(4 * every)
@@ -412,7 +457,7 @@ def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
         "ablation_mlp_no_fallback": {"speedup": t_plain / nofb["ms"], "rmse_mv": nofb["rmse_mv"],
                                      "spike_time_err_ms": nofb["spike_time_err_ms"]},
         "training": {**rep, "wall_s": train_wall},
-        "roofline": roofline(nets, t_plain * 1e-3 / total_steps, step_kernel_name(info, nets)),
+        "roofline": roofline(nets, t_plain * 1e-3 / total_steps, step_kernel_name(info, nets), paths),
     }
     out["roofline"]["traffic"] = measured_traffic(args.workload)
     if not args.no_cpu_baseline:
@@ -616,6 +661,7 @@ def main():
     sim = infoli.Simulator(nets, init_states=x0s, stream=stream, step_mode=args.mode,
                            graph_chunk=args.graph_chunk)
     info = sim.info()
+    paths = [sim.gap_path(k)[0] for k in range(len(nets))]
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -651,7 +697,7 @@ def main():
                    "lanes_per_row": info["lanes_per_row"]},
         "gap_pairs_per_s": pairs * steps / wall,
         "device_ms_per_step": dev_ms / steps,
-        "roofline": roofline(nets, launch_s, step_kernel_name(info, nets)),
+        "roofline": roofline(nets, launch_s, step_kernel_name(info, nets), paths),
     }
     out["roofline"]["traffic"] = measured_traffic(args.workload)
     if not args.no_cpu_baseline:

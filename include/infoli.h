@@ -280,6 +280,33 @@ typedef struct infoli_info {
 } infoli_info;
 infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
 
+/* The gap-junction path one network runs, as chosen at init (by the tuner or
+ * the built-in rule), which fixes the form in which its coupling is read each
+ * step (the coupling of Section 2.3, Algorithm 1; for the CSR paths, the
+ * same sum over each row's neighbours, reordered only within a row):
+ *   NONE        no gap junctions;
+ *   UNIFORM     all-to-all with one weight: only the Vd vector is read;
+ *   DENSE       the n x n fp32 weight matrix;
+ *   CSR_GATHER  row pointers and columns (uint16 when every CSR network of the
+ *               context has <= 65,536 cells, else int32), fp32 weights if given;
+ *   CSR_CHUNKED the same columns as uint16 in 16-byte chunks of eight;
+ *   CSR_BITMAP  one bit per (row, column) pair; every pair is evaluated and
+ *               masked by its bit (one weight g, <= 16,384 cells).
+ * (The persistent step mode walks CSR rows from the gather format.)
+ * *path receives the code; *vd_blocked (either pointer may be NULL) receives
+ * 1 when the network's Vd is staged in LDS one column block at a time (CSR
+ * networks too large for one LDS copy), else 0.
+ * Errors: INVALID_ARG when ctx is NULL or instance is out of range. */
+typedef enum infoli_gap_path {
+    INFOLI_PATH_NONE = 0,
+    INFOLI_PATH_UNIFORM = 1,
+    INFOLI_PATH_DENSE = 2,
+    INFOLI_PATH_CSR_GATHER = 3,
+    INFOLI_PATH_CSR_CHUNKED = 4,
+    INFOLI_PATH_CSR_BITMAP = 5
+} infoli_gap_path;
+infoli_status infoli_get_gap_path(const infoli_ctx *ctx, int32_t instance, int32_t *path, int32_t *vd_blocked);
+
 /* Duration (ms, HIP events on the context stream) of the last infoli_step
  * call's device work; valid after infoli_sync. */
 infoli_status infoli_last_step_ms(infoli_ctx *ctx, float *ms);

@@ -1622,6 +1622,34 @@ infoli_status infoli_get_info(const infoli_ctx* ctx, infoli_info* info) {
     return INFOLI_OK;
 }
 
+infoli_status infoli_get_gap_path(const infoli_ctx* ctx, int32_t instance, int32_t* path, int32_t* vd_blocked) {
+    if (!ctx) {
+        g_thread_error = "ctx is NULL";
+        return INFOLI_E_INVALID_ARG;
+    }
+    return guarded(const_cast<infoli_ctx*>(ctx), [&] {
+        check_instance(ctx, instance);
+        // the step kernel's own dispatch: the bitmap first; column blocks
+        // only in the wide launch group (chunked when the block-major chunk
+        // layout exists; simplified networks without it take row gathers);
+        // else chunked rows or plain gathers
+        const InstDesc& d = ctx->inst[instance];
+        int32_t p = INFOLI_PATH_NONE, blk = 0;
+        if (d.conn == CONN_UNIFORM) p = INFOLI_PATH_UNIFORM;
+        else if (d.conn == CONN_DENSE) p = INFOLI_PATH_DENSE;
+        else if (d.conn == CONN_CSR) {
+            const bool wide = ctx->group_of.size() > (size_t)instance && ctx->group_of[instance] == 1;
+            if (ctx->opt.step_mode == INFOLI_MODE_PERSISTENT) p = INFOLI_PATH_CSR_GATHER;   // row walks
+            else if (d.bitmap) p = INFOLI_PATH_CSR_BITMAP;
+            else if (wide && d.blocked && d.cb_off >= 0) p = INFOLI_PATH_CSR_CHUNKED, blk = 1;
+            else if (wide && d.blocked && !d.sgj) p = INFOLI_PATH_CSR_GATHER, blk = 1;
+            else p = d.chunked && d.ca_off >= 0 ? INFOLI_PATH_CSR_CHUNKED : INFOLI_PATH_CSR_GATHER;
+        }
+        if (path) *path = p;
+        if (vd_blocked) *vd_blocked = blk;
+    });
+}
+
 infoli_status infoli_last_step_ms(infoli_ctx* ctx, float* ms) {
     if (!ctx || !ms) {
         g_thread_error = "ctx or ms is NULL";

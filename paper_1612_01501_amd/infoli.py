@@ -31,7 +31,7 @@ EXPORTS = (
     "infoli_batch_init", "infoli_step", "infoli_sync", "infoli_read_state",
     "infoli_read_state_device", "infoli_write_state", "infoli_read_gap_current",
     "infoli_read_spikes", "infoli_clear_spikes", "infoli_output_copy_async", "infoli_output_wait",
-    "infoli_get_info", "infoli_last_step_ms",
+    "infoli_get_info", "infoli_get_gap_path", "infoli_last_step_ms",
     "infoli_state_var_name", "infoli_last_error", "infoli_destroy",
     "infoli_default_train_cfg", "infoli_default_drift_cfg", "infoli_surrogate_train",
     "infoli_surrogate_get", "infoli_surrogate_set", "infoli_step_surrogate",
@@ -148,6 +148,8 @@ def lib():
     L.infoli_output_copy_async.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64]
     L.infoli_output_wait.argtypes = [vp]
     L.infoli_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.infoli_get_gap_path.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]
     L.infoli_last_step_ms.argtypes = [vp, _PF]
     L.infoli_state_var_name.argtypes = [ctypes.c_int32]
     L.infoli_state_var_name.restype = ctypes.c_char_p
@@ -271,6 +273,7 @@ def mlp_adam_step(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e
 
 
 GAP_KIND = {"rgj": 0, "sgj": 1}
+GAP_PATH = ("none", "uniform", "dense", "csr_gather", "csr_chunked", "csr_bitmap")
 
 
 class _SpecHolder:
@@ -409,6 +412,13 @@ class Simulator:
         i = Info()
         _check(lib().infoli_get_info(self._ctx, ctypes.byref(i)), self._ctx)
         return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def gap_path(self, k: int = 0):
+        """(path name, Vd staged by column blocks) of network k: the form
+        its coupling is read in each step."""
+        p, blk = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().infoli_get_gap_path(self._ctx, k, ctypes.byref(p), ctypes.byref(blk)), self._ctx)
+        return GAP_PATH[p.value], bool(blk.value)
 
     # ----------------------------------------------------------- surrogate
     def surrogate_train(self, init_params, cfg: Optional[TrainCfg] = None, **kw):

@@ -34,6 +34,12 @@ def test_algorithmic_bytes_by_hand():
     assert bench.algorithmic_bytes([dense]) == 116 * 2 + 4 * 4
     assert bench.algorithmic_bytes([I.Network(n=5, conn="uniform", g=0.1)]) == 116 * 5
     assert bench.algorithmic_bytes([I.Network(n=7, conn="none")]) == 116 * 7
+    # a network on the coupling bitmap streams one bit per (row, column)
+    # pair, rows of whole 32-bit words, instead of columns and row pointers
+    assert bench.algorithmic_bytes([csr], ["csr_bitmap"]) == 116 * 3 + 4 * 3 * 1
+    big = I.Network(n=40, conn="csr", g=0.04, row_ptr=np.zeros(41, np.int64), col=np.zeros(0, np.int32))
+    assert bench.algorithmic_bytes([big], ["csr_bitmap"]) == 116 * 40 + 4 * 40 * 2
+    assert bench.algorithmic_bytes([csr], ["csr_chunked"]) == bench.algorithmic_bytes([csr])
 
 
 def test_roofline_bound_per_workload_kind():
@@ -54,13 +60,41 @@ def test_roofline_bound_per_workload_kind():
     mixed = bench.roofline([I.Network(n=10, conn="uniform", g=0.1),
                             I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)], 1e-6)
     assert mixed["bound"] == "alu" and mixed["unit"] == "T lane-slots/s"
-    # composite: per network the larger of bytes at the HBM peak and slots at
-    # the lane-slot peak, summed
-    u = 5 * 10 * 10 / bench.LANE_SLOTS_PER_S
+    # composite: per network the larger of bytes at the HBM peak and slots
+    # (compartment updates and pair work) at the lane-slot peak, summed
+    u = (5 * 10 * 10 + bench.CELL_SLOTS * 10) / bench.LANE_SLOTS_PER_S
     c_bytes = (116 * 3 + 2 * 2 + 8 * 3) / 8e12
-    c_slots = bench.CSR_SLOTS_PER_EDGE * 2 / bench.LANE_SLOTS_PER_S
+    c_slots = (bench.CSR_SLOTS_PER_EDGE * 2 + bench.CELL_SLOTS * 3) / bench.LANE_SLOTS_PER_S
+    assert mixed["slots_per_launch"] == 5 * 100 + bench.CELL_SLOTS * 13 + bench.CSR_SLOTS_PER_EDGE * 2
     assert mixed["composite_roofline_us"] == pytest.approx((max(116 * 10 / 8e12, u) + max(c_bytes, c_slots)) * 1e6)
     assert mixed["composite_frac"] == pytest.approx(mixed["composite_roofline_us"] * 1e-6 / 1e-6)
+
+
+def test_csr_roofline_takes_the_larger_bound():
+    """All-CSR launches: bound = the larger of bytes at the HBM peak and issue
+    slots at the lane-slot peak, each network counted in its path's form."""
+    n = 64
+    edges = [(i, j) for i in range(n) for j in range(n) if i != j and (i + j) % 2 == 1]
+    rp, col = _csr(n, edges)
+    net = I.Network(n=n, conn="csr", g=0.04, row_ptr=rp, col=col)
+    launch = 1e-6
+    gath = bench.roofline([net], launch, paths=["csr_gather"])
+    b_g = 116 * n + 2 * len(edges) + 8 * n
+    s_g = bench.CELL_SLOTS * n + bench.CSR_SLOTS_PER_EDGE * len(edges)
+    assert gath["algorithmic_bytes_per_launch"] == b_g and gath["slots_per_launch"] == s_g
+    bit = bench.roofline([net], launch, paths=["csr_bitmap"])
+    b_b = 116 * n + 4 * n * 2
+    s_b = bench.CELL_SLOTS * n + bench.BITMAP_SLOTS_PER_PAIR * n * n
+    assert bit["algorithmic_bytes_per_launch"] == b_b and bit["slots_per_launch"] == s_b
+    for r, b, sl in ((gath, b_g, s_g), (bit, b_b, s_b)):
+        t_hbm, t_alu = b / 8e12, sl / bench.LANE_SLOTS_PER_S
+        assert r["hbm_frac"] == pytest.approx(t_hbm / launch) and r["alu_frac"] == pytest.approx(t_alu / launch)
+        assert r["bound"] == ("alu" if t_alu > t_hbm else "hbm")
+        assert r["frac"] == pytest.approx(max(t_hbm, t_alu) / launch)
+    assert bit["bound"] == "alu" and bit["unit"] == "T lane-slots/s" and bit["gap_paths"] == ["csr_bitmap"]
+    # simplified gap junctions cost fewer slots per edge
+    sgj = I.Network(n=n, conn="csr", g=0.04, row_ptr=rp, col=col, gap="sgj")
+    assert bench.slots_of(sgj) == bench.CELL_SLOTS * n + bench.SGJ_SLOTS_PER_EDGE * len(edges)
 
 
 def test_step_kernel_variant_names():

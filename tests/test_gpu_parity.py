@@ -889,6 +889,39 @@ def test_bitmap_in_the_wide_group(infoli, o32, o64, wide):
     assert per_var_error(xk1[None], ref[None]).max() <= 1e-5
 
 
+def test_gap_path_reports_the_path_in_use(infoli):
+    """The per-network path query names the form each network's coupling is
+    read in: by kind for all-to-all and dense networks, and the forced CSR
+    path; an instance out of range is refused."""
+    rng = np.random.default_rng(3)
+    w = (rng.random((50, 50)) * 0.01).astype(np.float32)
+    np.fill_diagonal(w, 0.0)
+    nets = [I.Network(n=40, conn="none"), I.Network(n=60, conn="uniform", g=0.04),
+            I.config1(0.1, seed=5, n=700)]
+    sim = infoli.Simulator(nets, csr_path=1, autotune=0)   # (a batch takes no dense and CSR together)
+    got = [sim.gap_path(k) for k in range(3)]
+    with pytest.raises(infoli.InfoliError) as e:
+        sim.gap_path(3)
+    sim.close()
+    assert e.value.status == 1
+    assert got == [("none", False), ("uniform", False), ("csr_gather", False)]
+    sim = infoli.Simulator(I.Network(n=50, conn="dense", w_dense=w))
+    assert sim.gap_path(0) == ("dense", False)
+    sim.close()
+    for path, name in ((2, "csr_bitmap"), (4, "csr_chunked")):
+        sim = infoli.Simulator(nets[2], csr_path=path, autotune=0)
+        assert sim.gap_path(0) == (name, False)
+        sim.close()
+    big = I.config4(seed=9, n=9000, degree=50)
+    sim = infoli.Simulator(big, csr_path=3, autotune=0)
+    path, blocked = sim.gap_path(0)
+    sim.close()
+    assert blocked and path in ("csr_gather", "csr_chunked")
+    sim = infoli.Simulator(nets[2], step_mode="persistent")
+    assert sim.gap_path(0) == ("csr_gather", False)
+    sim.close()
+
+
 def test_headline_mix_as_tuned(infoli, o32, o64):
     """The three 4,096-cell networks in one context, shapes and launch
     arrangement as the tuner picks them (as the benchmark runs): after 100

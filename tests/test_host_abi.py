@@ -76,6 +76,9 @@ def test_state_names_and_errors():
     assert L.infoli_state_var_name(-1) is None
     assert L.infoli_default_params(None) == 1
     assert b"NULL" in L.infoli_last_error(None)
+    p = ctypes.c_int32(-1)
+    assert L.infoli_get_gap_path(None, 0, ctypes.byref(p), None) == 1
+    assert p.value == -1
 
 
 def _init_status(net, **kw):
