@@ -188,9 +188,9 @@ CSR_SLOTS_PER_EDGE = 9
 # operations.
 SGJ_SLOTS_PER_EDGE = 4
 # Coupling bitmap: every (row, column) pair is evaluated and masked by its
-# bit: v_and, v_cmp, v_cndmask, then v_sub, v_mul, v_exp_f32 (2 slots), v_fma
-# and v_fmac.
-BITMAP_SLOTS_PER_PAIR = 9
+# bit, the row's 64-bit word of 64 senders serving as the lane mask of one
+# select: v_sub, v_mul, v_exp_f32 (2 slots), v_fma, v_cndmask, v_fmac.
+BITMAP_SLOTS_PER_PAIR = 7
 
 
 def slots_of(n, path=None):

@@ -214,7 +214,7 @@ namespace {
 
 size_t bitmap_lds_floats(int n) {
     const int groups = (n + kBitGroup - 1) / kBitGroup;
-    return (size_t)std::min(groups, kBitChunkGroups) * 4 * kBitStride;
+    return (size_t)std::min(groups, kBitChunkGroups) * kBitGroup;
 }
 
 void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int rows, double deg) {

@@ -697,10 +697,9 @@ __device__ __forceinline__ void gap_csr(const StepArgs& a, const InstDesc& d, co
 // Bitmap words of a network: group gr (128 senders), row r (padded to a
 // multiple of 16 rows), block p (senders gr*128 + 32p .. +31): word
 // (gr * n_pad16 + r) * 4 + p, bit t = sender gr*128 + 32p + t. LDS holds a
-// chunk of prescaled Vd with each 32-sender block at a stride of 36 floats.
+// chunk of prescaled Vd, contiguous.
 constexpr int kBitGroup = 128;
 constexpr int kBitRows = 16;
-constexpr int kBitStride = 36;
 constexpr int kBitChunkGroups = kChunk / kBitGroup;            // 64 groups per LDS chunk
 
 __host__ __device__ __forceinline__ int bitmap_rows_pad(int n) { return (n + kBitRows - 1) / kBitRows * kBitRows; }
@@ -709,59 +708,96 @@ template <int BLOCK>
 __device__ __forceinline__ void gap_bitmap(const StepArgs& a, const InstDesc& d, const Tile& t,
                                            const float* __restrict__ vd, float* s_v, float* s_part,
                                            float* s_ig) {
+    // Lanes are senders, the tile's 16 rows are wave-uniform: row r's 64-bit
+    // coupling word for 64 senders is a scalar load and masks the pair term
+    // as the lane mask of one select.
     constexpr int W = BLOCK / 64;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int p = lane >> 4;                   // 32-sender block within a group
-    const int r = lane & 15;                   // row within the tile
-    const int row = t.row0 + r;
-    const bool valid = row < t.row1;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = d.n;
     const int npad = bitmap_rows_pad(n);
     const int groups = (n + kBitGroup - 1) / kBitGroup;
-    const uint32_t* bits = a.bits + d.bits_off;
-    const float vis = valid ? vd[row] * kPreScale : 0.0f;
-    float acc0 = 0.0f, acc1 = 0.0f;
+    const int nrows = t.row1 - t.row0;
+    float vis[kBitRows];
+    float acc[kBitRows];
+#pragma unroll
+    for (int r = 0; r < kBitRows; ++r) {
+        vis[r] = r < nrows ? vd[t.row0 + r] * kPreScale : 0.0f;
+        acc[r] = 0.0f;
+    }
+    // words of the tile's rows in group gr: 16 rows x 4 words, contiguous
+    const uint32_t* bits = a.bits + d.bits_off + (int64_t)t.row0 * 4;
     for (int g0 = 0; g0 < groups; g0 += kBitChunkGroups) {
         const int gc = min(kBitChunkGroups, groups - g0);
         __syncthreads();
-        // stage the chunk's senders, prescaled, 32-sender blocks at stride 36
         for (int k = threadIdx.x; k < gc * kBitGroup; k += BLOCK) {
             const int j = g0 * kBitGroup + k;
-            s_v[(k >> 5) * kBitStride + (k & 31)] = j < n ? vd[j] * kPreScale : kSentinel;
+            s_v[k] = j < n ? vd[j] * kPreScale : kSentinel;
         }
         __syncthreads();
         const int per = (gc + W - 1) / W;
         const int gb = wave * per, ge = min(gc, gb + per);
         for (int gl = gb; gl < ge; ++gl) {
-            const uint32_t wbits = valid ? bits[((int64_t)(g0 + gl) * npad + row) * 4 + p] : 0u;
-            const float4* sv = reinterpret_cast<const float4*>(s_v + (gl * 4 + p) * kBitStride);
+            // qword 2r + h: row r's senders (g0 + gl) * 128 + 64h + (0..63);
+            // the bitmap is not written while a step runs, so it is read
+            // through the constant address space (scalar loads)
+            const auto wq = (const __attribute__((address_space(4))) uint64_t*)(
+                bits + (int64_t)(g0 + gl) * npad * 4);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const float4 v4 = sv[q];
-                const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+            for (int h = 0; h < 2; ++h) {
+                const float vj = s_v[gl * kBitGroup + 64 * h + lane];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int tb = 4 * q + e;
-                    const float dv = vis - vv[e];
+                for (int r = 0; r < kBitRows; ++r) {
+                    const float dv = vis[r] - vj;
                     const float f = fmaf(0.8f, __builtin_amdgcn_exp2f(-(dv * dv)), 0.2f);
-                    // all ones when the bit is set, else zero (signed 1-bit field)
-                    const int m = __builtin_amdgcn_sbfe((int)wbits, tb, 1);
-                    const float dm = __int_as_float(__float_as_int(dv) & m);
-                    if (e & 1) acc1 = fmaf(dm, f, acc1);
-                    else acc0 = fmaf(dm, f, acc0);
+                    const float dm = __builtin_amdgcn_inverse_ballot_w64(wq[2 * r + h]) ? dv : 0.0f;
+                    acc[r] = fmaf(dm, f, acc[r]);
                 }
             }
         }
     }
-    float acc = acc0 + acc1;
-    acc += __shfl_xor(acc, 16, 64);
-    acc += __shfl_xor(acc, 32, 64);
-    if (p == 0) s_part[wave * 16 + r] = acc;
+    // Sum each row over the 64 lanes: four exchanges that halve the values
+    // a lane holds (a lane with bit b of its index set keeps the upper half)
+    // leave lane l with row (l & 15) summed over its 16-lane group; two
+    // more add the four groups.
+    float v8[8], v4[4], v2[2];
+    {
+        const bool up = lane & 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float keep = up ? acc[i + 8] : acc[i], send = up ? acc[i] : acc[i + 8];
+            v8[i] = keep + __shfl_xor(send, 8, 64);
+        }
+    }
+    {
+        const bool up = lane & 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float keep = up ? v8[i + 4] : v8[i], send = up ? v8[i] : v8[i + 4];
+            v4[i] = keep + __shfl_xor(send, 4, 64);
+        }
+    }
+    {
+        const bool up = lane & 2;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float keep = up ? v4[i + 2] : v4[i], send = up ? v4[i] : v4[i + 2];
+            v2[i] = keep + __shfl_xor(send, 2, 64);
+        }
+    }
+    float v1;
+    {
+        const bool up = lane & 1;
+        const float keep = up ? v2[1] : v2[0], send = up ? v2[0] : v2[1];
+        v1 = keep + __shfl_xor(send, 1, 64);
+    }
+    v1 += __shfl_xor(v1, 16, 64);
+    v1 += __shfl_xor(v1, 32, 64);
+    if (lane < kBitRows) s_part[wave * kBitRows + lane] = v1;
     __syncthreads();
-    if (threadIdx.x < 16 && t.row0 + (int)threadIdx.x < t.row1) {
+    if (threadIdx.x < kBitRows && t.row0 + (int)threadIdx.x < t.row1) {
         float tot = 0.0f;
-        for (int w = 0; w < W; ++w) tot += s_part[w * 16 + threadIdx.x];
+        for (int w = 0; w < W; ++w) tot += s_part[w * kBitRows + threadIdx.x];
         s_ig[threadIdx.x] = d.g * (tot * kInvPreScale);
     }
 }
