@@ -466,7 +466,7 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
 // candidate tile shapes (lanes per row, rows per tile, LDS staging of Vd) are
 // timed on the network's own device data with dry launches (they write only
 // the next-state buffer) and the fastest is kept, in memory and in an
-// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v10.txt).
+// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v11.txt).
 struct TuneChoice {
     int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS,
                            // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers)
@@ -477,7 +477,7 @@ std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v10.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v11.txt";
     return "";
 }
 
@@ -490,8 +490,8 @@ std::string tune_key(const infoli_ctx* c, const InstDesc& d, double deg) {
     return buf;
 }
 
-// Whole-step launch modes: five bits (see the tuner below), so 0..31.
-constexpr int kStepModes = 32;
+// Whole-step launch modes: six bits (see the tuner below), so 0..63.
+constexpr int kStepModes = 64;
 
 // Lines "<class key>|L R lds bm block" (the class's best shape),
 // "<class key>#256|..." (its best shape in 256-thread workgroups) and
@@ -656,6 +656,7 @@ void autotune(infoli_ctx* c) {
     struct ClassChoice {
         TuneChoice best, best256, best256nc;   // overall; in 256 threads; in 256 threads, not chunked
         TuneChoice best1024;                   // in 1024 threads (block 0: none timed)
+        TuneChoice bm256, bm1024;              // the bitmap path in 256 / 1024 threads (block 0: none)
         TuneChoice alt[kAlts];                 // the fastest distinct 256-thread shapes, fastest first
         int nalt = 0;
     };
@@ -665,6 +666,7 @@ void autotune(infoli_ctx* c) {
         const std::vector<int>& ks = kv.second;
         TuneChoice best{0, 0, 0, 0, 256}, best256{0, 0, 0, 0, 256}, best256nc{0, 0, 0, 0, 256};
         TuneChoice best1024{0, 0, 0, 0, 0};
+        TuneChoice bm256{0, 0, 0, 0, 0}, bm1024{0, 0, 0, 0, 0};
         ClassChoice cc;
         auto hit = cache.find(key);
         auto hit256 = cache.find(key + "#256");
@@ -679,6 +681,10 @@ void autotune(infoli_ctx* c) {
             best256 = hit256->second;
             best256nc = hitnc->second;
             best1024 = hit1024->second;
+            auto hb = cache.find(key + "#bm256");
+            if (hb != cache.end() && hb->second.bm == 1 && hb->second.block == 256) bm256 = hb->second;
+            hb = cache.find(key + "#bm1024");
+            if (hb != cache.end() && hb->second.bm == 1 && hb->second.block == 1024) bm1024 = hb->second;
             for (int a = 0; a < kAlts; ++a) {
                 auto h = cache.find(key + "#a" + std::to_string(a));
                 if (h == cache.end() || h->second.block != 256 || h->second.L > 256) break;
@@ -717,6 +723,7 @@ void autotune(infoli_ctx* c) {
                     best1024_ms = ms;
                     best1024 = t;
                 }
+                if (t.bm == 1) (t.block == 256 ? bm256 : bm1024) = t;
             };
             for (int L = 4; L <= 256; L *= 2) {
                 if (L > 4 && L > 2.0 * deg) break;
@@ -769,6 +776,8 @@ void autotune(infoli_ctx* c) {
             append_tune_cache(path, key + "#256", best256);
             append_tune_cache(path, key + "#256nc", best256nc);
             append_tune_cache(path, key + "#1024", best1024);
+            if (bm256.block) append_tune_cache(path, key + "#bm256", bm256);
+            if (bm1024.block) append_tune_cache(path, key + "#bm1024", bm1024);
             for (int a = 0; a < cc.nalt; ++a) append_tune_cache(path, key + "#a" + std::to_string(a), cc.alt[a]);
             c->tuned += (int)ks.size();
         }
@@ -776,6 +785,8 @@ void autotune(infoli_ctx* c) {
         cc.best256 = best256;
         cc.best256nc = best256nc;
         cc.best1024 = best1024;
+        cc.bm256 = bm256;
+        cc.bm1024 = bm1024;
         chosen[key] = cc;
     }
 
@@ -795,8 +806,13 @@ void autotune(infoli_ctx* c) {
     // variant of the per-class choices: bit 0, each class in its best
     // 256-thread shape; bit 3, each class in its best 1024-thread shape;
     // bit 2, chunked gathers in 256 threads replaced by the best
-    // non-chunked 256-thread shape
+    // non-chunked 256-thread shape; bit 5, every class that has a bitmap
+    // shape takes it (in 1024 threads under bit 3 when timed, else in 256):
+    // timed alone a class can rank the bitmap and its gathers differently
+    // from the whole step
     auto pick = [&](const ClassChoice& ch, int m) {
+        if ((m & 32) && (ch.bm256.block || ch.bm1024.block))
+            return ((m & 8) && ch.bm1024.block) || !ch.bm256.block ? ch.bm1024 : ch.bm256;
         TuneChoice t = (m & 8) && ch.best1024.block == 1024 ? ch.best1024 : (m & 1) ? ch.best256 : ch.best;
         if ((m & 4) && t.bm == 3 && t.block == 256) t = ch.best256nc;
         return t;
@@ -809,7 +825,7 @@ void autotune(infoli_ctx* c) {
         for (int k = 0; k < c->n_inst; ++k)
             if (c->inst[k].conn == CONN_UNIFORM) c->inst[k].wide = (m & 8) ? 1 : 0;
     };
-    // bits 0, 2 and 3 as above; bit 1: the two launch groups one after the
+    // bits 0, 2, 3 and 5 as above; bit 1: the two launch groups one after the
     // other; bit 4: the wide launch group in 512-thread workgroups (two per
     // compute unit, so one can stage a column block while the other gathers)
     int mode = 0;
@@ -820,8 +836,9 @@ void autotune(infoli_ctx* c) {
         mode = mh->second[0];
         for (int i = 0; i < ncls; ++i) refine[i] = mh->second[1 + i];
     } else {
-        bool wide = false, chunk = false, narrow = false;   // variants that change something
+        bool wide = false, chunk = false, narrow = false, bits = false;   // variants that change something
         for (const auto& kv : chosen) {
+            bits = bits || kv.second.bm256.block || kv.second.bm1024.block;
             wide = wide || kv.second.best.block != 256;
             narrow = narrow || (kv.second.best.block == 256 && kv.second.best1024.block == 1024);
             chunk = chunk || kv.second.best.bm == 3 || kv.second.best256.bm == 3;
@@ -832,6 +849,7 @@ void autotune(infoli_ctx* c) {
         for (int round = 0; round < 2; ++round)
             for (int m = 0; m < kStepModes; ++m) {
                 if (((m & 1) && !wide) || ((m & 4) && !chunk) || ((m & 8) && (!narrow || (m & 1)))) continue;
+                if ((m & 32) && !bits) continue;
                 if ((m & 16) && c->opt.wide_threads) continue;
                 apply_all(m);
                 c->grp[1].block = wide_block(m);

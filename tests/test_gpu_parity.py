@@ -456,14 +456,18 @@ def test_autotuner_times_caches_and_stays_exact(infoli, o32, tmp_path, monkeypat
         else:
             assert info["tuned"] == 0 and info["tune_cached"] == 2
     lines = (tmp_path / "tune.txt").read_text().strip().splitlines()
-    # per class its best, best 256-thread, best non-chunked 256-thread and
-    # best 1024-thread shapes and up to eight 256-thread alternatives; then
+    # per class its best, best 256-thread, best non-chunked 256-thread,
+    # best 1024-thread and bitmap shapes and up to eight 256-thread
+    # alternatives; then
     # the whole-step choice for the mix (mode and one refinement per class)
     assert all("|" in l for l in lines)
     ctx = [l for l in lines if l.startswith("ctx ")]
     assert len(ctx) == 1 and len(ctx[0].split("|")[1].split()) == 1 + 2
     assert sum("#256|" in l for l in lines) == 2 and sum("#256nc|" in l for l in lines) == 2
     assert sum("#1024|" in l for l in lines) == 2
+    # both classes have one weight and <= 16,384 cells: their bitmap shapes
+    # in 256 and 1024 threads are kept for the whole-step search
+    assert sum("#bm256|" in l for l in lines) == 2 and sum("#bm1024|" in l for l in lines) == 2
     assert 2 <= sum("#a" in l for l in lines) <= 16
     for k, net in enumerate(nets):
         np.testing.assert_array_equal(out[0][k], out[1][k])
