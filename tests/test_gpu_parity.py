@@ -505,6 +505,37 @@ def test_cached_wide_step_mode_is_read_back(infoli, o32, tmp_path, monkeypatch):
     assert per_var_error(got[None], ref[None]).max() <= TOL_STATE
 
 
+def test_cached_bitmap_mode_puts_the_class_on_its_bitmap(infoli, o32, tmp_path, monkeypatch):
+    """Mode bit 5 read from the cache puts every class that has a bitmap
+    shape on the coupling bitmap; results stay within the oracle bound."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("INFOLI_TUNE_CACHE", str(path))
+    net = I.config1(0.3, seed=22, n=1500)
+    x0 = infoli.initial_state(net)
+    infoli.Simulator(net, init_states=[x0], autotune=2, step_mode="launch").close()
+    lines = path.read_text().strip().splitlines()
+    assert any("#bm256|" in l for l in lines) and any("#bm1024|" in l for l in lines)
+    ctx = [i for i, l in enumerate(lines) if l.startswith("ctx ")]
+    assert len(ctx) == 1
+    key, vals = lines[ctx[0]].split("|")
+    vals = vals.split()
+    vals[0] = str(int(vals[0]) | 32)
+    vals[1:] = ["-1"] * (len(vals) - 1)          # no per-class refinement over the bitmap
+    lines[ctx[0]] = key + "|" + " ".join(vals)
+    path.write_text("\n".join(lines) + "\n")
+    sim = infoli.Simulator(net, init_states=[x0], autotune=1, step_mode="launch")
+    info = sim.info()
+    gp = sim.gap_path(0)
+    sim.step(300)
+    got = sim.read_state(0)
+    sim.close()
+    assert info["tuned"] == 0 and info["tune_cached"] == 1
+    assert gp == ("csr_bitmap", False) and info["n_bitmap"] == 1
+    assert sum(l.startswith("ctx ") for l in path.read_text().strip().splitlines()) == 1
+    ref = o32.run(net, 300, x0=x0)["x"]
+    assert per_var_error(got[None], ref[None]).max() <= TOL_STATE
+
+
 # ------------------------------------------------------------------ batches of uneven networks
 def test_uneven_batch_against_oracle(infoli, o32, o64):
     """The 256-network batch recipe at reduced size: 24 networks of 64-600
