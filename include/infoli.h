@@ -47,7 +47,8 @@ extern "C" {
 typedef enum infoli_status {
     INFOLI_OK = 0,
     INFOLI_E_INVALID_ARG = 1,   /* NULL pointer, bad size, bad enum, capacity too small */
-    INFOLI_E_BAD_GRAPH = 2,     /* CSR not monotone, column out of range, non-finite weight */
+    INFOLI_E_BAD_GRAPH = 2,     /* CSR not monotone, column out of range or a row's columns
+                                   not strictly ascending, non-finite weight                 */
     INFOLI_E_OUT_OF_MEMORY = 3, /* device or host allocation failed                        */
     INFOLI_E_DEVICE = 4,        /* HIP runtime error, or no gfx950 device                   */
     INFOLI_E_NUMERIC = 5,       /* a state value became NaN or infinite while stepping      */
@@ -116,7 +117,8 @@ typedef struct infoli_network_spec {
     float g_uniform;            /* UNIFORM_ALL weight; CSR weight when w_csr is NULL       */
     const float *w_dense;       /* DENSE: [n][n], finite                                   */
     const int64_t *row_ptr;     /* CSR: [n+1], row_ptr[0] = 0, non-decreasing, = nnz at n  */
-    const int32_t *col;         /* CSR: [nnz], 0 <= col < n                                */
+    const int32_t *col;         /* CSR: [nnz], 0 <= col < n, strictly ascending within each
+                                   row (sorted, no repeated column): else INFOLI_E_BAD_GRAPH */
     const float *w_csr;         /* CSR: [nnz] finite weights, optional                     */
     int64_t nnz;                /* CSR: number of directed edges                           */
     const float *params;        /* optional [INFOLI_NUM_PARAMS]; NULL => defaults          */

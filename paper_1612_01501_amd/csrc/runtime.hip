@@ -109,6 +109,15 @@ void validate_spec(const infoli_network_spec& s, int k) {
                 if (s.col[e] < 0 || s.col[e] >= s.n_cells)
                     fail(INFOLI_E_BAD_GRAPH, "network %d: column %d out of range at edge %lld", k,
                          s.col[e], (long long)e);
+            // every row strictly ascending: the column-block and chunk layouts
+            // cut a row into contiguous per-block runs, and a repeated column
+            // would be one bit of the coupling bitmap but two gathered terms
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t e = s.row_ptr[i] + 1; e < s.row_ptr[i + 1]; ++e)
+                    if (s.col[e] <= s.col[e - 1])
+                        fail(INFOLI_E_BAD_GRAPH,
+                             "network %d: row %lld columns not strictly ascending at edge %lld (%d after %d)", k,
+                             (long long)i, (long long)e, s.col[e], s.col[e - 1]);
             if (s.w_csr && !finite_all(s.w_csr, s.nnz))
                 fail(INFOLI_E_BAD_GRAPH, "network %d: non-finite CSR weight", k);
             if (!s.w_csr && !std::isfinite(s.g_uniform))

@@ -129,6 +129,23 @@ def test_validation_rejects_bad_csr():
     assert st == 2 and "non-finite" in msg
 
 
+def test_validation_rejects_unsorted_or_repeated_columns():
+    # the column-block and chunk layouts assume every row strictly ascending
+    net = _csr_net(8)
+    rp, col = np.array(net.row_ptr), np.array(net.col)
+    row = int(np.argmax(np.diff(rp)))                 # a row with >= 2 edges
+    b, e = int(rp[row]), int(rp[row + 1])
+    assert e - b >= 2
+    shuffled = col.copy()
+    shuffled[b:e] = shuffled[b:e][::-1]
+    st, msg = _init_status(net, col=shuffled.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    assert st == 2 and "ascending" in msg
+    repeated = col.copy()
+    repeated[b + 1] = repeated[b]
+    st, msg = _init_status(net, col=repeated.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    assert st == 2 and "ascending" in msg
+
+
 def test_validation_rejects_bad_dense_and_inputs():
     n = 3
     w = np.ones((n, n), np.float32)
