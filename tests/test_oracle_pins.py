@@ -533,3 +533,118 @@ def test_instrumented_operation_counts(tmp_path):
     assert rhs_tr == 21 and rhs_ops == 224
     assert pair_tr == 1 and pair_ops == 9
     assert abs((rhs_ops - rhs_tr) + 31 * rhs_tr - 859) < 20
+
+
+# ---------------------------------------------------------------------------
+# Cell-model rate functions, read out of the oracle's right-hand side through
+# clamped states and compared with values evaluated by hand from the
+# published model's equations (tests/golden/cell_rates.txt). Each gate's
+# derivative at gate value 0 and 1 gives its two rates (alpha, -beta) or its
+# steady state and time constant; the Na activation is read from the soma or
+# axon voltage derivative with every other conductance set to zero.
+_SV = dict(VD=0, CA=1, R=2, S=3, Q=4, VS=5, K=6, L=7, H=8, N=9, X=10, VA=11, HA=12, XA=13)
+_GNA_S, _GNA_A, _GCAH, _VNA, _VCA = 5, 9, 0, 15, 17
+
+
+def _golden_rates():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "cell_rates.txt")):
+        if line.strip() and not line.startswith("#"):
+            name, arg, val = line.split()
+            rows.append((name, float(arg), float(val)))
+    return rows
+
+
+def _gate_pair(o, var, vvar, v, params=None):
+    """dy/dt of gate `var` at y = 0 and y = 1 with voltage `vvar` = v."""
+    x = o.rest().astype(np.float64)
+    x[_SV[vvar]] = v
+    out = []
+    for y in (0.0, 1.0):
+        x[_SV[var]] = y
+        out.append(float(o.rhs(x, params=params)[_SV[var]]))
+    return out
+
+
+def _steady_tau(o, var, vvar, v):
+    d0, d1 = _gate_pair(o, var, vvar, v)       # y_inf / tau, (y_inf - 1) / tau
+    tau = 1.0 / (d0 - d1)
+    return d0 * tau, tau
+
+
+def _na_activation(o, vvar, v):
+    from paper_1612_01501_amd.inputs import DEFAULT_PARAMS
+    p = np.zeros(20)
+    p[13], p[14] = DEFAULT_PARAMS[13], DEFAULT_PARAMS[14]   # area ratios (no coupling: g_int = 0)
+    p[_VNA] = 55.0
+    g, vi, hi = (_GNA_S, "VS", "H") if vvar == "VS" else (_GNA_A, "VA", "HA")
+    p[g] = 1.0
+    x = o.rest().astype(np.float64)
+    x[_SV[vi]] = v
+    x[_SV[hi]] = 1.0
+    dv = float(o.rhs(x, params=p)[_SV[vi]])     # -m_inf^3 (V - V_Na)
+    return np.cbrt(dv / (55.0 - v))
+
+
+def _read_rate(o, name, a):
+    if name in ("alpha_r", "beta_r"):
+        d0, d1 = _gate_pair(o, "R", "VD", a)
+        return 5.0 * d0 if name == "alpha_r" else -5.0 * d1
+    if name in ("alpha_x", "beta_x"):
+        d0, d1 = _gate_pair(o, "X", "VS", a)
+        return d0 if name == "alpha_x" else -d1
+    if name in ("alpha_s", "beta_s"):
+        x = o.rest().astype(np.float64)
+        x[_SV["CA"]] = a
+        x[_SV["S"]] = 0.0 if name == "alpha_s" else 1.0
+        d = float(o.rhs(x)[_SV["S"]])
+        return d if name == "alpha_s" else -d
+    if name in ("ca_decay", "ca_inflow"):
+        p = np.zeros(20)
+        p[13], p[14] = 0.25, 0.15
+        x = o.rest().astype(np.float64)
+        if name == "ca_decay":
+            x[_SV["CA"]] = a
+        else:
+            p[_GCAH], p[_VCA] = 1.0, 120.0
+            x[_SV["CA"]], x[_SV["R"]], x[_SV["VD"]] = 0.0, 1.0, a
+        return float(o.rhs(x, params=p)[_SV["CA"]])
+    if name == "m_inf":
+        return _na_activation(o, "VS", a)
+    gates = {"q": ("Q", "VD"), "k": ("K", "VS"), "l": ("L", "VS"), "h": ("H", "VS"),
+             "n": ("N", "VS"), "ha": ("HA", "VA")}
+    kind, g = ("tau", name[4:]) if name.startswith("tau_") else ("inf", name[:-4])
+    inf, tau = _steady_tau(o, *gates[g], a)
+    return inf if kind == "inf" else tau
+
+
+def test_cell_rates_match_published_equations(o64):
+    rows = _golden_rates()
+    assert len(rows) >= 80
+    for name, a, val in rows:
+        got = _read_rate(o64, name, a)
+        assert got == pytest.approx(val, rel=2e-12, abs=1e-15), (name, a, got, val)
+
+
+def test_axon_gates_share_the_soma_rate_forms(o64):
+    """The axon's Na activation and K gate rates are the soma's functions of
+    the axon voltage (same golden values)."""
+    rows = {(n, a): v for n, a, v in _golden_rates()}
+    for v in (-70.0, -45.0, -10.0, 20.0):
+        assert _na_activation(o64, "VA", v) == pytest.approx(rows[("m_inf", v)], rel=2e-12)
+        d0, d1 = _gate_pair(o64, "XA", "VA", v)
+        assert d0 == pytest.approx(rows[("alpha_x", v)], rel=2e-12)
+        assert -d1 == pytest.approx(rows[("beta_x", v)], rel=2e-12)
+
+
+def test_cell_rate_pins_catch_planted_slips(o64, monkeypatch):
+    """A plausible slip in a rate constant (planted in the values the test
+    reads, on the CPU) fails the golden comparison."""
+    rows = _golden_rates()
+    real = _read_rate
+    for target in ("tau_h", "beta_x", "tau_q", "alpha_r"):
+        def slipped(o, name, a, _t=target):
+            v = real(o, name, a)
+            return v * 1.001 if name == _t else v
+        bad = [(n, a, v) for n, a, v in rows if slipped(o64, n, a) != pytest.approx(v, rel=2e-12, abs=1e-15)]
+        assert bad and all(n == target for n, _, _ in bad), target
