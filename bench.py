@@ -8,18 +8,20 @@ shaped like the paper's networks, and resident in device memory before the
 timed region starts.
 
 Workloads (--workload):
+  c4       the default: 65,536 cells, symmetric ER graph of mean degree 1,000
+           (CSR, 65.5 M edges, g = 3.84e-3), bias N(0, 0.5), pulse, jitter;
+           the plain step timed over --steps steps (every one a replay of a
+           HIP graph captured at init), then the trained MLP surrogate
+           against the plain method over 10,000 dt (2,500 macro steps of
+           4 dt, drift check 1/64 cells, theta 0.5 mV) with the two ablations
+           (held gap without MLP; MLP without fallback), and the same under
+           the paper's 25 ms validation pulse where cells fire
   csr4096  three 4,096-cell symmetric Erdos-Renyi CSR networks at 1 %, 10 %
            and 50 % density (g = 0.04, bias N(0, 0.5), 6 uA/cm^2 pulse at
-           20-25 ms), stepped together: the default, 20,000 steps
+           20-25 ms), stepped together, 20,000 steps
   uni96    96 cells all-to-all (g = 0.04), 2,000 steps
   uni16k   16,384 cells all-to-all (g = 0.04*96/N), 4,000 steps
-  surr65k  65,536 cells, symmetric ER graph of mean degree 1,000 (CSR,
-           g = 3.84e-3), bias, pulse, jitter: the plain method for 10,000
-           steps against the trained MLP surrogate for 2,500 macro steps of
-           4 dt (drift check 1/64 cells, theta 0.5 mV), with the two
-           ablations (held gap without MLP; MLP without fallback)
-  csr65k   the surr65k network stepped by the plain method only, 2,000
-           steps (the large-CSR, column-blocked gap path)
+  csr65k   the c4 network stepped by the plain method only, 2,000 steps
   ngj16m   2^24 uncoupled cells: the compartment update alone, 1.95 GB of
            state per step (beyond the 256 MB cache), 200 steps
   valid120k the paper's validation run: 96 cells, 25 ms pulse, 120,000 steps
@@ -68,23 +70,43 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """Bytes per launch, or None when no counters were taken for this
-    workload or the kernel sources changed since."""
+def traffic_key(workload, kernel, paths, info):
+    """What the counters must have been taken on to count for this run: the
+    workload, the step kernel(s), the gap paths and the wide workgroup size."""
+    return "|".join([workload, kernel, ",".join(sorted(set(p or "csr_gather" for p in paths))),
+                     f"wide{info.get('wide_threads', 0)}"])
+
+
+def measured_traffic(key):
+    """Measured HBM bytes per launch for exactly this configuration (see
+    traffic_key), or None when no counters were taken for it or the kernel
+    sources changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            entry = json.load(fh).get(workload)
+            entry = json.load(fh).get(key)
     except (OSError, ValueError):
         return None
     if not entry or entry.get("kernel_sources_sha256") != kernel_source_hash():
         return None
     return entry["bytes_per_launch"]
+
+
+def tuned_config(info, sim, nets):
+    """What the library runs for these networks, as chosen at init."""
+    return {"tiles": info["n_tiles"], "tiles_wide": info["n_tiles_wide"], "wide_threads": info["wide_threads"],
+            "csr_bitmap_networks": info["n_bitmap"], "csr_blocked_networks": info["n_blocked"],
+            "lanes_per_row": info["lanes_per_row"], "tile_rows": info["tile_rows"],
+            "gap_paths": sorted(set(sim.gap_path(k)[0] for k in range(len(nets)))),
+            "step_kernel": step_kernel_name(info, nets),
+            "tuned_networks": info["tuned"], "tune_cached_networks": info["tune_cached"]}
+
+
 WORKLOADS = {
+    "c4": dict(steps=2000, warmup=100),
     "csr4096": dict(steps=20000, warmup=1000),
     "uni96": dict(steps=2000, warmup=200),
     "uni16k": dict(steps=4000, warmup=100),
     "batch256": dict(steps=10000, warmup=200),
-    "surr65k": dict(steps=10000, warmup=100),
     "csr65k": dict(steps=2000, warmup=100),
     "ngj16m": dict(steps=200, warmup=10),
     "valid120k": dict(steps=120000, warmup=1000),
@@ -105,11 +127,12 @@ def build_workload(name):
         nets = I.config3()
         desc = ("256 networks, N_k ~ U{64..2048}, density ~ U{5,25,100 %} (100 % all-to-all, else ER CSR), "
                 "g_k ~ U[0.01,0.08] mS/cm^2, pulse A_k ~ U[2,10] uA/cm^2 steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms")
-    elif name == "surr65k":
+    elif name == "c4":
         nets = [I.config4()]
-        desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR), g=3.84e-3 mS/cm^2, "
-                "bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms; "
-                "MLP 16-128-128-16 BF16 on MFMA, 4 dt per macro step")
+        desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR, 65.5 M edges), g=3.84e-3 mS/cm^2, "
+                "bias N(0,0.5), 6 uA/cm^2 pulse steps [400,500), +-1 mV jitter, FP32, dt=0.05 ms; plain step "
+                "throughput, then the MLP surrogate (16-128-128-16, BF16 on MFMA, 4 dt per macro step, drift "
+                "check 1/64 cells) against the plain method over 10,000 dt")
     elif name == "csr65k":
         nets = [I.config4()]
         desc = ("65,536 cells, symmetric ER gap graph of mean degree 1,000 (CSR), g=3.84e-3 mS/cm^2, "
@@ -378,88 +401,220 @@ def run_validation(nets, desc, steps, warmup, args, torch, infoli):
     print(json.dumps(out), flush=True)
 
 
-def run_surrogate(nets, desc, steps, warmup, args, torch, infoli):
-    """Plain run vs trained surrogate on the same network and initial state."""
-    net = nets[0]
-    x0 = infoli.initial_state(net)
-    V = [I.IDX_VD, I.IDX_VS, I.IDX_VA]
-    macro = steps // 4
-    samples = 25
-    every = macro // samples
-    # plain method
-    plain = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
-    info = plain.info()
-    paths = [plain.gap_path(0)[0]]
-    ref, t_plain = [], 0.0
-    for _ in range(samples):
-        plain.step(4 * every)
-        plain.sync()
-        t_plain += plain.last_step_ms()
-        ref.append(plain.read_state(0)[V])
-    ca, ta = plain.read_spikes(0)
-    plain.close()
-    # training
-    sim = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
-    t0 = time.perf_counter()
-    rep, hist = sim.surrogate_train(I.mlp_init_params(5000))
-    train_wall = time.perf_counter() - t0
-    params, norm = sim.surrogate_get()
-    sim.close()
+def graph_chunk_for(steps, cap=100):
+    """The largest even number of steps <= cap that divides `steps` (so every
+    timed step is a graph replay), else 2."""
+    for c in range(min(cap, steps) - (min(cap, steps) % 2), 1, -2):
+        if steps % c == 0:
+            return c
+    return 2
 
-    def surrogate_run(**drift):
-        s = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
-        s.surrogate_set(params, norm)
-        sq, n, ms, checked, flagged, plain_cells = 0.0, 0, 0.0, 0, 0, 0
-        for k in range(samples):
-            r = s.step_surrogate(every, **drift)
+
+def match_spikes(ca, ta, cb, tb, cap):
+    """Per cell, greedy nearest-time matching of the kept spike times of run b
+    to those of run a (each used once). Returns (abs time differences of the
+    matched pairs, spikes of a left unmatched, spikes of b left unmatched)."""
+    diffs, un_a, un_b = [], 0, 0
+    for i in np.nonzero((ca > 0) | (cb > 0))[0]:
+        a = np.sort(ta[i, :min(int(ca[i]), cap)].astype(np.float64))
+        b = list(np.sort(tb[i, :min(int(cb[i]), cap)].astype(np.float64)))
+        for t in a:
+            if not b:
+                un_a += 1
+                continue
+            k = int(np.argmin([abs(t - u) for u in b]))
+            diffs.append(abs(t - b.pop(k)))
+        un_b += len(b)
+        un_a += max(0, int(ca[i]) - cap)
+        un_b += max(0, int(cb[i]) - cap)
+    return np.array(diffs), un_a, un_b
+
+
+def stability(nets):
+    """dt * lambda_max / C_m of the gap coupling linearised at synchrony
+    (d/d(dV) of dV*(0.8*exp(-dV^2/100) + 0.2) is 1 at dV = 0, so the coupling
+    is the weighted graph Laplacian), bounded by Gershgorin's 2*max_i sum_j
+    w_ij; explicit Euler is stable for values <= 2 (C_m = 1 uF/cm^2)."""
+    vals = []
+    for n in nets:
+        if n.conn == "uniform":
+            row = (n.n - 1) * n.g
+        elif n.conn == "csr":
+            deg = np.diff(np.asarray(n.row_ptr))
+            row = float(np.max(deg)) * n.g if n.w_csr is None else float(
+                np.max(np.add.reduceat(np.asarray(n.w_csr, np.float64), np.asarray(n.row_ptr[:-1])))) if len(n.col) else 0.0
+        elif n.conn == "dense":
+            row = float(np.max(np.asarray(n.w_dense, np.float64).sum(axis=1)))
+        else:
+            row = 0.0
+        vals.append(n.dt * 2.0 * row)
+    vals = np.array(vals)
+    return {"dt_lambda_max_gershgorin": float(vals.max()), "networks": len(vals),
+            "networks_above_2": int((vals > 2.0).sum()), "euler_stable": bool((vals <= 2.0).all())}
+
+
+def time_plain(sim, steps, warmup, torch):
+    """Wall time of exactly `steps` steps between device synchronisations
+    after `warmup` untimed ones, and the device time of the same call (HIP
+    events on the context's stream)."""
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    return wall, sim.last_step_ms()
+
+
+SURR_DT = 10000          # the surrogate comparison's length in dt, whatever --steps says
+SURR_SAMPLES = 25
+
+
+def surrogate_leg(net, x0, sim, torch, infoli, log):
+    """Plain method against the trained MLP surrogate on the same network
+    and initial state for SURR_DT time steps (SURR_DT / 4 macro steps), with
+    the two ablations (held gap without MLP; MLP without fallback). `sim` is
+    the plain context, rewound to x0 at step 0 for each run."""
+    V = [I.IDX_VD, I.IDX_VS, I.IDX_VA]
+    every = SURR_DT // 4 // SURR_SAMPLES            # macro steps per sample
+    cap = sim.spike_cap
+    sim.write_state(0, x0, 0)
+    sim.clear_spikes()
+    ref, t_plain = [], 0.0
+    for _ in range(SURR_SAMPLES):
+        sim.step(4 * every)
+        sim.sync()
+        t_plain += sim.last_step_ms()
+        ref.append(sim.read_state(0)[V])
+    ca, ta = sim.read_spikes(0)
+    log("surrogate leg: plain reference done")
+    t0 = time.perf_counter()
+    rep, _ = sim.surrogate_train(I.mlp_init_params(5000))
+    train_wall = time.perf_counter() - t0
+    log(f"surrogate leg: trained ({train_wall:.1f} s)")
+
+    def run(**drift):
+        sim.write_state(0, x0, 0)
+        sim.clear_spikes()
+        sq, n, ms, checked, flagged, plain_cells, guarded = 0.0, 0, 0.0, 0, 0, 0, 0
+        for k in range(SURR_SAMPLES):
+            r = sim.step_surrogate(every, **drift)
             ms += r["ms"]
             checked += r["checked"]
             flagged += r["flagged"]
             plain_cells += r["plain_cell_macro_steps"]
-            d = (s.read_state(0)[V] - ref[k]).astype(np.float64)
+            guarded += r["guarded"]
+            d = (sim.read_state(0)[V] - ref[k]).astype(np.float64)
             sq += float((d * d).sum())
             n += d.size
-        cb, tb = s.read_spikes(0)
-        s.close()
-        worst = 0.0
-        for i in np.nonzero((ca > 0) & (cb > 0))[0]:
-            m = min(ca[i], cb[i], ta.shape[1])
-            worst = max(worst, float(np.max(np.abs(np.sort(ta[i, :m]) - np.sort(tb[i, :m])))))
+        cb, tb = sim.read_spikes(0)
+        diffs, un_a, un_b = match_spikes(ca, ta, cb, tb, cap)
         return {"ms": ms, "rmse_mv": float(np.sqrt(sq / n)), "spikes": int(cb.sum()),
-                "spike_count_max_diff": int(np.max(np.abs(ca.astype(np.int64) - cb))),
-                "spike_time_err_ms": worst, "checked": checked, "flagged": flagged,
+                "spike_time_err_ms_max": float(diffs.max()) if diffs.size else 0.0,
+                "spike_time_err_ms_mean": float(diffs.mean()) if diffs.size else 0.0,
+                "spikes_unmatched_plain": un_a, "spikes_unmatched_surrogate": un_b,
+                "checked": checked, "flagged": flagged, "guarded": guarded,
                 "plain_cell_macro_steps": plain_cells}
 
-    surr = surrogate_run()
-    hold = surrogate_run(mode="plain_hold")
-    nofb = surrogate_run(sample_every=0, v_max=1e30, z_max=0.0)
-    cells = net.n
-    total_steps = 4 * every * samples
-    out = {
-        "metric": "surrogate vs plain speedup at voltage RMSE <= 1 mV (cell-steps/s of the surrogate path)",
-        "value": cells * total_steps / (surr["ms"] * 1e-3),
-        "unit": "cell-steps/s",
-        "n_gpus": 1, "steps": total_steps, "warmup": 0,
-        "ms_per_step": surr["ms"] / total_steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
-        "data": "synthetic",
-        "config": {"workload": f"surr65k: {desc}", "cells": cells, "gap_pairs_per_step": net.pairs_per_step(),
-                   "tiles": info["n_tiles"], "tiles_wide": info["n_tiles_wide"], "wide_threads": info["wide_threads"],
-                   "csr_bitmap_networks": info["n_bitmap"], "csr_blocked_networks": info["n_blocked"],
-                   "lanes_per_row": info["lanes_per_row"]},
-        "plain_cell_steps_per_s": cells * total_steps / (t_plain * 1e-3),
-        "plain_ms_per_step": t_plain / total_steps,
+    surr = run()
+    hold = run(mode="plain_hold")
+    nofb = run(sample_every=0, v_max=1e30, z_max=0.0, ca_max=1e30)
+    log("surrogate leg: surrogate and ablations done")
+    return {
+        "dt_steps": SURR_DT, "macro_steps": SURR_DT // 4,
+        "plain_ms": t_plain, "surrogate_ms": surr["ms"],
         "speedup": t_plain / surr["ms"],
-        "rmse_mv": surr["rmse_mv"], "spike_time_err_ms": surr["spike_time_err_ms"],
+        "rmse_mv": surr["rmse_mv"],
+        "spike_time_err_ms": surr["spike_time_err_ms_max"],
         "spikes_plain": int(ca.sum()), "spikes_surrogate": surr["spikes"],
-        "drift": {k: surr[k] for k in ("checked", "flagged", "plain_cell_macro_steps")},
-        "ablation_held_gap_no_mlp": {"speedup": t_plain / hold["ms"], "rmse_mv": hold["rmse_mv"]},
-        "ablation_mlp_no_fallback": {"speedup": t_plain / nofb["ms"], "rmse_mv": nofb["rmse_mv"],
-                                     "spike_time_err_ms": nofb["spike_time_err_ms"]},
+        "surrogate": surr,
+        "ablation_held_gap_no_mlp": {"speedup": t_plain / hold["ms"], **hold},
+        "ablation_mlp_no_fallback": {"speedup": t_plain / nofb["ms"], **nofb},
+        "mlp_gain_over_held_gap": hold["ms"] / surr["ms"],
         "training": {**rep, "wall_s": train_wall},
-        "roofline": roofline(nets, t_plain * 1e-3 / total_steps, step_kernel_name(info, nets), paths),
     }
-    out["roofline"]["traffic"] = measured_traffic(args.workload)
+
+
+def spiking_accuracy_leg(params, norm, infoli, log, steps=2000):
+    """The surrogate where cells fire: the 65,536-cell network under the
+    paper's validation pulse (Section 3: about 500 steps, here 6 uA/cm^2
+    during steps [400, 900)), plain method against the surrogate for `steps`
+    time steps; RMSE at every 100 dt and spike times matched per cell."""
+    net = I.config4()
+    net.pulses = [I.Pulse(400, 900, 6.0)]
+    x0 = infoli.initial_state(net)
+    sim = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
+    V = [I.IDX_VD, I.IDX_VS, I.IDX_VA]
+    every, ref = 25, []
+    for _ in range(steps // 100):
+        sim.step(4 * every)
+        ref.append(sim.read_state(0)[V])
+    ca, ta = sim.read_spikes(0)
+    sim.write_state(0, x0, 0)
+    sim.clear_spikes()
+    sim.surrogate_set(params, norm)
+    sq, n, plain_cells, guarded = 0.0, 0, 0, 0
+    for k in range(steps // 100):
+        r = sim.step_surrogate(every)
+        plain_cells += r["plain_cell_macro_steps"]
+        guarded += r["guarded"]
+        d = (sim.read_state(0)[V] - ref[k]).astype(np.float64)
+        sq += float((d * d).sum())
+        n += d.size
+    cb, tb = sim.read_spikes(0)
+    diffs, un_a, un_b = match_spikes(ca, ta, cb, tb, sim.spike_cap)
+    sim.close()
+    log("spiking accuracy leg done")
+    return {"pulse": "6 uA/cm^2, steps [400, 900)", "dt_steps": steps,
+            "rmse_mv": float(np.sqrt(sq / n)), "spikes_plain": int(ca.sum()), "spikes_surrogate": int(cb.sum()),
+            "cells_spiking_plain": int((ca > 0).sum()),
+            "spike_time_err_ms_max": float(diffs.max()) if diffs.size else None,
+            "spike_time_err_ms_mean": float(diffs.mean()) if diffs.size else None,
+            "spikes_matched": int(diffs.size), "spikes_unmatched_plain": un_a,
+            "spikes_unmatched_surrogate": un_b, "plain_cell_macro_steps": plain_cells, "guarded": guarded}
+
+
+def run_c4(nets, desc, steps, warmup, args, torch, infoli):
+    """The 65,536-cell network of mean degree 1,000: the plain step timed
+    over exactly `steps` steps, every one a graph replay (graphs captured at
+    init); then the surrogate comparison at its full length."""
+    net = nets[0]
+    log = (lambda m: print(m, file=sys.stderr, flush=True))
+    x0 = infoli.initial_state(net)
+    chunk = graph_chunk_for(steps)
+    stream = torch.cuda.current_stream().cuda_stream
+    sim = infoli.Simulator(net, init_states=[x0], stream=stream, step_mode="graph", graph_chunk=chunk)
+    info = sim.info()
+    paths = [sim.gap_path(0)[0]]
+    log(f"c4: context ready ({info['n_tiles']} tiles, graph chunk {chunk})")
+    wall, dev_ms = time_plain(sim, steps, warmup, torch)
+    launch_s = dev_ms * 1e-3 / steps
+    kernel = step_kernel_name(info, nets)
+    cells, pairs = net.n, net.pairs_per_step()
+    out = {
+        "metric": "cell-steps/sec and gap pairs/sec at 1 MI355X; surrogate vs plain speedup at 1 mV RMSE",
+        "value": cells * steps / wall,
+        "unit": "cell-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c4: {desc}", "cells": cells, "gap_pairs_per_step": pairs,
+                   "step_mode": "graph", "graph_chunk": chunk, **tuned_config(info, sim, nets)},
+        "gap_pairs_per_s": pairs * steps / wall,
+        "device_ms_per_step": dev_ms / steps,
+        "roofline": roofline(nets, launch_s, kernel, paths),
+        "stability": stability(nets),
+    }
+    out["roofline"]["traffic"] = measured_traffic(traffic_key("c4", kernel, paths, info))
+    log(f"c4: plain {dev_ms / steps * 1e3:.2f} us/step")
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(net, x0, sim, torch, infoli, log)
+        params, norm = sim.surrogate_get()
+        out["surrogate"]["spiking_validation_pulse"] = spiking_accuracy_leg(params, norm, infoli, log)
+    sim.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)
     print(json.dumps(out), flush=True)
@@ -616,10 +771,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="csr4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="auto", choices=["graph", "launch", "auto", "persistent"])
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="c4: the plain step only")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--rt-sweep", action="store_true",
                     help="only run the real-time size sweep (largest network per use case within the budget)")
@@ -650,27 +806,26 @@ def main():
         paper_batches(args, torch, infoli)
         return
     nets, desc = build_workload(args.workload)
-    if args.workload == "surr65k":
-        run_surrogate(nets, desc, steps, warmup, args, torch, infoli)
+    if args.workload == "c4":
+        run_c4(nets, desc, steps, warmup, args, torch, infoli)
         return
     if args.workload == "valid120k":
         run_validation(nets, desc, steps, warmup, args, torch, infoli)
         return
     x0s = [infoli.initial_state(n) for n in nets]
     stream = torch.cuda.current_stream().cuda_stream
-    sim = infoli.Simulator(nets, init_states=x0s, stream=stream, step_mode=args.mode,
-                           graph_chunk=args.graph_chunk)
+    mode = args.mode
+    chunk = args.graph_chunk
+    if mode == "auto" and not (len(nets) == 1 and nets[0].n <= 1024):
+        # every timed step a graph replay: chunks that divide the step count,
+        # captured at init (a lone network of <= 1,024 cells stays in the
+        # library's automatic choice, which times the persistent kernel)
+        mode, chunk = "graph", graph_chunk_for(steps, args.graph_chunk)
+    sim = infoli.Simulator(nets, init_states=x0s, stream=stream, step_mode=mode, graph_chunk=chunk)
     info = sim.info()
     paths = [sim.gap_path(k)[0] for k in range(len(nets))]
-    sim.step(warmup)
-    sim.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sim.sync()
-    dev_ms = sim.last_step_ms()
+    wall, dev_ms = time_plain(sim, steps, warmup, torch)
+    tuned = tuned_config(info, sim, nets)
     sim.close()
 
     cells = sum(n.n for n in nets)
@@ -691,15 +846,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "cells": cells,
-                   "gap_pairs_per_step": pairs, "step_mode": args.mode,
-                   "tiles": info["n_tiles"], "tiles_wide": info["n_tiles_wide"], "wide_threads": info["wide_threads"],
-                   "csr_bitmap_networks": info["n_bitmap"], "csr_blocked_networks": info["n_blocked"],
-                   "lanes_per_row": info["lanes_per_row"]},
+                   "gap_pairs_per_step": pairs, "step_mode": mode, "graph_chunk": chunk, **tuned},
         "gap_pairs_per_s": pairs * steps / wall,
         "device_ms_per_step": dev_ms / steps,
         "roofline": roofline(nets, launch_s, step_kernel_name(info, nets), paths),
+        "stability": stability(nets),
     }
-    out["roofline"]["traffic"] = measured_traffic(args.workload)
+    out["roofline"]["traffic"] = measured_traffic(traffic_key(args.workload, step_kernel_name(info, nets),
+                                                              paths, info))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)
     print(json.dumps(out), flush=True)

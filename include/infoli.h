@@ -142,7 +142,9 @@ typedef struct infoli_network_spec {
 typedef enum infoli_step_mode {
     INFOLI_MODE_AUTO = 0,       /* library choice                                          */
     INFOLI_MODE_LAUNCH = 1,     /* one kernel launch per step                              */
-    INFOLI_MODE_GRAPH = 2,      /* chunks of steps captured in a HIP graph and replayed    */
+    INFOLI_MODE_GRAPH = 2,      /* chunks of graph_chunk steps captured in a HIP graph (at
+                                   init) and replayed; a remainder shorter than a chunk is
+                                   launched step by step                                  */
     INFOLI_MODE_PERSISTENT = 3  /* one launch for many steps; workgroup barriers only,
                                    for networks that fit one workgroup each               */
 } infoli_step_mode;

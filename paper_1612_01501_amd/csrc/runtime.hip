@@ -1421,7 +1421,15 @@ infoli_status infoli_batch_init(const infoli_network_spec* specs, int32_t n_inst
         g_thread_error = "host allocation failed";
         return INFOLI_E_OUT_OF_MEMORY;
     }
-    infoli_status st = guarded(nullptr, [&] { build_context(c, specs, n_instances, opt); });
+    infoli_status st = guarded(nullptr, [&] {
+        build_context(c, specs, n_instances, opt);
+        // GRAPH mode: both captured chunks (by starting buffer) are built and
+        // instantiated here, so no step call pays for capture
+        if (c->opt.step_mode == INFOLI_MODE_GRAPH) {
+            get_graph(c, 0);
+            get_graph(c, 1);
+        }
+    });
     if (st != INFOLI_OK) {
         c->release();
         delete c;

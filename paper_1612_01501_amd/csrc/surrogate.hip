@@ -17,9 +17,24 @@ T* dev_alloc(std::vector<void*>& owned, size_t n) {
     return static_cast<T*>(p);
 }
 
+// Device buffers and events of one call. On every exit, normal or by a
+// failure, the stream the call queues on (nullptr: the null stream) is
+// drained before anything is released, so no queued kernel or copy still
+// uses a buffer when it is freed.
 struct Scoped {
+    hipStream_t stream = nullptr;
     std::vector<void*> owned;
+    std::vector<hipEvent_t> events;
+    explicit Scoped(hipStream_t st = nullptr) : stream(st) {}
+    hipEvent_t event() {
+        hipEvent_t e = nullptr;
+        HIPX(hipEventCreate(&e));
+        events.push_back(e);
+        return e;
+    }
     ~Scoped() {
+        (void)hipStreamSynchronize(stream);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (void* p : owned) (void)hipFree(p);
     }
 };
@@ -202,14 +217,11 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
         ensure_surrogate_buffers(ctx);
         SurrogateState& s = ctx->surr;
         hipStream_t st = ctx->stream;
-        Scoped tmp;
+        Scoped tmp(st);
         float* xd = dev_alloc<float>(tmp.owned, (size_t)n_data * 16);
         float* td = dev_alloc<float>(tmp.owned, (size_t)n_data * 16);
         double* stats = dev_alloc<double>(tmp.owned, 64);
-        hipEvent_t e0, e1, e2;
-        HIPX(hipEventCreate(&e0));
-        HIPX(hipEventCreate(&e1));
-        HIPX(hipEventCreate(&e2));
+        hipEvent_t e0 = tmp.event(), e1 = tmp.event(), e2 = tmp.event();
         HIPX(hipEventRecord(e0, st));
 
         // 1. transitions of the plain method under random currents
@@ -241,9 +253,11 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
         hipLaunchKernelGGL(k_feature_stats, dim3(16), dim3(256), 0, st, xd, n_data, stats);
         hipLaunchKernelGGL(k_feature_stats, dim3(16), dim3(256), 0, st, td, n_data, stats + 32);
         HIPX(hipGetLastError());
-        double hs[64];
-        HIPX(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+        // the statistics kernels are done before the blocking copy reads them
+        // into heap memory (no copy is left in flight into a stack frame)
         HIPX(hipStreamSynchronize(st));
+        std::vector<double> hs(64);
+        HIPX(hipMemcpy(hs.data(), stats, sizeof(double) * 64, hipMemcpyDeviceToHost));
         float nrm[64];
         for (int f = 0; f < 16; ++f) {
             const double sd_in = hs[2 * f + 1], sd_out = hs[32 + 2 * f + 1];
@@ -304,9 +318,6 @@ infoli_status infoli_surrogate_train(infoli_ctx* ctx, const infoli_train_cfg* cf
             HIPX(hipEventElapsedTime(&rep->data_ms, e0, e1));
             HIPX(hipEventElapsedTime(&rep->train_ms, e1, e2));
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        (void)hipEventDestroy(e2);
         s.ready = true;
     });
 }

@@ -129,3 +129,45 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_graph_chunk_divides_the_timed_steps():
+    assert bench.graph_chunk_for(20) == 20
+    assert bench.graph_chunk_for(2000) == 100
+    assert bench.graph_chunk_for(1000) == 100
+    assert bench.graph_chunk_for(30) == 30
+    assert bench.graph_chunk_for(35) == 2           # no even divisor: pairs of steps
+    for k in (20, 2000, 4000, 10000, 120000, 42):
+        c = bench.graph_chunk_for(k)
+        assert c % 2 == 0 and c >= 2 and (k % c == 0 or c == 2)
+
+
+def test_spike_matching_by_nearest_time():
+    cap = 4
+    ca = np.array([2, 0, 1], np.int32)
+    ta = np.array([[10.0, 20.0, 0, 0], [0, 0, 0, 0], [5.0, 0, 0, 0]], np.float32)
+    cb = np.array([2, 1, 0], np.int32)
+    tb = np.array([[20.05, 9.9, 0, 0], [7.0, 0, 0, 0], [0, 0, 0, 0]], np.float32)
+    d, un_a, un_b = bench.match_spikes(ca, ta, cb, tb, cap)
+    assert sorted(np.round(d, 4)) == [0.05, 0.1]
+    assert un_a == 1 and un_b == 1
+
+
+def test_stability_is_gershgorin_of_the_laplacian():
+    rp, col = _csr(3, [(0, 1), (0, 2), (1, 0), (2, 0)])
+    net = I.Network(n=3, conn="csr", g=0.5, row_ptr=rp, col=col)
+    s = bench.stability([net])
+    assert s["dt_lambda_max_gershgorin"] == pytest.approx(0.05 * 2 * 2 * 0.5)
+    uni = I.Network(n=96, conn="uniform", g=0.04)
+    s = bench.stability([uni, net])
+    assert s["dt_lambda_max_gershgorin"] == pytest.approx(0.05 * 2 * 95 * 0.04)
+    assert s["euler_stable"] and s["networks_above_2"] == 0
+    # the 50 % network of 4,096 cells at g = 0.04 is far above the limit
+    big = I.Network(n=4, conn="uniform", g=0.04 * 2048 / 3)
+    assert not bench.stability([big])["euler_stable"]
+
+
+def test_traffic_key_names_the_configuration():
+    k = bench.traffic_key("c4", "infoli::k_step<1024, 2>", ["csr_chunked"], {"wide_threads": 512})
+    assert k == "c4|infoli::k_step<1024, 2>|csr_chunked|wide512"
+    assert bench.measured_traffic(k + "x") is None
