@@ -189,8 +189,9 @@ def algorithmic_bytes(nets, paths=None):
     <= 65,536 cells, else int32) plus its fp32 weight when the network has
     per-edge weights, and per CSR row its row pointer (8 B); for a network on
     the coupling bitmap instead, one bit per (row, column) pair in rows of
-    whole 32-bit words. Gathered neighbour voltages are cache hits and not
-    counted."""
+    whole 32-bit words; for a network on the chunk stream, also one byte per
+    eight edges (the row tag of each chunk; padding not counted). Gathered
+    neighbour voltages are cache hits and not counted."""
     col_b = 2 if all(n.n <= 65536 for n in nets if n.conn == "csr") else 4
     b = 0
     for k, n in enumerate(nets):
@@ -198,7 +199,10 @@ def algorithmic_bytes(nets, paths=None):
         if n.conn == "csr" and paths is not None and paths[k] == "csr_bitmap":
             b += 4 * n.n * ((n.n + 31) // 32)
         elif n.conn == "csr":
-            b += (col_b + (4 if n.w_csr is not None else 0)) * int(n.row_ptr[-1]) + 8 * n.n
+            nnz = int(n.row_ptr[-1])
+            b += (col_b + (4 if n.w_csr is not None else 0)) * nnz + 8 * n.n
+            if paths is not None and paths[k] == "csr_stream":
+                b += nnz // 8        # the one-byte row tag of each chunk of eight columns
         elif n.conn == "dense":
             b += 4 * n.n * n.n
     return b
@@ -585,7 +589,8 @@ def run_c4(nets, desc, steps, warmup, args, torch, infoli):
     x0 = infoli.initial_state(net)
     chunk = graph_chunk_for(steps)
     stream = torch.cuda.current_stream().cuda_stream
-    sim = infoli.Simulator(net, init_states=[x0], stream=stream, step_mode="graph", graph_chunk=chunk)
+    sim = infoli.Simulator(net, init_states=[x0], stream=stream, step_mode="graph", graph_chunk=chunk,
+                           csr_path=args.csr_path)
     info = sim.info()
     paths = [sim.gap_path(0)[0]]
     log(f"c4: context ready ({info['n_tiles']} tiles, graph chunk {chunk})")
@@ -774,6 +779,8 @@ def main():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="auto", choices=["graph", "launch", "auto", "persistent"])
     ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--csr-path", type=int, default=0,
+                    help="force a CSR gap path (the library's csr_path option; 0: tuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="c4: the plain step only")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -821,7 +828,8 @@ def main():
         # captured at init (a lone network of <= 1,024 cells stays in the
         # library's automatic choice, which times the persistent kernel)
         mode, chunk = "graph", graph_chunk_for(steps, args.graph_chunk)
-    sim = infoli.Simulator(nets, init_states=x0s, stream=stream, step_mode=mode, graph_chunk=chunk)
+    sim = infoli.Simulator(nets, init_states=x0s, stream=stream, step_mode=mode, graph_chunk=chunk,
+                           csr_path=args.csr_path)
     info = sim.info()
     paths = [sim.gap_path(k)[0] for k in range(len(nets))]
     wall, dev_ms = time_plain(sim, steps, warmup, torch)

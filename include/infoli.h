@@ -165,7 +165,10 @@ typedef struct infoli_options {
                                     in the wide group when wide_threads is set);
                                     3 => Vd staged in LDS by column blocks (> 8,192 cells);
                                     4 => edge gathers from 16-byte column chunks
-                                    (<= 65,536 cells); other networks keep the default   */
+                                    (<= 65,536 cells); 5 => the column blocks read as one
+                                    flat stream of chunks per tile (> 8,192 cells; needs
+                                    ~110 KB of LDS per workgroup, else
+                                    INFOLI_E_UNSUPPORTED); other networks keep the default */
     int32_t output_ring_steps;   /* 0 => off; R > 0 => every plain step also writes the axon
                                     voltage of every cell into a device ring of R steps,
                                     read out with infoli_output_copy_async                 */
@@ -295,7 +298,10 @@ infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
  *               context has <= 65,536 cells, else int32), fp32 weights if given;
  *   CSR_CHUNKED the same columns as uint16 in 16-byte chunks of eight;
  *   CSR_BITMAP  one bit per (row, column) pair; every pair is evaluated and
- *               masked by its bit (one weight g, <= 16,384 cells).
+ *               masked by its bit (one weight g, <= 16,384 cells);
+ *   CSR_STREAM  the CSR_CHUNKED columns of each column block (relative to
+ *               the block) as one contiguous run per tile, plus one byte per
+ *               chunk naming its row (Vd staged block by block).
  * (The persistent step mode walks CSR rows from the gather format.)
  * *path receives the code; *vd_blocked (either pointer may be NULL) receives
  * 1 when the network's Vd is staged in LDS one column block at a time (CSR
@@ -307,7 +313,8 @@ typedef enum infoli_gap_path {
     INFOLI_PATH_DENSE = 2,
     INFOLI_PATH_CSR_GATHER = 3,
     INFOLI_PATH_CSR_CHUNKED = 4,
-    INFOLI_PATH_CSR_BITMAP = 5
+    INFOLI_PATH_CSR_BITMAP = 5,
+    INFOLI_PATH_CSR_STREAM = 6
 } infoli_gap_path;
 infoli_status infoli_get_gap_path(const infoli_ctx *ctx, int32_t instance, int32_t *path, int32_t *vd_blocked);
 

@@ -135,6 +135,8 @@ struct infoli_ctx {
     int32_t* d_cb = nullptr;        // chunked blocks: per-row, per-block chunk starts
     uint4* d_chk = nullptr;         // chunks of eight 16-bit columns
     float* d_chkw = nullptr;        // per-edge weights in the chunk layout
+    uint8_t* d_rtag = nullptr;      // chunked blocks: per chunk, its row mod 256
+    int lds_max = 65536;            // dynamic LDS one workgroup may use (bytes)
     int blk_cols = 8192;            // blocked CSR: cells per LDS block
     float* d_w = nullptr;
     float* d_stream = nullptr;

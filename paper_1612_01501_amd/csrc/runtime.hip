@@ -179,7 +179,12 @@ void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, i
     if (ntiles == 0) return;
     const float* xin = c->state[from];
     float* xout = c->state[from ^ 1];
-    if (block == 512 && var == kVarNoW)
+    if (block == 512 && var == kVarStream)
+        hipLaunchKernelGGL((k_step<512, kVarStream>), dim3(ntiles), dim3(512), lds, st, a, xin, xout, step_arg, off);
+    else if (block == 1024 && var == kVarStream)
+        hipLaunchKernelGGL((k_step<1024, kVarStream>), dim3(ntiles), dim3(1024), lds, st, a, xin, xout, step_arg,
+                           off);
+    else if (block == 512 && var == kVarNoW)
         hipLaunchKernelGGL((k_step<512, kVarNoW>), dim3(ntiles), dim3(512), lds, st, a, xin, xout, step_arg, off);
     else if (block == 512)
         hipLaunchKernelGGL((k_step<512, kVarAll>), dim3(ntiles), dim3(512), lds, st, a, xin, xout, step_arg, off);
@@ -244,6 +249,9 @@ int group_for(const InstDesc& d) {
 }
 
 size_t lds_floats_for(const infoli_ctx* c, const InstDesc& d, int block) {
+    if (d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0)   // block, own voltages, chunk sums
+        return (size_t)std::min(d.n, c->blk_cols) + kSelfSlots +
+               (block >= 1024 ? stream_round_chunks<1024>() : stream_round_chunks<512>());
     if (d.conn == CONN_CSR && d.blocked)   // the column block, then the tile rows' own voltages
         return (size_t)std::min(d.n, c->blk_cols) + (d.cb_off >= 0 ? kSelfSlots : 0);
     if (d.conn == CONN_UNIFORM) return (size_t)std::min(d.n, kChunk) + 8 * (size_t)(block / 64);
@@ -258,12 +266,30 @@ void finalize_tiles(infoli_ctx* c) {
     std::vector<std::pair<double, Tile>> planned[2];
     size_t floats[2] = {4, 4};
     c->group_of.assign(c->n_inst, 0);
+    // the chunk stream runs in a launch of stream tiles only (its kernel
+    // variant compiles no other path): a stream network that would share its
+    // launch with other tiles, or has weights or per-cell parameters, takes
+    // the chunked column blocks instead
+    {
+        bool mixed[2] = {false, false};
+        for (int k = 0; k < c->n_inst; ++k) {
+            const InstDesc& d = c->inst[k];
+            const bool st = d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0 && !d.has_w && !d.pcell;
+            if (!st) mixed[group_for(d)] = true;
+        }
+        for (int k = 0; k < c->n_inst; ++k) {
+            InstDesc& d = c->inst[k];
+            if (d.stream && (mixed[group_for(d)] || d.has_w || d.pcell || d.cb_off < 0 || !d.blocked)) d.stream = 0;
+        }
+    }
     for (int k = 0; k < c->n_inst; ++k) {
         const InstDesc& d = c->inst[k];
         const int g = group_for(d);
         c->group_of[k] = g;
         int rows = c->rows_of[k];
-        if (d.conn == CONN_CSR && d.blocked)   // rows the column-blocked passes of this workgroup size cover
+        if (d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0)   // one owner group per row
+            rows = std::min(rows, kSelfSlots);
+        else if (d.conn == CONN_CSR && d.blocked)   // rows the column-blocked passes of this workgroup size cover
             rows = std::min(rows, kBlkPasses * std::max(1, c->grp[g].block / std::max(1, d.lanes_per_row)));
         append_tiles(planned[g], k, d.n, rows, c->deg_of[k]);
         floats[g] = std::max(floats[g], lds_floats_for(c, d, c->grp[g].block));
@@ -274,14 +300,15 @@ void finalize_tiles(infoli_ctx* c) {
         std::stable_sort(planned[g].begin(), planned[g].end(),
                          [](const auto& x, const auto& y) { return x.first > y.first; });
         tg.tiles.clear();
-        bool nogap = true, now = true;
+        bool nogap = true, now = true, stream = !planned[g].empty();
         for (const auto& pt : planned[g]) {
             tg.tiles.push_back(pt.second);
             const InstDesc& d = c->inst[pt.second.inst];
             if (d.conn != CONN_NONE || d.pcell) nogap = false;
             if (d.has_w || d.pcell) now = false;
+            if (!d.stream) stream = false;
         }
-        tg.var = nogap ? kVarNoGap : now ? kVarNoW : kVarAll;
+        tg.var = nogap ? kVarNoGap : stream && tg.block >= 512 ? kVarStream : now ? kVarNoW : kVarAll;
         if (tg.tiles.size() > (size_t)INT32_MAX / 2) fail(INFOLI_E_INVALID_ARG, "too many tiles");
         if (!tg.tiles.empty()) {
             if (tg.tiles.size() > tg.cap) {
@@ -460,6 +487,19 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
             }
         }
     }
+    // per chunk of the blocks layout, its row mod 256 (the chunk stream's row tag)
+    std::vector<uint8_t> ht((size_t)nchunks, 0);
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstDesc& d = c->inst[k];
+        if (d.cb_off < 0) continue;
+        for (int b = 0; b < d.nblk; ++b)
+            for (int i = 0; i < d.n; ++i)
+                for (int32_t x = hb[(size_t)(d.cb_off + (int64_t)b * (d.n + 1) + i)];
+                     x < hb[(size_t)(d.cb_off + (int64_t)b * (d.n + 1) + i + 1)]; ++x)
+                    ht[(size_t)(d.chkb_off + x)] = (uint8_t)(i & (kSelfSlots - 1));
+    }
+    c->d_rtag = c->alloc<uint8_t>((size_t)nchunks);
+    HIPX(hipMemcpy(c->d_rtag, ht.data(), ht.size(), hipMemcpyHostToDevice));
     c->d_chk = c->alloc<uint4>((size_t)nchunks);
     HIPX(hipMemcpy(c->d_chk, hc.data(), sizeof(uint16_t) * hc.size(), hipMemcpyHostToDevice));
     c->d_chkw = c->alloc<float>(hw.size());
@@ -478,7 +518,8 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
 // on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v11.txt).
 struct TuneChoice {
     int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS,
-                           // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers)
+                           // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers,
+                           // 4 blocked chunk stream)
     int block;             // workgroup size timed (256 or 1024; the wide group may run 512)
 };
 
@@ -486,7 +527,7 @@ std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v11.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v12.txt";
     return "";
 }
 
@@ -531,7 +572,7 @@ std::map<std::string, TuneChoice> read_tune_cache(const std::string& path,
         if (std::sscanf(bar + 1, "%d %d %d %d %d", &t.L, &t.R, &t.lds, &t.bm, &t.block) == 5 &&
             (t.block == 256 || t.block == 1024) && t.L >= 4 && t.L <= 1024 &&
             (t.L & (t.L - 1)) == 0 && t.R >= 1 && t.R <= kMaxTileRows && (t.lds == 0 || t.lds == 1) &&
-            (t.bm >= 0 && t.bm <= 3))
+            (t.bm >= 0 && t.bm <= 4))
             m[line] = t;
     }
     std::fclose(f);
@@ -559,20 +600,23 @@ void append_tune_cache(const std::string& path, const std::string& key, const Tu
 float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t, Tile* d_tmp) {
     std::vector<std::pair<double, Tile>> planned;
     size_t lds = 16;
-    int var = kVarNoW;          // the variant the step will launch these tiles with
+    int var = t.bm == 4 ? kVarStream : kVarNoW;   // the variant the step will launch these tiles with
     for (int k : ks) {
         InstDesc d = c->inst[k];
         if (d.has_w || d.pcell) var = kVarAll;
         d.lanes_per_row = t.L;
         d.vd_lds = t.lds;
         d.bitmap = t.bm == 1;
-        d.blocked = t.bm == 2;
+        d.blocked = t.bm == 2 || t.bm == 4;
+        d.stream = t.bm == 4;
         d.chunked = t.bm == 3;
         HIPX(hipMemcpy(c->d_inst + k, &d, sizeof(d), hipMemcpyHostToDevice));
         append_tiles(planned, k, d.n, t.R, 0.0);
         if (t.bm == 1) lds = std::max(lds, ((bitmap_lds_floats(d.n) + 3) / 4) * sizeof(float4));
         else if (t.bm == 2)
             lds = std::max(lds, ((size_t)(std::min(d.n, c->blk_cols) + kSelfSlots + 3) / 4) * sizeof(float4));
+        else if (t.bm == 4)
+            lds = std::max(lds, ((lds_floats_for(c, d, t.block) + 3) / 4) * sizeof(float4));
         else if (t.lds) lds = std::max(lds, ((size_t)(d.n + 3) / 4) * sizeof(float4));
     }
     std::vector<Tile> tl;
@@ -599,13 +643,14 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
 void apply_choice(infoli_ctx* c, const std::vector<int>& ks, TuneChoice best) {
     for (int k : ks)   // a cached choice this context cannot honour falls back to gathers
         if ((best.bm == 1 && c->inst[k].bits_off < 0) || (best.bm == 2 && c->inst[k].blk_off < 0) ||
-            (best.bm == 3 && c->inst[k].ca_off < 0))
+            (best.bm == 3 && c->inst[k].ca_off < 0) || (best.bm == 4 && c->inst[k].cb_off < 0))
             best = TuneChoice{std::min(best.L, 256), std::max(1, 256 / std::min(best.L, 256)), 0, 0, 256};
     for (int k : ks) {
         c->inst[k].lanes_per_row = best.L;
         c->inst[k].vd_lds = best.lds;
         c->inst[k].bitmap = best.bm == 1;
-        c->inst[k].blocked = best.bm == 2;
+        c->inst[k].blocked = best.bm == 2 || best.bm == 4;
+        c->inst[k].stream = best.bm == 4;
         c->inst[k].chunked = best.bm == 3;
         c->inst[k].wide = best.block == 1024;
         c->rows_of[k] = best.R;
@@ -763,6 +808,17 @@ void autotune(infoli_ctx* c) {
             for (int k : ks) all_bits = all_bits && c->inst[k].bits_off >= 0;
             if (all_bits)
                 for (int blk : {256, 1024}) consider(TuneChoice{best256.L, kBitRows, 0, 1, blk});
+            // the blocked chunk stream, when every network of the class has the
+            // chunked blocks layout and the device gives a workgroup its LDS
+            bool all_cb = c->d_rtag != nullptr;
+            for (int k : ks) all_cb = all_cb && c->inst[k].cb_off >= 0 && !c->inst[k].has_w && !c->inst[k].pcell;
+            if (all_cb)
+                for (int blk : {1024, 512}) {
+                    InstDesc d = c->inst[ks[0]];
+                    d.blocked = d.stream = 1;
+                    if (lds_floats_for(c, d, blk) * sizeof(float) + kStaticLds <= (size_t)c->lds_max)
+                        consider(TuneChoice{64, kSelfSlots, 0, 4, blk});
+                }
             // the column-blocked path, when every network of the class has it
             bool all_blk = c->d_blk != nullptr;
             for (int k : ks) all_blk = all_blk && c->inst[k].blk_off >= 0;
@@ -977,8 +1033,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         fail(INFOLI_E_INVALID_ARG, "lanes_per_row must be 0 or a power of two in [4, 256]");
     if (c->opt.autotune < 0 || c->opt.autotune > 2)
         fail(INFOLI_E_INVALID_ARG, "autotune must be 0, 1 or 2");
-    if (c->opt.csr_path < 0 || c->opt.csr_path > 4)
-        fail(INFOLI_E_INVALID_ARG, "csr_path must be 0, 1, 2, 3 or 4");
+    if (c->opt.csr_path < 0 || c->opt.csr_path > 5)
+        fail(INFOLI_E_INVALID_ARG, "csr_path must be 0, 1, 2, 3, 4 or 5");
     if (c->opt.tile_rows < 0 || c->opt.tile_rows > kMaxTileRows)
         fail(INFOLI_E_INVALID_ARG, "tile_rows must be in [0, %d]", kMaxTileRows);
     if (c->opt.output_ring_steps < 0 || c->opt.output_ring_steps > (1 << 20))
@@ -1009,6 +1065,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         HIPX(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         // 16,384-cell blocks (64 KB) when the 1024-thread kernel's static LDS fits beside them
         c->blk_cols = lds_max >= 16384 * 4 + 8192 ? 16384 : 8192;
+        c->lds_max = lds_max;
     }
 
     // ---- layout of the flattened networks
@@ -1240,6 +1297,18 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     if (c->opt.csr_path == 4)
         for (int k = 0; k < ninst; ++k)
             if (c->inst[k].ca_off >= 0) c->inst[k].chunked = 1;
+    if (c->opt.csr_path == 5)
+        for (int k = 0; k < ninst; ++k)
+            if (c->inst[k].cb_off >= 0) {
+                InstDesc d = c->inst[k];
+                d.blocked = d.stream = 1;
+                const int blk = c->opt.wide_threads ? c->opt.wide_threads : 1024;
+                if (lds_floats_for(c, d, blk) * sizeof(float) + kStaticLds > (size_t)c->lds_max)
+                    fail(INFOLI_E_UNSUPPORTED, "the chunk stream needs %zu bytes of LDS per workgroup, the device "
+                         "gives %d", lds_floats_for(c, d, blk) * sizeof(float) + kStaticLds, c->lds_max);
+                c->inst[k].blocked = c->inst[k].stream = 1;
+                c->rows_of[k] = kSelfSlots;
+            }
     if (c->opt.csr_path == 2)
         for (int k = 0; k < ninst; ++k)
             if (c->inst[k].bits_off >= 0) {
@@ -1270,6 +1339,7 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     a.cb = c->d_cb;
     a.chk = c->d_chk;
     a.chkw = c->d_chkw;
+    a.rtag = c->d_rtag;
     a.blk_cols = c->blk_cols;
     a.w = c->d_w;
     a.i_stream = c->d_stream;
@@ -1676,6 +1746,7 @@ infoli_status infoli_get_gap_path(const infoli_ctx* ctx, int32_t instance, int32
             const bool wide = ctx->group_of.size() > (size_t)instance && ctx->group_of[instance] == 1;
             if (ctx->opt.step_mode == INFOLI_MODE_PERSISTENT) p = INFOLI_PATH_CSR_GATHER;   // row walks
             else if (d.bitmap) p = INFOLI_PATH_CSR_BITMAP;
+            else if (wide && d.blocked && d.stream && d.cb_off >= 0) p = INFOLI_PATH_CSR_STREAM, blk = 1;
             else if (wide && d.blocked && d.cb_off >= 0) p = INFOLI_PATH_CSR_CHUNKED, blk = 1;
             else if (wide && d.blocked && !d.sgj) p = INFOLI_PATH_CSR_GATHER, blk = 1;
             else p = d.chunked && d.ca_off >= 0 ? INFOLI_PATH_CSR_CHUNKED : INFOLI_PATH_CSR_GATHER;

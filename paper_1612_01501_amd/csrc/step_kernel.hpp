@@ -73,6 +73,8 @@ struct InstDesc {
     int32_t chunked;       // CSR gathers from the chunked rows layout
     int32_t sgj;           // simplified (linear) gap junctions: term w * dV
     int32_t pcell;         // per-cell parameters in StepArgs::cparams
+    int32_t stream;        // blocked: the flat chunk stream (row tags) instead of row groups
+    int32_t pad_desc;
     int64_t bits_off;      // bitmap: offset of the network's first word
     int64_t blk_off;       // blocked: offset of the network's [n][nblk] block starts
     int64_t ca_off;        // chunked rows: offset of the [n + 1] row chunk starts, -1 none
@@ -111,6 +113,7 @@ struct StepArgs {
     const int32_t* cb;         // chunked blocks: per row and block, first chunk
     const uint4* chk;          // chunks of eight 16-bit columns
     const float* chkw;         // per-edge weights in the chunk layout (8 per chunk)
+    const uint8_t* rtag;       // chunked blocks: per chunk, its row mod 256
     const float* w;            // DENSE matrices and CSR weights
     const float* i_stream;     // dense input streams
     int32_t* spike_count;      // [cells]
@@ -625,6 +628,167 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
     }
 }
 
+// ---------------------------------------------------------------- chunk stream
+// Column blocks read as one flat stream per tile: in the block-major layout
+// the chunks of the tile's rows in block b are one contiguous run
+// [cb[b][row0], cb[b][row1]). Every wave takes consecutive 64-chunk sweeps of
+// it (lane l the l-th chunk: one coalesced 1 KB load per sweep), the loads of
+// up to kStreamSweeps sweeps in flight at once; a one-byte tag per chunk (its
+// row mod 256) selects the row's own voltage, the chunk's eight terms go to
+// an LDS slot of their own, and after a barrier the OWN threads owning each
+// row add that row's slots in a fixed order. No lane idles on a short row,
+// and the sums are bitwise reproducible.
+constexpr int kStreamSweeps = 8;
+constexpr size_t kStaticLds = 8192;    // bound on k_step's static LDS (s_ig, s_part, s_red)
+
+template <int BLOCK>
+__host__ __device__ constexpr int stream_round_chunks() { return (BLOCK / 64) * 64 * kStreamSweeps; }
+
+// One chunk's eight terms (voltages prescaled, staged in LDS).
+template <bool HASW, bool SGJ>
+__device__ __forceinline__ float chunk_terms(const uint4 q, const float4 wa, const float4 wb, const float* src,
+                                             float vi) {
+    const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+    float v[kChunkCols];
+#pragma unroll
+    for (int e = 0; e < kChunkCols; ++e) v[e] = src[(e & 1) ? (wd[e >> 1] >> 16) : (wd[e >> 1] & 0xffffu)];
+    const float w[kChunkCols] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+    float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+    for (int e = 0; e < kChunkCols; e += 2) {
+        const float d0 = vi - v[e], d1 = vi - v[e + 1];
+        const float f0 = pair_factor<SGJ, true>(d0), f1 = pair_factor<SGJ, true>(d1);
+        if (HASW) {
+            a0 = fmaf(w[e], d0 * f0, a0);
+            a1 = fmaf(w[e + 1], d1 * f1, a1);
+        } else {
+            a0 = fmaf(d0, f0, a0);
+            a1 = fmaf(d1, f1, a1);
+        }
+    }
+    return a0 + a1;
+}
+
+template <int BLOCK, bool HASW, bool SGJ>
+__device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                                   const float* __restrict__ vd, float* s_vd, float* s_ig) {
+    constexpr int W = BLOCK / 64;
+    constexpr int ROUND = stream_round_chunks<BLOCK>();   // chunk slots of one round
+    constexpr int OWN = BLOCK / kSelfSlots;               // threads owning one row
+    constexpr int STAGE = 16384 / BLOCK;                  // block voltages staged per thread (C <= 16,384)
+    static_assert(OWN >= 1 && OWN <= 64, "owners per row");
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int C = a.blk_cols;
+    const int S = min(d.n, C);
+    float* s_self = s_vd + S;                   // row r's own voltage at S + (r mod 256)
+    float* s_chunk = s_vd + S + kSelfSlots;     // per-chunk sums of one round
+    const int64_t n1 = d.n + 1;
+    const int32_t* cb = a.cb + d.cb_off;
+    const uint4* ch = a.chk + d.chkb_off;
+    const float4* cw = reinterpret_cast<const float4*>(a.chkw) + 2 * d.chkb_off;
+    const uint8_t* tag = a.rtag + d.chkb_off;
+    const int nrows = t.row1 - t.row0;
+    for (int k = threadIdx.x; k < nrows; k += BLOCK)
+        s_self[(t.row0 + k) & (kSelfSlots - 1)] = vd[t.row0 + k] * kPreScale;
+    const int orow = threadIdx.x / OWN, oq = threadIdx.x % OWN;
+    const bool owner = orow < nrows;
+    float rowacc = 0.0f;
+    auto sweeps_of = [&](int m) { return ((m + 63) / 64 + W - 1) / W; };   // per wave, <= kStreamSweeps
+    // the owners' fixed-order sum of one round's chunk slots
+    auto combine = [&](int b, int r0, int r1) {
+        float part = 0.0f;
+        if (owner) {
+            const int rlo = max(cb[b * n1 + t.row0 + orow], r0), rhi = min(cb[b * n1 + t.row0 + orow + 1], r1);
+            for (int c = rlo + oq; c < rhi; c += OWN) part += s_chunk[c - r0];
+        }
+        rowacc += wave_sum_xor(part, OWN);
+    };
+
+    // Work items: the rounds of every column block in which the tile has
+    // chunks. Each iteration is straight-line code: its loads (the block's
+    // voltages when the item starts a block, and the item's chunks) are
+    // issued first, the previous item's rows are summed while they fly, then
+    // the voltages are staged and the item's chunks summed into their slots.
+    int b = -1, r0 = 0, re = 0, pb = -1, p0 = 0, p1 = 0;
+    auto advance = [&]() {     // to the next item: (b, r0) within [.., re)
+        if (b >= 0 && r0 + ROUND < re) {
+            r0 += ROUND;
+            return;
+        }
+        do {
+            ++b;
+            if (b < d.nblk) {
+                r0 = cb[b * n1 + t.row0];
+                re = cb[b * n1 + t.row1];
+            }
+        } while (b < d.nblk && r0 == re);
+    };
+    advance();
+    int staged = -1;
+    while (b < d.nblk) {
+        const int r1 = min(re, r0 + ROUND);
+        const int P = sweeps_of(r1 - r0);
+        const bool stage = staged != b;
+        const int j0 = b * C, jn = min(C, d.n - j0);
+        // this thread's block voltages: indices tid + u * BLOCK below jn
+        const int lim = jn - (int)threadIdx.x;
+        const float* vsrc = vd + j0 + threadIdx.x;
+        float sv[STAGE];
+        if (stage) {
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) sv[u] = u * BLOCK < lim ? vsrc[u * BLOCK] : 0.0f;
+        }
+        uint4 q[kStreamSweeps];
+        uint32_t tg[kStreamSweeps];
+        const int base = r0 + wave * P * 64 + lane;
+#pragma unroll
+        for (int i = 0; i < kStreamSweeps; ++i) {
+            if (i < P) {
+                const int c = min(base + i * 64, r1 - 1);
+                q[i] = ch[c];
+                tg[i] = tag[c];
+            }
+        }
+        __syncthreads();                        // the previous item's slots are written
+        if (pb >= 0) combine(pb, p0, p1);
+        __syncthreads();                        // ... and read; its voltages no longer needed
+        if (stage) {
+            float* vdst = s_vd + threadIdx.x;
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u)
+                if (u * BLOCK < lim) vdst[u * BLOCK] = sv[u] * kPreScale;
+            staged = b;
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kStreamSweeps; ++i) {
+            if (i < P) {
+                const int c = base + i * 64;
+                const float vi = s_self[tg[i]];
+                float4 wa{}, wb{};
+                if (HASW) {     // per-edge weights are loaded where they are used (registers)
+                    const int64_t cc = min(c, r1 - 1);
+                    wa = cw[2 * cc];
+                    wb = cw[2 * cc + 1];
+                }
+                const float sum = chunk_terms<HASW, SGJ>(q[i], wa, wb, s_vd, vi);
+                if (c < r1) s_chunk[c - r0] = sum;
+            }
+            // one sweep at a time: the scheduler does not hoist the next
+            // sweeps' gathers (their registers would spill at 1,024 threads)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        pb = b;
+        p0 = r0;
+        p1 = r1;
+        advance();
+    }
+    __syncthreads();
+    if (pb >= 0) combine(pb, p0, p1);
+    if (owner && oq == 0) s_ig[orow] = (HASW ? rowacc : d.g * rowacc) * kInvPreScale;
+}
+
 // f(std::true_type) for a network with per-edge weights when the launch
 // compiles those paths (W), else f(std::false_type).
 template <bool W, typename F>
@@ -819,8 +983,10 @@ __device__ __forceinline__ float evoked_input(const StepArgs& a, const InstDesc&
 // update alone). kVarNoW: no network has per-edge weights. The narrow
 // variants are compiled without the paths they exclude and their registers
 // (kVarNoW: 85 VGPRs against 124 in 256-thread workgroups), so that more
-// waves per SIMD keep loads in flight.
-enum : int { kVarAll = 0, kVarNoGap = 1, kVarNoW = 2 };
+// waves per SIMD keep loads in flight. kVarStream: every tile is a chunk
+// stream tile (column blocks, no per-edge weights, no per-cell parameters),
+// the only gap path it compiles.
+enum : int { kVarAll = 0, kVarNoGap = 1, kVarNoW = 2, kVarStream = 3 };
 
 template <int BLOCK, int VAR = kVarAll>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restrict__ xin,
@@ -859,7 +1025,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
         iapp = evoked_input(a, d, step, li, cell);
     }
 
-    if constexpr (VAR == kVarNoGap) {
+    if constexpr (VAR == kVarStream) {
+        if (d.sgj) gap_stream_blocked<BLOCK, false, true>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_ig);
+        else gap_stream_blocked<BLOCK, false, false>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_ig);
+    } else if constexpr (VAR == kVarNoGap) {
         for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
     } else {
         switch (d.conn) {

@@ -273,7 +273,7 @@ def mlp_adam_step(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e
 
 
 GAP_KIND = {"rgj": 0, "sgj": 1}
-GAP_PATH = ("none", "uniform", "dense", "csr_gather", "csr_chunked", "csr_bitmap")
+GAP_PATH = ("none", "uniform", "dense", "csr_gather", "csr_chunked", "csr_bitmap", "csr_stream")
 
 
 class _SpecHolder:

@@ -171,3 +171,9 @@ def test_traffic_key_names_the_configuration():
     k = bench.traffic_key("c4", "infoli::k_step<1024, 2>", ["csr_chunked"], {"wide_threads": 512})
     assert k == "c4|infoli::k_step<1024, 2>|csr_chunked|wide512"
     assert bench.measured_traffic(k + "x") is None
+
+
+def test_stream_path_bytes_add_the_row_tags():
+    rp, col = _csr(4, [(i, j) for i in range(4) for j in range(4) if i != j])
+    net = I.Network(n=4, conn="csr", g=0.04, row_ptr=rp, col=col)
+    assert bench.algorithmic_bytes([net], ["csr_stream"]) == bench.algorithmic_bytes([net]) + 12 // 8

@@ -690,6 +690,55 @@ def test_blocked_path_trajectory(infoli, o32, o64):
     print("blocked vs gathers (spiking run), per variable:", per_var_error(got_b, got_g))
 
 
+# ------------------------------------------------------------------ chunk stream path
+@pytest.mark.parametrize("n,deg,wide", [(9000, 150, 0), (20000, 150, 0), (40000, 150, 0), (20000, 2, 0),
+                                        (20000, 1000, 0), (40000, 150, 512)])
+def test_stream_path_step_and_gap(infoli, o32, o64, n, deg, wide):
+    """The column blocks read as one chunk stream per tile: one, two and
+    three blocks with a ragged last block and a ragged last tile; a sparse
+    graph (rows with no edge in a block, tiles with no chunk in a block); a
+    dense one whose tiles need several rounds per block (degree 1,000:
+    ~26,000 chunks per tile and block); 512-thread workgroups. Gap currents
+    against fp64 and one step against the oracle, after 100 steps."""
+    net = I.config4(seed=n + deg, n=n, degree=deg)
+    x0 = infoli.initial_state(net)
+    print(f"stream path n={n} degree={deg} wide={wide}", flush=True)
+    sim = infoli.Simulator(net, init_states=[x0], csr_path=5, wide_threads=wide, step_mode="graph",
+                           graph_chunk=50)
+    assert sim.gap_path(0) == ("csr_stream", True)
+    sim.step(100)
+    xk = sim.read_state(0)
+    ig = sim.read_gap_current(0).astype(np.float64)
+    sim.step(1)
+    xk1 = sim.read_state(0)
+    sim.close()
+    ref_ig = o64.gap(net, xk[0].astype(np.float64))
+    tol = gap_bound(net, xk[0])
+    assert np.all(np.abs(ig - ref_ig) <= tol), np.max(np.abs(ig - ref_ig) / tol)
+    ref = o32.run(net, 1, x0=xk, step0=100)["x"]
+    assert per_var_error(xk1[None], ref[None]).max() <= 1e-5
+
+
+def test_stream_path_trajectory_and_repeatability(infoli, o32, o64):
+    """400 steps of a 20,000-cell network on the chunk stream against the
+    oracle (every state variable, subthreshold pulse), and a second run
+    bitwise equal to the first."""
+    net = I.config4(seed=3, n=20000, degree=60)
+    net.pulses = [I.Pulse(50, 150, 6.0)]
+    x0 = infoli.initial_state(net)
+    got, c, _ = gpu_trace(infoli, net, 400, 50, x0, csr_path=5, step_mode="graph", graph_chunk=50)
+    again, c2, _ = gpu_trace(infoli, net, 400, 50, x0, csr_path=5, step_mode="graph", graph_chunk=50)
+    assert np.array_equal(got, again) and np.array_equal(c, c2)
+    ref = o32.run(net, 400, x0=x0, trace_every=50, trace_cells=net.n)
+    r64 = o64.run(net, 400, x0=x0.astype(np.float64), trace_every=50, trace_cells=net.n)
+    floor = per_var_error(ref["trace"], r64["trace"])
+    e = per_var_error(got, ref["trace"])
+    e64 = per_var_error(got, r64["trace"])
+    print(f"stream 20k: vs f32 {e.max():.2e}, vs f64 {e64.max():.2e}, floor {floor.max():.2e}")
+    assert np.all(e <= np.maximum(TOL_STATE, 2 * floor)), e
+    assert np.all(e64 <= np.maximum(TOL_STATE, 1.25 * floor)), (e64, floor)
+
+
 # ------------------------------------------------------------------ simplified gap junctions
 def _sgj(net):
     net.gap = "sgj"
@@ -750,7 +799,7 @@ def test_sgj_gap_current(infoli, o64, conn, n):
     assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
 
 
-@pytest.mark.parametrize("csr_path", [1, 2, 3, 4])
+@pytest.mark.parametrize("csr_path", [1, 2, 3, 4, 5])
 def test_sgj_csr_paths(infoli, o32, o64, csr_path):
     """A 20,000-cell simplified network (two column blocks) on each CSR path
     the option can ask for: edge gathers, the bitmap (not built for the
