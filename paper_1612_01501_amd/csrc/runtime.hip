@@ -249,11 +249,10 @@ int group_for(const InstDesc& d) {
 }
 
 size_t lds_floats_for(const infoli_ctx* c, const InstDesc& d, int block) {
-    if (d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0)   // block, own voltages, chunk sums
-        return (size_t)std::min(d.n, c->blk_cols) + kSelfSlots +
-               (block >= 1024 ? stream_round_chunks<1024>() : stream_round_chunks<512>());
+    if (d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0)   // block, own voltages, sums, offsets
+        return (size_t)(block >= 1024 ? stream_lds_floats<1024>(c->blk_cols) : stream_lds_floats<512>(c->blk_cols));
     if (d.conn == CONN_CSR && d.blocked)   // the column block, then the tile rows' own voltages
-        return (size_t)std::min(d.n, c->blk_cols) + (d.cb_off >= 0 ? kSelfSlots : 0);
+        return d.cb_off >= 0 ? (size_t)c->blk_cols + kSelfSlots : (size_t)std::min(d.n, c->blk_cols);
     if (d.conn == CONN_UNIFORM) return (size_t)std::min(d.n, kChunk) + 8 * (size_t)(block / 64);
     if (d.conn == CONN_CSR && d.bitmap) return bitmap_lds_floats(d.n);
     if (d.conn == CONN_CSR && d.vd_lds) return (size_t)d.n;
@@ -274,12 +273,15 @@ void finalize_tiles(infoli_ctx* c) {
         bool mixed[2] = {false, false};
         for (int k = 0; k < c->n_inst; ++k) {
             const InstDesc& d = c->inst[k];
-            const bool st = d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0 && !d.has_w && !d.pcell;
+            const bool st = d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0 && !d.has_w && !d.pcell &&
+                            d.nblk <= kStreamMaxBlocks && c->blk_cols == kStreamCols;
             if (!st) mixed[group_for(d)] = true;
         }
         for (int k = 0; k < c->n_inst; ++k) {
             InstDesc& d = c->inst[k];
-            if (d.stream && (mixed[group_for(d)] || d.has_w || d.pcell || d.cb_off < 0 || !d.blocked)) d.stream = 0;
+            if (d.stream && (mixed[group_for(d)] || d.has_w || d.pcell || d.cb_off < 0 || !d.blocked ||
+                             d.nblk > kStreamMaxBlocks || c->blk_cols != kStreamCols))
+                d.stream = 0;
         }
     }
     for (int k = 0; k < c->n_inst; ++k) {
@@ -393,8 +395,8 @@ void build_blocks(infoli_ctx* c, const infoli_network_spec* specs) {
 // columns padded with i itself to whole chunks; per row its first chunk
 // ([n + 1], relative to the network's first chunk). Blocks layout, for
 // networks with column blocks: per row and block of C columns, the columns
-// relative to the block start padded with min(n, C) + (i mod kSelfSlots) to
-// whole chunks; per row and block the first chunk ([n][nblk + 1]). Per-edge
+// relative to the block start padded with C + (i mod kSelfSlots) to whole
+// chunks; per row and block the first chunk ([n][nblk + 1]). Per-edge
 // weights follow the same layout, 0 on padding.
 void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
     const int C = c->blk_cols;
@@ -473,7 +475,7 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
             for (int b = 0; b < d.nblk; ++b) {
                 for (int i = 0; i < d.n; ++i) {
                     hb[(size_t)(d.cb_off + (int64_t)b * (d.n + 1) + i)] = (int32_t)pos;
-                    const uint16_t pad = (uint16_t)(std::min(d.n, C) + (i & (kSelfSlots - 1)));
+                    const uint16_t pad = (uint16_t)(C + (i & (kSelfSlots - 1)));
                     const int64_t e0 = bnd[(size_t)i * (d.nblk + 1) + b];
                     const int64_t cnt = bnd[(size_t)i * (d.nblk + 1) + b + 1] - e0;
                     const int64_t base = (d.chkb_off + pos) * kChunkCols;
@@ -498,10 +500,15 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
                      x < hb[(size_t)(d.cb_off + (int64_t)b * (d.n + 1) + i + 1)]; ++x)
                     ht[(size_t)(d.chkb_off + x)] = (uint8_t)(i & (kSelfSlots - 1));
     }
-    c->d_rtag = c->alloc<uint8_t>((size_t)nchunks);
+    // the chunk stream loads whole items without clamping: both arrays carry
+    // one item of zeroed slack after the last chunk
+    const size_t slack = (size_t)stream_item_chunks<1024>();
+    c->d_rtag = c->alloc<uint8_t>((size_t)nchunks + slack);
     HIPX(hipMemcpy(c->d_rtag, ht.data(), ht.size(), hipMemcpyHostToDevice));
-    c->d_chk = c->alloc<uint4>((size_t)nchunks);
+    HIPX(hipMemset(c->d_rtag + nchunks, 0, slack));
+    c->d_chk = c->alloc<uint4>((size_t)nchunks + slack);
     HIPX(hipMemcpy(c->d_chk, hc.data(), sizeof(uint16_t) * hc.size(), hipMemcpyHostToDevice));
+    HIPX(hipMemset(c->d_chk + nchunks, 0, sizeof(uint4) * slack));
     c->d_chkw = c->alloc<float>(hw.size());
     HIPX(hipMemcpy(c->d_chkw, hw.data(), sizeof(float) * hw.size(), hipMemcpyHostToDevice));
     c->d_ca = c->alloc<int32_t>(ha.size());
@@ -614,7 +621,7 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
         append_tiles(planned, k, d.n, t.R, 0.0);
         if (t.bm == 1) lds = std::max(lds, ((bitmap_lds_floats(d.n) + 3) / 4) * sizeof(float4));
         else if (t.bm == 2)
-            lds = std::max(lds, ((size_t)(std::min(d.n, c->blk_cols) + kSelfSlots + 3) / 4) * sizeof(float4));
+            lds = std::max(lds, ((size_t)(c->blk_cols + kSelfSlots + 3) / 4) * sizeof(float4));
         else if (t.bm == 4)
             lds = std::max(lds, ((lds_floats_for(c, d, t.block) + 3) / 4) * sizeof(float4));
         else if (t.lds) lds = std::max(lds, ((size_t)(d.n + 3) / 4) * sizeof(float4));
@@ -811,7 +818,9 @@ void autotune(infoli_ctx* c) {
             // the blocked chunk stream, when every network of the class has the
             // chunked blocks layout and the device gives a workgroup its LDS
             bool all_cb = c->d_rtag != nullptr;
-            for (int k : ks) all_cb = all_cb && c->inst[k].cb_off >= 0 && !c->inst[k].has_w && !c->inst[k].pcell;
+            for (int k : ks)
+                all_cb = all_cb && c->inst[k].cb_off >= 0 && !c->inst[k].has_w && !c->inst[k].pcell &&
+                         c->inst[k].nblk <= kStreamMaxBlocks && c->blk_cols == kStreamCols;
             if (all_cb)
                 for (int blk : {1024, 512}) {
                     InstDesc d = c->inst[ks[0]];
@@ -1299,7 +1308,8 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
             if (c->inst[k].ca_off >= 0) c->inst[k].chunked = 1;
     if (c->opt.csr_path == 5)
         for (int k = 0; k < ninst; ++k)
-            if (c->inst[k].cb_off >= 0) {
+            if (c->inst[k].cb_off >= 0 && !c->inst[k].has_w && !c->inst[k].pcell &&
+                c->inst[k].nblk <= kStreamMaxBlocks && c->blk_cols == kStreamCols) {
                 InstDesc d = c->inst[k];
                 d.blocked = d.stream = 1;
                 const int blk = c->opt.wide_threads ? c->opt.wide_threads : 1024;

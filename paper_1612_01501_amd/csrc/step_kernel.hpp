@@ -566,7 +566,7 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
     const int32_t* cb = a.cb + d.cb_off;   // [nblk][n + 1]: block-major chunk starts
     const uint4* ch = a.chk + d.chkb_off;
     const float4* cw = reinterpret_cast<const float4*>(a.chkw) + 2 * d.chkb_off;
-    const int S = min(d.n, C);     // own-voltage slots follow the largest block
+    const int S = C;               // own-voltage slots follow the block's C slots
     for (int k = threadIdx.x; k < t.row1 - t.row0; k += BLOCK)
         s_vd[S + ((t.row0 + k) & (kSelfSlots - 1))] = vd[t.row0 + k] * kPreScale;
     float acc[kBlkPasses], vi[kBlkPasses];
@@ -631,162 +631,220 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
 // ---------------------------------------------------------------- chunk stream
 // Column blocks read as one flat stream per tile: in the block-major layout
 // the chunks of the tile's rows in block b are one contiguous run
-// [cb[b][row0], cb[b][row1]). Every wave takes consecutive 64-chunk sweeps of
-// it (lane l the l-th chunk: one coalesced 1 KB load per sweep), the loads of
-// up to kStreamSweeps sweeps in flight at once; a one-byte tag per chunk (its
-// row mod 256) selects the row's own voltage, the chunk's eight terms go to
-// an LDS slot of their own, and after a barrier the OWN threads owning each
-// row add that row's slots in a fixed order. No lane idles on a short row,
-// and the sums are bitwise reproducible.
-constexpr int kStreamSweeps = 8;
+// [cb[b][row0], cb[b][row1]). The run is cut into items of kStreamSweeps
+// sweeps per wave; in an item every wave takes consecutive 64-chunk sweeps
+// (lane l the l-th chunk: one coalesced 1 KB load per sweep). A one-byte tag
+// per chunk (its row mod 256) selects the row's own voltage; the chunk's
+// eight terms go to an LDS slot of their own, and after a barrier the OWN
+// threads owning each row add that row's slots in a fixed order (bitwise
+// reproducible). Two register sets alternate: while one item's chunks are
+// summed, the next item's loads are in flight, and the next block's
+// voltages load during the current block's items.
+constexpr int kStreamSweeps = 4;
+constexpr int kStreamMaxBlocks = 8;    // column blocks whose chunk offsets a tile keeps in LDS
+constexpr int kStreamCols = 16384;     // the column block (C) the stream is compiled for
 constexpr size_t kStaticLds = 8192;    // bound on k_step's static LDS (s_ig, s_part, s_red)
 
 template <int BLOCK>
-__host__ __device__ constexpr int stream_round_chunks() { return (BLOCK / 64) * 64 * kStreamSweeps; }
+__host__ __device__ constexpr int stream_item_chunks() { return (BLOCK / 64) * 64 * kStreamSweeps; }
+
+// LDS floats of a stream tile: block voltages, own voltages, chunk sums of
+// one item, chunk offsets of every block ([nblk][kSelfSlots + 1] ints).
+template <int BLOCK>
+__host__ __device__ constexpr int stream_lds_floats(int S) {
+    return S + kSelfSlots + stream_item_chunks<BLOCK>() + kStreamMaxBlocks * (kSelfSlots + 1);
+}
+
+// Byte offset 4*j of the 16-bit column j in the low or high half of w: one
+// instruction (a shift reading one half-word of its operand), where the
+// plain form takes an extract and a shift.
+__device__ __forceinline__ uint32_t col_lo_bytes(uint32_t w) {
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "=v"(r) : "v"(w));
+    return r;
+}
+__device__ __forceinline__ uint32_t col_hi_bytes(uint32_t w) {
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+        : "=v"(r) : "v"(w));
+    return r;
+}
 
 // One chunk's eight terms (voltages prescaled, staged in LDS).
-template <bool HASW, bool SGJ>
-__device__ __forceinline__ float chunk_terms(const uint4 q, const float4 wa, const float4 wb, const float* src,
-                                             float vi) {
+template <bool SGJ>
+__device__ __forceinline__ float chunk_terms(const uint4 q, const float* src, float vi) {
     const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+    const char* base = reinterpret_cast<const char*>(src);
     float v[kChunkCols];
 #pragma unroll
-    for (int e = 0; e < kChunkCols; ++e) v[e] = src[(e & 1) ? (wd[e >> 1] >> 16) : (wd[e >> 1] & 0xffffu)];
-    const float w[kChunkCols] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+    for (int e = 0; e < kChunkCols; ++e)
+        v[e] = *reinterpret_cast<const float*>(base + ((e & 1) ? col_hi_bytes(wd[e >> 1]) : col_lo_bytes(wd[e >> 1])));
     float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
     for (int e = 0; e < kChunkCols; e += 2) {
         const float d0 = vi - v[e], d1 = vi - v[e + 1];
-        const float f0 = pair_factor<SGJ, true>(d0), f1 = pair_factor<SGJ, true>(d1);
-        if (HASW) {
-            a0 = fmaf(w[e], d0 * f0, a0);
-            a1 = fmaf(w[e + 1], d1 * f1, a1);
-        } else {
-            a0 = fmaf(d0, f0, a0);
-            a1 = fmaf(d1, f1, a1);
-        }
+        a0 = fmaf(d0, pair_factor<SGJ, true>(d0), a0);
+        a1 = fmaf(d1, pair_factor<SGJ, true>(d1), a1);
     }
     return a0 + a1;
 }
 
-template <int BLOCK, bool HASW, bool SGJ>
+struct StreamItem {
+    int b, r0, r1;     // column block, chunk range [r0, r1); b == nblk: none
+};
+
+template <int BLOCK, bool SGJ>
 __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const InstDesc& d, const Tile& t,
                                                    const float* __restrict__ vd, float* s_vd, float* s_ig) {
     constexpr int W = BLOCK / 64;
-    constexpr int ROUND = stream_round_chunks<BLOCK>();   // chunk slots of one round
+    constexpr int ITEM = stream_item_chunks<BLOCK>();     // chunk slots of one item
     constexpr int OWN = BLOCK / kSelfSlots;               // threads owning one row
-    constexpr int STAGE = 16384 / BLOCK;                  // block voltages staged per thread (C <= 16,384)
+    constexpr int STAGE = kStreamCols / BLOCK;            // block voltages staged per thread (C = kStreamCols)
+    constexpr int SW = kStreamSweeps;
     static_assert(OWN >= 1 && OWN <= 64, "owners per row");
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    // descriptor fields in registers: read once, not again inside the loop
+    // (a load there would wait for the chunk loads in flight)
     const int C = a.blk_cols;
-    const int S = min(d.n, C);
+    const int n = d.n;
+    const int S = C;                            // own voltages after the block's C slots
+    const int nblk = d.nblk;
+    const float g = d.g;
     float* s_self = s_vd + S;                   // row r's own voltage at S + (r mod 256)
-    float* s_chunk = s_vd + S + kSelfSlots;     // per-chunk sums of one round
-    const int64_t n1 = d.n + 1;
+    float* s_chunk = s_self + kSelfSlots;       // per-chunk sums of one item
+    int* s_off = reinterpret_cast<int*>(s_chunk + ITEM);   // [b][i]: chunk start of row row0 + i in block b
+    const int64_t n1 = n + 1;
     const int32_t* cb = a.cb + d.cb_off;
     const uint4* ch = a.chk + d.chkb_off;
-    const float4* cw = reinterpret_cast<const float4*>(a.chkw) + 2 * d.chkb_off;
     const uint8_t* tag = a.rtag + d.chkb_off;
     const int nrows = t.row1 - t.row0;
+    const int nr1 = nrows + 1;
     for (int k = threadIdx.x; k < nrows; k += BLOCK)
         s_self[(t.row0 + k) & (kSelfSlots - 1)] = vd[t.row0 + k] * kPreScale;
+    for (int k = threadIdx.x; k < nblk * nr1; k += BLOCK) {
+        const int b = k / nr1, i = k - b * nr1;
+        s_off[k] = cb[b * n1 + t.row0 + i];
+    }
+    __syncthreads();
     const int orow = threadIdx.x / OWN, oq = threadIdx.x % OWN;
     const bool owner = orow < nrows;
     float rowacc = 0.0f;
-    auto sweeps_of = [&](int m) { return ((m + 63) / 64 + W - 1) / W; };   // per wave, <= kStreamSweeps
-    // the owners' fixed-order sum of one round's chunk slots
-    auto combine = [&](int b, int r0, int r1) {
+
+    // the item after `it` (the first one for it.b < 0): the next ITEM chunks
+    // of its block, else the first chunks of the next block that has any
+    // Item bounds are the same in every lane (made scalar, so that branches
+    // on them are scalar: the loads and stores of the pipeline stay in
+    // straight-line code and wait only for what they use).
+    auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+    auto next_item = [&](StreamItem it) {
+        if (it.b >= 0 && it.b < nblk) {
+            const int re = uni(s_off[it.b * nr1 + nrows]);
+            if (it.r1 < re) return StreamItem{it.b, it.r1, min(re, it.r1 + ITEM)};
+        }
+        for (int b = it.b + 1; b < nblk; ++b) {
+            const int r0 = uni(s_off[b * nr1]), re = uni(s_off[b * nr1 + nrows]);
+            if (r0 < re) return StreamItem{b, r0, min(re, r0 + ITEM)};
+        }
+        return StreamItem{nblk, 0, 0};
+    };
+    auto next_block = [&](int b) {     // the next block with chunks after b, nblk if none
+        for (++b; b < nblk; ++b)
+            if (uni(s_off[b * nr1]) < uni(s_off[b * nr1 + nrows])) return b;
+        return nblk;
+    };
+    auto sweeps_of = [&](const StreamItem& it) { return ((it.r1 - it.r0 + 63) / 64 + W - 1) / W; };
+    // every sweep slot loads (past the item's end, chunks the compute skips:
+    // the arrays carry an item of slack), from one address per item, so that
+    // no load sits in a branch
+    auto load = [&](uint4 (&q)[SW], uint32_t (&tg)[SW], const StreamItem& it) {
+        const int P = sweeps_of(it);
+        const int base = it.r0 + wave * P * 64 + lane;
+        const uint4* qp = ch + base;
+        const uint8_t* tp = tag + base;
+#pragma unroll
+        for (int i = 0; i < SW; ++i) {
+            q[i] = qp[i * 64];
+            tg[i] = tp[i * 64];
+        }
+    };
+    auto compute = [&](const uint4 (&q)[SW], const uint32_t (&tg)[SW], const StreamItem& it) {
+        const int P = sweeps_of(it);
+        const int base = it.r0 + wave * P * 64 + lane;
+#pragma unroll
+        for (int i = 0; i < SW; ++i) {
+            if (i < P) {
+                const int c = base + i * 64;
+                const float sum = chunk_terms<SGJ>(q[i], s_vd, s_self[tg[i]]);
+                if (c < it.r1) s_chunk[c - it.r0] = sum;
+            }
+            // one sweep at a time: the next sweeps' gathers are not hoisted
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    auto combine = [&](const StreamItem& it) {
         float part = 0.0f;
         if (owner) {
-            const int rlo = max(cb[b * n1 + t.row0 + orow], r0), rhi = min(cb[b * n1 + t.row0 + orow + 1], r1);
-            for (int c = rlo + oq; c < rhi; c += OWN) part += s_chunk[c - r0];
+            const int rlo = max(s_off[it.b * nr1 + orow], it.r0), rhi = min(s_off[it.b * nr1 + orow + 1], it.r1);
+            for (int c = rlo + oq; c < rhi; c += OWN) part += s_chunk[c - it.r0];
         }
         rowacc += wave_sum_xor(part, OWN);
     };
-
-    // Work items: the rounds of every column block in which the tile has
-    // chunks. Each iteration is straight-line code: its loads (the block's
-    // voltages when the item starts a block, and the item's chunks) are
-    // issued first, the previous item's rows are summed while they fly, then
-    // the voltages are staged and the item's chunks summed into their slots.
-    int b = -1, r0 = 0, re = 0, pb = -1, p0 = 0, p1 = 0;
-    auto advance = [&]() {     // to the next item: (b, r0) within [.., re)
-        if (b >= 0 && r0 + ROUND < re) {
-            r0 += ROUND;
-            return;
-        }
-        do {
-            ++b;
-            if (b < d.nblk) {
-                r0 = cb[b * n1 + t.row0];
-                re = cb[b * n1 + t.row1];
-            }
-        } while (b < d.nblk && r0 == re);
+    float sv[STAGE];
+    // block voltages: every thread loads and stores STAGE of them, indices
+    // past the block's end clamped to its last voltage (a repeated store of
+    // the same value), so that neither sits in a branch
+    // all C slots are loaded and stored, past the network's last cell too:
+    // the state buffer holds 14 rows of at least n > C / 2 cells after Vd,
+    // and no column entry names a slot past the block's end
+    auto load_voltages = [&](int b) {
+        const float* src = vd + b * C + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < STAGE; ++u) sv[u] = src[u * BLOCK];
     };
-    advance();
+    auto store_voltages = [&](int b) {
+        float* dst = s_vd + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < STAGE; ++u) dst[u * BLOCK] = sv[u] * kPreScale;
+    };
+
+    uint4 qa[SW], qb[SW];
+    uint32_t ta[SW], tb[SW];
+    StreamItem prev{-1, 0, 0};
+    StreamItem cur = next_item(StreamItem{-1, 0, 0});
+    StreamItem nxt = next_item(cur);
     int staged = -1;
-    while (b < d.nblk) {
-        const int r1 = min(re, r0 + ROUND);
-        const int P = sweeps_of(r1 - r0);
-        const bool stage = staged != b;
-        const int j0 = b * C, jn = min(C, d.n - j0);
-        // this thread's block voltages: indices tid + u * BLOCK below jn
-        const int lim = jn - (int)threadIdx.x;
-        const float* vsrc = vd + j0 + threadIdx.x;
-        float sv[STAGE];
-        if (stage) {
-#pragma unroll
-            for (int u = 0; u < STAGE; ++u) sv[u] = u * BLOCK < lim ? vsrc[u * BLOCK] : 0.0f;
-        }
-        uint4 q[kStreamSweeps];
-        uint32_t tg[kStreamSweeps];
-        const int base = r0 + wave * P * 64 + lane;
-#pragma unroll
-        for (int i = 0; i < kStreamSweeps; ++i) {
-            if (i < P) {
-                const int c = min(base + i * 64, r1 - 1);
-                q[i] = ch[c];
-                tg[i] = tag[c];
-            }
-        }
+    if (cur.b < nblk) {
+        load_voltages(cur.b);
+        load(qa, ta, cur);
+    }
+    // One item from set X while set Y loads the item after it.
+    auto half = [&](uint4 (&qx)[SW], uint32_t (&tx)[SW], uint4 (&qy)[SW], uint32_t (&ty)[SW]) {
+        if (nxt.b < nblk) load(qy, ty, nxt);
         __syncthreads();                        // the previous item's slots are written
-        if (pb >= 0) combine(pb, p0, p1);
-        __syncthreads();                        // ... and read; its voltages no longer needed
-        if (stage) {
-            float* vdst = s_vd + threadIdx.x;
-#pragma unroll
-            for (int u = 0; u < STAGE; ++u)
-                if (u * BLOCK < lim) vdst[u * BLOCK] = sv[u] * kPreScale;
-            staged = b;
+        if (prev.b >= 0) combine(prev);
+        __syncthreads();                        // ... and read; earlier voltages no longer needed
+        if (staged != cur.b) {
+            store_voltages(cur.b);
+            staged = cur.b;
             __syncthreads();
+            const int nb = next_block(cur.b);   // its voltages load during this block's items
+            if (nb < nblk) load_voltages(nb);
         }
-#pragma unroll
-        for (int i = 0; i < kStreamSweeps; ++i) {
-            if (i < P) {
-                const int c = base + i * 64;
-                const float vi = s_self[tg[i]];
-                float4 wa{}, wb{};
-                if (HASW) {     // per-edge weights are loaded where they are used (registers)
-                    const int64_t cc = min(c, r1 - 1);
-                    wa = cw[2 * cc];
-                    wb = cw[2 * cc + 1];
-                }
-                const float sum = chunk_terms<HASW, SGJ>(q[i], wa, wb, s_vd, vi);
-                if (c < r1) s_chunk[c - r0] = sum;
-            }
-            // one sweep at a time: the scheduler does not hoist the next
-            // sweeps' gathers (their registers would spill at 1,024 threads)
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        pb = b;
-        p0 = r0;
-        p1 = r1;
-        advance();
+        compute(qx, tx, cur);
+        prev = cur;
+        cur = nxt;
+        nxt = next_item(cur);
+    };
+    while (cur.b < nblk) {
+        half(qa, ta, qb, tb);
+        if (cur.b >= nblk) break;
+        half(qb, tb, qa, ta);
     }
     __syncthreads();
-    if (pb >= 0) combine(pb, p0, p1);
-    if (owner && oq == 0) s_ig[orow] = (HASW ? rowacc : d.g * rowacc) * kInvPreScale;
+    if (prev.b >= 0) combine(prev);
+    if (owner && oq == 0) s_ig[orow] = g * rowacc * kInvPreScale;
 }
 
 // f(std::true_type) for a network with per-edge weights when the launch
@@ -1026,8 +1084,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
     }
 
     if constexpr (VAR == kVarStream) {
-        if (d.sgj) gap_stream_blocked<BLOCK, false, true>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_ig);
-        else gap_stream_blocked<BLOCK, false, false>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_ig);
+        if (d.sgj) gap_stream_blocked<BLOCK, true>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_ig);
+        else gap_stream_blocked<BLOCK, false>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_ig);
     } else if constexpr (VAR == kVarNoGap) {
         for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
     } else {
