@@ -489,6 +489,49 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
             }
         }
     }
+    // Bank-aware order of each chunk's eight columns (blocks layout, one
+    // weight g): the chunk stream reads a tile's run in sweeps of 64
+    // consecutive chunks from the run's start (tiles of kSelfSlots rows), lane
+    // l the l-th chunk, and its e-th gather reads every lane's e-th column. A
+    // chunk's columns may come in any order (only the order of the row's sum
+    // changes), so each sweep's chunks are given orders under which each
+    // gather's 64 slots fall on distinct LDS banks (slot mod 64), and each
+    // half-wave's on distinct slot mod 32, as far as a greedy pass finds.
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstDesc& d = c->inst[k];
+        if (d.cb_off < 0 || d.has_w) continue;
+        for (int b = 0; b < d.nblk; ++b) {
+            const int32_t* off = &hb[(size_t)(d.cb_off + (int64_t)b * (d.n + 1))];
+            for (int r = 0; r < d.n; r += kSelfSlots) {
+                const int64_t x0 = off[r], x1 = off[std::min(d.n, r + kSelfSlots)];
+                for (int64_t w0 = x0; w0 < x1; w0 += 64) {
+                    const int nch = (int)std::min<int64_t>(64, x1 - w0);
+                    uint16_t* base = &hc[(size_t)(d.chkb_off + w0) * kChunkCols];
+                    uint16_t out[64][kChunkCols];
+                    bool used[64][kChunkCols] = {};
+                    for (int e = 0; e < kChunkCols; ++e) {
+                        int c64[64] = {}, c32[2][32] = {};
+                        for (int l = 0; l < nch; ++l) {
+                            int best = -1, cost = 1 << 30;
+                            for (int u = 0; u < kChunkCols; ++u) {
+                                if (used[l][u]) continue;
+                                const int sl = base[l * kChunkCols + u];
+                                const int cu = 4 * c64[sl & 63] + c32[l >> 5][sl & 31];
+                                if (cu < cost) cost = cu, best = u;
+                            }
+                            used[l][best] = true;
+                            const int sl = base[l * kChunkCols + best];
+                            out[l][e] = (uint16_t)sl;
+                            ++c64[sl & 63];
+                            ++c32[l >> 5][sl & 31];
+                        }
+                    }
+                    for (int l = 0; l < nch; ++l)
+                        for (int e = 0; e < kChunkCols; ++e) base[l * kChunkCols + e] = out[l][e];
+                }
+            }
+        }
+    }
     // per chunk of the blocks layout, its row mod 256 (the chunk stream's row tag)
     std::vector<uint8_t> ht((size_t)nchunks, 0);
     for (int k = 0; k < c->n_inst; ++k) {
@@ -502,7 +545,7 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
     }
     // the chunk stream loads whole items without clamping: both arrays carry
     // one item of zeroed slack after the last chunk
-    const size_t slack = (size_t)stream_item_chunks<1024>();
+    const size_t slack = (size_t)kStreamSlack;
     c->d_rtag = c->alloc<uint8_t>((size_t)nchunks + slack);
     HIPX(hipMemcpy(c->d_rtag, ht.data(), ht.size(), hipMemcpyHostToDevice));
     HIPX(hipMemset(c->d_rtag + nchunks, 0, slack));

@@ -631,29 +631,33 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
 // ---------------------------------------------------------------- chunk stream
 // Column blocks read as one flat stream per tile: in the block-major layout
 // the chunks of the tile's rows in block b are one contiguous run
-// [cb[b][row0], cb[b][row1]). The run is cut into items of kStreamSweeps
-// sweeps per wave; in an item every wave takes consecutive 64-chunk sweeps
-// (lane l the l-th chunk: one coalesced 1 KB load per sweep). A one-byte tag
-// per chunk (its row mod 256) selects the row's own voltage; the chunk's
-// eight terms go to an LDS slot of their own, and after a barrier the OWN
-// threads owning each row add that row's slots in a fixed order (bitwise
-// reproducible). Two register sets alternate: while one item's chunks are
-// summed, the next item's loads are in flight, and the next block's
-// voltages load during the current block's items.
+// [cb[b][row0], cb[b][row1]). A round is that run (cut at kStreamRound
+// chunks); every wave takes a contiguous share of the round's 64-chunk
+// sweeps (lane l the l-th chunk of a sweep: one coalesced 1 KB load), in
+// pieces of kStreamSweeps sweeps. A one-byte tag per chunk (its row mod 256)
+// selects the row's own voltage; the chunk's eight terms go to an LDS slot of
+// their own. Waves run a round's pieces without synchronising; at the round's
+// end the OWN threads owning each row add that row's slots in a fixed order
+// (bitwise reproducible). Two register sets alternate: while one piece is
+// summed the next piece's loads are in flight, and the next block's voltages
+// load during the current block. kStreamSets register sets rotate, so that
+// the loads of kStreamSets - 1 pieces are in flight while one is summed.
 constexpr int kStreamSweeps = 4;
+constexpr int kStreamSets = 2;
 constexpr int kStreamMaxBlocks = 8;    // column blocks whose chunk offsets a tile keeps in LDS
 constexpr int kStreamCols = 16384;     // the column block (C) the stream is compiled for
+constexpr int kStreamRound = 16384;    // chunk sums of one round in LDS
 constexpr size_t kStaticLds = 8192;    // bound on k_step's static LDS (s_ig, s_part, s_red)
 
-template <int BLOCK>
-__host__ __device__ constexpr int stream_item_chunks() { return (BLOCK / 64) * 64 * kStreamSweeps; }
-
 // LDS floats of a stream tile: block voltages, own voltages, chunk sums of
-// one item, chunk offsets of every block ([nblk][kSelfSlots + 1] ints).
+// one round, chunk offsets of every block ([nblk][kSelfSlots + 1] ints).
 template <int BLOCK>
-__host__ __device__ constexpr int stream_lds_floats(int S) {
-    return S + kSelfSlots + stream_item_chunks<BLOCK>() + kStreamMaxBlocks * (kSelfSlots + 1);
+__host__ __device__ constexpr int stream_lds_floats(int C) {
+    return C + kSelfSlots + kStreamRound + kStreamMaxBlocks * (kSelfSlots + 1);
 }
+// chunks the stream may load past a round's end (the arrays carry as many
+// zeroed ones): a wave's share is rounded up to whole pieces
+constexpr int kStreamSlack = (1024 / 64 + kStreamSweeps) * 64;
 
 // Byte offset 4*j of the 16-bit column j in the low or high half of w: one
 // instruction (a shift reading one half-word of its operand), where the
@@ -690,31 +694,32 @@ __device__ __forceinline__ float chunk_terms(const uint4 q, const float* src, fl
     return a0 + a1;
 }
 
-struct StreamItem {
-    int b, r0, r1;     // column block, chunk range [r0, r1); b == nblk: none
+// One piece of a wave's share of a round: block b, round [r0, r1), the
+// wave's first sweep s0 and its sweeps in this piece np (0..kStreamSweeps),
+// the piece's index in the share and the pieces per share; b == nblk: none.
+struct StreamPiece {
+    int b, r0, r1, s0, np, j, npieces;
 };
 
 template <int BLOCK, bool SGJ>
 __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const InstDesc& d, const Tile& t,
                                                    const float* __restrict__ vd, float* s_vd, float* s_ig) {
     constexpr int W = BLOCK / 64;
-    constexpr int ITEM = stream_item_chunks<BLOCK>();     // chunk slots of one item
     constexpr int OWN = BLOCK / kSelfSlots;               // threads owning one row
     constexpr int STAGE = kStreamCols / BLOCK;            // block voltages staged per thread (C = kStreamCols)
     constexpr int SW = kStreamSweeps;
     static_assert(OWN >= 1 && OWN <= 64, "owners per row");
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // descriptor fields in registers: read once, not again inside the loop
     // (a load there would wait for the chunk loads in flight)
-    const int C = a.blk_cols;
+    const int C = kStreamCols;
     const int n = d.n;
-    const int S = C;                            // own voltages after the block's C slots
     const int nblk = d.nblk;
     const float g = d.g;
-    float* s_self = s_vd + S;                   // row r's own voltage at S + (r mod 256)
-    float* s_chunk = s_self + kSelfSlots;       // per-chunk sums of one item
-    int* s_off = reinterpret_cast<int*>(s_chunk + ITEM);   // [b][i]: chunk start of row row0 + i in block b
+    float* s_self = s_vd + C;                   // row r's own voltage at C + (r mod 256)
+    float* s_chunk = s_self + kSelfSlots;       // per-chunk sums of one round
+    int* s_off = reinterpret_cast<int*>(s_chunk + kStreamRound);   // [b][i]: chunk start of row row0 + i
     const int64_t n1 = n + 1;
     const int32_t* cb = a.cb + d.cb_off;
     const uint4* ch = a.chk + d.chkb_off;
@@ -732,115 +737,138 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
     const bool owner = orow < nrows;
     float rowacc = 0.0f;
 
-    // the item after `it` (the first one for it.b < 0): the next ITEM chunks
-    // of its block, else the first chunks of the next block that has any
-    // Item bounds are the same in every lane (made scalar, so that branches
-    // on them are scalar: the loads and stores of the pipeline stay in
-    // straight-line code and wait only for what they use).
+    // Piece bounds are the same in every lane of a wave (made scalar, so that
+    // branches on them are scalar: the loads and stores of the pipeline stay
+    // in straight-line code and wait only for what they use).
     auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
-    auto next_item = [&](StreamItem it) {
-        if (it.b >= 0 && it.b < nblk) {
-            const int re = uni(s_off[it.b * nr1 + nrows]);
-            if (it.r1 < re) return StreamItem{it.b, it.r1, min(re, it.r1 + ITEM)};
-        }
-        for (int b = it.b + 1; b < nblk; ++b) {
+    auto piece_of = [&](int b, int r0, int r1, int j) {
+        const int nsw = (r1 - r0 + 63) / 64;                 // sweeps of the round
+        const int q = (nsw + W - 1) / W;                     // sweeps per wave
+        const int s0 = min(nsw, wave * q + j * SW);
+        const int np = min(SW, min(nsw, wave * q + q) - s0);
+        return StreamPiece{b, r0, r1, s0, max(np, 0), j, (q + SW - 1) / SW};
+    };
+    auto first_round_from = [&](int b0) {    // the first piece of the first round of block b0 or later
+        for (int b = b0; b < nblk; ++b) {
             const int r0 = uni(s_off[b * nr1]), re = uni(s_off[b * nr1 + nrows]);
-            if (r0 < re) return StreamItem{b, r0, min(re, r0 + ITEM)};
+            if (r0 < re) return piece_of(b, r0, min(re, r0 + kStreamRound), 0);
         }
-        return StreamItem{nblk, 0, 0};
+        return StreamPiece{nblk, 0, 0, 0, 0, 0, 1};
+    };
+    auto next_piece = [&](const StreamPiece& p) {
+        if (p.j + 1 < p.npieces) return piece_of(p.b, p.r0, p.r1, p.j + 1);
+        const int re = uni(s_off[p.b * nr1 + nrows]);
+        if (p.r1 < re) return piece_of(p.b, p.r1, min(re, p.r1 + kStreamRound), 0);
+        return first_round_from(p.b + 1);
     };
     auto next_block = [&](int b) {     // the next block with chunks after b, nblk if none
         for (++b; b < nblk; ++b)
             if (uni(s_off[b * nr1]) < uni(s_off[b * nr1 + nrows])) return b;
         return nblk;
     };
-    auto sweeps_of = [&](const StreamItem& it) { return ((it.r1 - it.r0 + 63) / 64 + W - 1) / W; };
-    // every sweep slot loads (past the item's end, chunks the compute skips:
-    // the arrays carry an item of slack), from one address per item, so that
-    // no load sits in a branch
-    auto load = [&](uint4 (&q)[SW], uint32_t (&tg)[SW], const StreamItem& it) {
-        const int P = sweeps_of(it);
-        const int base = it.r0 + wave * P * 64 + lane;
-        const uint4* qp = ch + base;
-        const uint8_t* tp = tag + base;
+    // every sweep slot of a piece loads (past its end, chunks the compute
+    // skips: the arrays carry kStreamSlack chunks of slack), from one address
+    auto load = [&](uint4 (&q)[SW], uint32_t (&tg)[SW], const StreamPiece& p) {
+        const int c0 = p.r0 + p.s0 * 64 + lane;
+        const uint4* qp = ch + c0;
+        const uint8_t* tp = tag + c0;
 #pragma unroll
         for (int i = 0; i < SW; ++i) {
             q[i] = qp[i * 64];
             tg[i] = tp[i * 64];
         }
     };
-    auto compute = [&](const uint4 (&q)[SW], const uint32_t (&tg)[SW], const StreamItem& it) {
-        const int P = sweeps_of(it);
-        const int base = it.r0 + wave * P * 64 + lane;
+    auto compute = [&](const uint4 (&q)[SW], const uint32_t (&tg)[SW], const StreamPiece& p) {
+        const int slot = p.s0 * 64 + lane;                  // this lane's slot of sweep 0
+        const int m = p.r1 - p.r0;
+        float* dst = s_chunk + slot;
+        if (p.np == SW && (p.s0 + SW) * 64 <= m) {
+            // whole sweeps only (all but a round's last piece): one basic
+            // block, in which the scheduler overlaps two sweeps at a time
 #pragma unroll
-        for (int i = 0; i < SW; ++i) {
-            if (i < P) {
-                const int c = base + i * 64;
-                const float sum = chunk_terms<SGJ>(q[i], s_vd, s_self[tg[i]]);
-                if (c < it.r1) s_chunk[c - it.r0] = sum;
+            for (int i = 0; i < SW; ++i) {
+                dst[i * 64] = chunk_terms<SGJ>(q[i], s_vd, s_self[tg[i]]);
+                if (i & 1) __builtin_amdgcn_sched_barrier(0);
             }
-            // one sweep at a time: the next sweeps' gathers are not hoisted
-            __builtin_amdgcn_sched_barrier(0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < SW; ++i) {
+                if (i < p.np) {
+                    const float sum = chunk_terms<SGJ>(q[i], s_vd, s_self[tg[i]]);
+                    if (slot + i * 64 < m) dst[i * 64] = sum;
+                }
+            }
         }
     };
-    auto combine = [&](const StreamItem& it) {
+    auto combine = [&](const StreamPiece& p) {
         float part = 0.0f;
         if (owner) {
-            const int rlo = max(s_off[it.b * nr1 + orow], it.r0), rhi = min(s_off[it.b * nr1 + orow + 1], it.r1);
-            for (int c = rlo + oq; c < rhi; c += OWN) part += s_chunk[c - it.r0];
+            const int rlo = max(s_off[p.b * nr1 + orow], p.r0), rhi = min(s_off[p.b * nr1 + orow + 1], p.r1);
+            for (int c = rlo + oq; c < rhi; c += OWN) part += s_chunk[c - p.r0];
         }
         rowacc += wave_sum_xor(part, OWN);
     };
-    float sv[STAGE];
-    // block voltages: every thread loads and stores STAGE of them, indices
-    // past the block's end clamped to its last voltage (a repeated store of
-    // the same value), so that neither sits in a branch
     // all C slots are loaded and stored, past the network's last cell too:
     // the state buffer holds 14 rows of at least n > C / 2 cells after Vd,
     // and no column entry names a slot past the block's end
+    float sv[STAGE];
     auto load_voltages = [&](int b) {
         const float* src = vd + b * C + threadIdx.x;
 #pragma unroll
         for (int u = 0; u < STAGE; ++u) sv[u] = src[u * BLOCK];
     };
-    auto store_voltages = [&](int b) {
+    auto store_voltages = [&]() {
         float* dst = s_vd + threadIdx.x;
 #pragma unroll
         for (int u = 0; u < STAGE; ++u) dst[u * BLOCK] = sv[u] * kPreScale;
     };
 
-    uint4 qa[SW], qb[SW];
-    uint32_t ta[SW], tb[SW];
-    StreamItem prev{-1, 0, 0};
-    StreamItem cur = next_item(StreamItem{-1, 0, 0});
-    StreamItem nxt = next_item(cur);
+    constexpr int NS = kStreamSets;
+    uint4 q[NS][SW];
+    uint32_t tg[NS][SW];
+    StreamPiece prev{-1, 0, 0, 0, 0, 0, 1};      // the round being summed last (combined at the next round)
+    StreamPiece cur = first_round_from(0);       // the piece summed next
+    StreamPiece ahead = cur;                     // the last piece whose loads are queued
     int staged = -1;
     if (cur.b < nblk) {
         load_voltages(cur.b);
-        load(qa, ta, cur);
+        load(q[0], tg[0], cur);
+#pragma unroll
+        for (int k = 1; k < NS - 1; ++k) {
+            const StreamPiece nx = ahead.b < nblk ? next_piece(ahead) : ahead;
+            ahead = nx;
+            if (ahead.b < nblk) load(q[k], tg[k], ahead);
+        }
     }
-    // One item from set X while set Y loads the item after it.
-    auto half = [&](uint4 (&qx)[SW], uint32_t (&tx)[SW], uint4 (&qy)[SW], uint32_t (&ty)[SW]) {
-        if (nxt.b < nblk) load(qy, ty, nxt);
-        __syncthreads();                        // the previous item's slots are written
-        if (prev.b >= 0) combine(prev);
-        __syncthreads();                        // ... and read; earlier voltages no longer needed
-        if (staged != cur.b) {
-            store_voltages(cur.b);
-            staged = cur.b;
-            __syncthreads();
-            const int nb = next_block(cur.b);   // its voltages load during this block's items
-            if (nb < nblk) load_voltages(nb);
+    // Sum the piece in set u while set u - 1 (summed last) loads the piece
+    // NS - 1 ahead. Every wave has the same pieces per round, so the barriers
+    // at round starts match.
+    auto step = [&](uint4 (&qx)[SW], uint32_t (&tx)[SW], uint4 (&qz)[SW], uint32_t (&tz)[SW]) {
+        if (ahead.b < nblk) {
+            ahead = next_piece(ahead);
+            if (ahead.b < nblk) load(qz, tz, ahead);
+        }
+        if (cur.j == 0) {
+            __syncthreads();                    // the previous round's slots are written
+            if (prev.b >= 0) combine(prev);
+            __syncthreads();                    // ... and read; earlier voltages no longer needed
+            if (staged != cur.b) {
+                store_voltages();
+                staged = cur.b;
+                __syncthreads();
+                const int nb = next_block(cur.b);   // its voltages load during this block
+                if (nb < nblk) load_voltages(nb);
+            }
         }
         compute(qx, tx, cur);
         prev = cur;
-        cur = nxt;
-        nxt = next_item(cur);
+        cur = next_piece(cur);
     };
     while (cur.b < nblk) {
-        half(qa, ta, qb, tb);
-        if (cur.b >= nblk) break;
-        half(qb, tb, qa, ta);
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            if (cur.b < nblk) step(q[u], tg[u], q[(u + NS - 1) % NS], tg[(u + NS - 1) % NS]);
+        }
     }
     __syncthreads();
     if (prev.b >= 0) combine(prev);
