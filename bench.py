@@ -97,7 +97,7 @@ def tuned_config(info, sim, nets):
             "csr_bitmap_networks": info["n_bitmap"], "csr_blocked_networks": info["n_blocked"],
             "lanes_per_row": info["lanes_per_row"], "tile_rows": info["tile_rows"],
             "gap_paths": sorted(set(sim.gap_path(k)[0] for k in range(len(nets)))),
-            "step_kernel": step_kernel_name(info, nets),
+            "step_kernel": step_kernel_name(info, nets, [sim.gap_path(k)[0] for k in range(len(nets))]),
             "tuned_networks": info["tuned"], "tune_cached_networks": info["tune_cached"]}
 
 
@@ -233,13 +233,15 @@ def slots_of(n, path=None):
     return s
 
 
-def step_kernel_name(info, nets):
+def step_kernel_name(info, nets, paths=None):
     """The kernel(s) one step launches, from the context's launch groups and
     the variant the runtime picks for them: 1 when no network has gap
-    junctions, 2 when none has per-edge weights or per-cell parameters,
-    else 0."""
+    junctions, 3 when every network runs the chunk stream (the wide group
+    only), 2 when none has per-edge weights or per-cell parameters, else 0."""
     if info["step_mode"] == 3:
         return "infoli::k_persist"
+    if paths and all(p == "csr_stream" for p in paths):
+        return f"infoli::k_step<{info.get('wide_threads', 1024)}, 3>"
     if all(n.conn == "none" and n.cell_params is None for n in nets):
         var = 1
     elif all(n.w_csr is None and n.cell_params is None for n in nets):
@@ -596,7 +598,7 @@ def run_c4(nets, desc, steps, warmup, args, torch, infoli):
     log(f"c4: context ready ({info['n_tiles']} tiles, graph chunk {chunk})")
     wall, dev_ms = time_plain(sim, steps, warmup, torch)
     launch_s = dev_ms * 1e-3 / steps
-    kernel = step_kernel_name(info, nets)
+    kernel = step_kernel_name(info, nets, paths)
     cells, pairs = net.n, net.pairs_per_step()
     out = {
         "metric": "cell-steps/sec and gap pairs/sec at 1 MI355X; surrogate vs plain speedup at 1 mV RMSE",
@@ -857,10 +859,10 @@ def main():
                    "gap_pairs_per_step": pairs, "step_mode": mode, "graph_chunk": chunk, **tuned},
         "gap_pairs_per_s": pairs * steps / wall,
         "device_ms_per_step": dev_ms / steps,
-        "roofline": roofline(nets, launch_s, step_kernel_name(info, nets), paths),
+        "roofline": roofline(nets, launch_s, step_kernel_name(info, nets, paths), paths),
         "stability": stability(nets),
     }
-    out["roofline"]["traffic"] = measured_traffic(traffic_key(args.workload, step_kernel_name(info, nets),
+    out["roofline"]["traffic"] = measured_traffic(traffic_key(args.workload, step_kernel_name(info, nets, paths),
                                                               paths, info))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)

@@ -646,14 +646,14 @@ constexpr int kStreamSweeps = 4;
 constexpr int kStreamSets = 2;
 constexpr int kStreamMaxBlocks = 8;    // column blocks whose chunk offsets a tile keeps in LDS
 constexpr int kStreamCols = 16384;     // the column block (C) the stream is compiled for
-constexpr int kStreamRound = 16384;    // chunk sums of one round in LDS
+constexpr int kStreamRound = 8192;     // chunk sums of one round in LDS (two buffers)
 constexpr size_t kStaticLds = 8192;    // bound on k_step's static LDS (s_ig, s_part, s_red)
 
 // LDS floats of a stream tile: block voltages, own voltages, chunk sums of
-// one round, chunk offsets of every block ([nblk][kSelfSlots + 1] ints).
+// two rounds, chunk offsets of every block ([nblk][kSelfSlots + 1] ints).
 template <int BLOCK>
 __host__ __device__ constexpr int stream_lds_floats(int C) {
-    return C + kSelfSlots + kStreamRound + kStreamMaxBlocks * (kSelfSlots + 1);
+    return C + kSelfSlots + 2 * kStreamRound + kStreamMaxBlocks * (kSelfSlots + 1);
 }
 // chunks the stream may load past a round's end (the arrays carry as many
 // zeroed ones): a wave's share is rounded up to whole pieces
@@ -694,11 +694,12 @@ __device__ __forceinline__ float chunk_terms(const uint4 q, const float* src, fl
     return a0 + a1;
 }
 
-// One piece of a wave's share of a round: block b, round [r0, r1), the
-// wave's first sweep s0 and its sweeps in this piece np (0..kStreamSweeps),
-// the piece's index in the share and the pieces per share; b == nblk: none.
+// One piece of a wave's share of a round: block b (whose run ends at re),
+// round [r0, r1), the wave's first sweep s0 and its sweeps in this piece np
+// (0..kStreamSweeps), the piece's index in the share and the pieces per
+// share; b == nblk: none.
 struct StreamPiece {
-    int b, r0, r1, s0, np, j, npieces;
+    int b, re, r0, r1, s0, np, j, npieces;
 };
 
 template <int BLOCK, bool SGJ>
@@ -718,21 +719,25 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
     const int nblk = d.nblk;
     const float g = d.g;
     float* s_self = s_vd + C;                   // row r's own voltage at C + (r mod 256)
-    float* s_chunk = s_self + kSelfSlots;       // per-chunk sums of one round
-    int* s_off = reinterpret_cast<int*>(s_chunk + kStreamRound);   // [b][i]: chunk start of row row0 + i
+    float* s_sums = s_self + kSelfSlots;        // per-chunk sums of a round, rounds alternating buffers
+    int* s_off = reinterpret_cast<int*>(s_sums + 2 * kStreamRound);   // [b][i]: chunk start of row row0 + i
     const int64_t n1 = n + 1;
     const int32_t* cb = a.cb + d.cb_off;
     const uint4* ch = a.chk + d.chkb_off;
     const uint8_t* tag = a.rtag + d.chkb_off;
     const int nrows = t.row1 - t.row0;
     const int nr1 = nrows + 1;
-    for (int k = threadIdx.x; k < nrows; k += BLOCK)
-        s_self[(t.row0 + k) & (kSelfSlots - 1)] = vd[t.row0 + k] * kPreScale;
-    for (int k = threadIdx.x; k < nblk * nr1; k += BLOCK) {
+    // the tables' loads first (so that storing them waits for them only)
+    constexpr int TBL = (kStreamMaxBlocks * (kSelfSlots + 1) + BLOCK - 1) / BLOCK;
+    const int ntab = nblk * nr1;
+    const float selfv = vd[t.row0 + min((int)threadIdx.x, nrows - 1)];
+    int offv[TBL];
+#pragma unroll
+    for (int u = 0; u < TBL; ++u) {
+        const int k = min((int)threadIdx.x + u * BLOCK, ntab - 1);
         const int b = k / nr1, i = k - b * nr1;
-        s_off[k] = cb[b * n1 + t.row0 + i];
+        offv[u] = cb[b * n1 + t.row0 + i];
     }
-    __syncthreads();
     const int orow = threadIdx.x / OWN, oq = threadIdx.x % OWN;
     const bool owner = orow < nrows;
     float rowacc = 0.0f;
@@ -741,24 +746,24 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
     // branches on them are scalar: the loads and stores of the pipeline stay
     // in straight-line code and wait only for what they use).
     auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
-    auto piece_of = [&](int b, int r0, int r1, int j) {
+    auto piece_of = [&](int b, int re, int r0, int r1, int j) {
         const int nsw = (r1 - r0 + 63) / 64;                 // sweeps of the round
         const int q = (nsw + W - 1) / W;                     // sweeps per wave
         const int s0 = min(nsw, wave * q + j * SW);
         const int np = min(SW, min(nsw, wave * q + q) - s0);
-        return StreamPiece{b, r0, r1, s0, max(np, 0), j, (q + SW - 1) / SW};
+        return StreamPiece{b, re, r0, r1, s0, max(np, 0), j, (q + SW - 1) / SW};
     };
     auto first_round_from = [&](int b0) {    // the first piece of the first round of block b0 or later
         for (int b = b0; b < nblk; ++b) {
             const int r0 = uni(s_off[b * nr1]), re = uni(s_off[b * nr1 + nrows]);
-            if (r0 < re) return piece_of(b, r0, min(re, r0 + kStreamRound), 0);
+            if (r0 < re) return piece_of(b, re, r0, min(re, r0 + kStreamRound), 0);
         }
-        return StreamPiece{nblk, 0, 0, 0, 0, 0, 1};
+        return StreamPiece{nblk, 0, 0, 0, 0, 0, 0, 1};
     };
+    // within a block from registers only; LDS is read at block changes
     auto next_piece = [&](const StreamPiece& p) {
-        if (p.j + 1 < p.npieces) return piece_of(p.b, p.r0, p.r1, p.j + 1);
-        const int re = uni(s_off[p.b * nr1 + nrows]);
-        if (p.r1 < re) return piece_of(p.b, p.r1, min(re, p.r1 + kStreamRound), 0);
+        if (p.j + 1 < p.npieces) return piece_of(p.b, p.re, p.r0, p.r1, p.j + 1);
+        if (p.r1 < p.re) return piece_of(p.b, p.re, p.r1, min(p.re, p.r1 + kStreamRound), 0);
         return first_round_from(p.b + 1);
     };
     auto next_block = [&](int b) {     // the next block with chunks after b, nblk if none
@@ -778,10 +783,10 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
             tg[i] = tp[i * 64];
         }
     };
-    auto compute = [&](const uint4 (&q)[SW], const uint32_t (&tg)[SW], const StreamPiece& p) {
+    auto compute = [&](const uint4 (&q)[SW], const uint32_t (&tg)[SW], const StreamPiece& p, float* sums) {
         const int slot = p.s0 * 64 + lane;                  // this lane's slot of sweep 0
         const int m = p.r1 - p.r0;
-        float* dst = s_chunk + slot;
+        float* dst = sums + slot;
         if (p.np == SW && (p.s0 + SW) * 64 <= m) {
             // whole sweeps only (all but a round's last piece): one basic
             // block, in which the scheduler overlaps two sweeps at a time
@@ -800,11 +805,11 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
             }
         }
     };
-    auto combine = [&](const StreamPiece& p) {
+    auto combine = [&](const StreamPiece& p, const float* sums) {
         float part = 0.0f;
         if (owner) {
             const int rlo = max(s_off[p.b * nr1 + orow], p.r0), rhi = min(s_off[p.b * nr1 + orow + 1], p.r1);
-            for (int c = rlo + oq; c < rhi; c += OWN) part += s_chunk[c - p.r0];
+            for (int c = rlo + oq; c < rhi; c += OWN) part += sums[c - p.r0];
         }
         rowacc += wave_sum_xor(part, OWN);
     };
@@ -826,41 +831,63 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
     constexpr int NS = kStreamSets;
     uint4 q[NS][SW];
     uint32_t tg[NS][SW];
-    StreamPiece prev{-1, 0, 0, 0, 0, 0, 1};      // the round being summed last (combined at the next round)
-    StreamPiece cur = first_round_from(0);       // the piece summed next
-    StreamPiece ahead = cur;                     // the last piece whose loads are queued
+    StreamPiece prev{-1, 0, 0, 0, 0, 0, 0, 1};   // the round summed last (combined at the next round's start)
     int staged = -1;
-    if (cur.b < nblk) {
-        load_voltages(cur.b);
-        load(q[0], tg[0], cur);
-#pragma unroll
-        for (int k = 1; k < NS - 1; ++k) {
-            const StreamPiece nx = ahead.b < nblk ? next_piece(ahead) : ahead;
-            ahead = nx;
-            if (ahead.b < nblk) load(q[k], tg[k], ahead);
+    // the first piece when block 0 has chunks: its loads go out before the
+    // tables are stored (the bounds from global memory; else after them)
+    StreamPiece cur{nblk, 0, 0, 0, 0, 0, 0, 1};
+    {
+        const int g0 = uni(cb[t.row0]), g1 = uni(cb[t.row1]);
+        if (nblk > 0 && g0 < g1) {
+            cur = piece_of(0, g1, g0, min(g1, g0 + kStreamRound), 0);
+            load_voltages(0);
+            load(q[0], tg[0], cur);
         }
     }
+    if (threadIdx.x < nrows) s_self[(t.row0 + threadIdx.x) & (kSelfSlots - 1)] = selfv * kPreScale;
+#pragma unroll
+    for (int u = 0; u < TBL; ++u)
+        if ((int)threadIdx.x + u * BLOCK < ntab) s_off[threadIdx.x + u * BLOCK] = offv[u];
+    __syncthreads();
+    if (cur.b >= nblk) {
+        cur = first_round_from(1);
+        if (cur.b < nblk) {
+            load_voltages(cur.b);
+            load(q[0], tg[0], cur);
+        }
+    }
+    StreamPiece ahead = cur;                     // the last piece whose loads are queued
+#pragma unroll
+    for (int k = 1; k < NS - 1; ++k) {
+        const StreamPiece nx = ahead.b < nblk ? next_piece(ahead) : ahead;
+        ahead = nx;
+        if (ahead.b < nblk) load(q[k], tg[k], ahead);
+    }
+    int rb = 0;                                  // the sums buffer of the current round
     // Sum the piece in set u while set u - 1 (summed last) loads the piece
     // NS - 1 ahead. Every wave has the same pieces per round, so the barriers
-    // at round starts match.
+    // at round starts match. Rounds alternate between two sums buffers: the
+    // previous round's rows are added while the next block is staged.
     auto step = [&](uint4 (&qx)[SW], uint32_t (&tx)[SW], uint4 (&qz)[SW], uint32_t (&tz)[SW]) {
         if (ahead.b < nblk) {
             ahead = next_piece(ahead);
             if (ahead.b < nblk) load(qz, tz, ahead);
         }
         if (cur.j == 0) {
-            __syncthreads();                    // the previous round's slots are written
-            if (prev.b >= 0) combine(prev);
-            __syncthreads();                    // ... and read; earlier voltages no longer needed
+            __syncthreads();                    // the previous round is summed; its voltages are done with
+            if (prev.b >= 0) {
+                rb ^= 1;
+                combine(prev, s_sums + (rb ^ 1) * kStreamRound);
+            }
             if (staged != cur.b) {
                 store_voltages();
                 staged = cur.b;
-                __syncthreads();
+                __syncthreads();                // the voltages are staged; the previous round's rows added
                 const int nb = next_block(cur.b);   // its voltages load during this block
                 if (nb < nblk) load_voltages(nb);
             }
         }
-        compute(qx, tx, cur);
+        compute(qx, tx, cur, s_sums + rb * kStreamRound);
         prev = cur;
         cur = next_piece(cur);
     };
@@ -871,7 +898,7 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
         }
     }
     __syncthreads();
-    if (prev.b >= 0) combine(prev);
+    if (prev.b >= 0) combine(prev, s_sums + rb * kStreamRound);
     if (owner && oq == 0) s_ig[orow] = g * rowacc * kInvPreScale;
 }
 

@@ -177,3 +177,11 @@ def test_stream_path_bytes_add_the_row_tags():
     rp, col = _csr(4, [(i, j) for i in range(4) for j in range(4) if i != j])
     net = I.Network(n=4, conn="csr", g=0.04, row_ptr=rp, col=col)
     assert bench.algorithmic_bytes([net], ["csr_stream"]) == bench.algorithmic_bytes([net]) + 12 // 8
+
+
+def test_stream_kernel_variant_name():
+    info = {"step_mode": 0, "n_tiles_wide": 256, "n_tiles": 256, "wide_threads": 1024}
+    rp, col = _csr(3, [(0, 1), (1, 0)])
+    plain = I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)
+    assert bench.step_kernel_name(info, [plain], ["csr_stream"]) == "infoli::k_step<1024, 3>"
+    assert bench.step_kernel_name(info, [plain], ["csr_chunked"]) == "infoli::k_step<1024, 2>"
