@@ -98,7 +98,8 @@ def tuned_config(info, sim, nets):
             "lanes_per_row": info["lanes_per_row"], "tile_rows": info["tile_rows"],
             "gap_paths": sorted(set(sim.gap_path(k)[0] for k in range(len(nets)))),
             "step_kernel": step_kernel_name(info, nets, [sim.gap_path(k)[0] for k in range(len(nets))]),
-            "tuned_networks": info["tuned"], "tune_cached_networks": info["tune_cached"]}
+            "tuned_networks": info["tuned"], "tune_cached_networks": info["tune_cached"],
+            "csr_stream_networks": info["n_stream"], "tune_mode": info["tune_mode"]}
 
 
 WORKLOADS = {

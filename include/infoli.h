@@ -285,6 +285,13 @@ typedef struct infoli_info {
     int32_t n_bitmap;           /* CSR networks on the coupling-bitmap path             */
     int32_t n_blocked;          /* CSR networks on the column-blocked path              */
     int32_t wide_threads;       /* workgroup size of the wide launch group (512 or 1024) */
+    int32_t n_stream;           /* CSR networks on the chunk stream (CSR_STREAM path)    */
+    int32_t tune_mode;          /* whole-step launch arrangement the tuner chose, -1 when
+                                   the shapes were not tuned (bits: 1 every class in its
+                                   256-thread shape, 2 launch groups one after the other,
+                                   4 no chunked 256-thread gathers, 8 every class in its
+                                   1024-thread shape, 16 wide group of 512 threads, 32
+                                   every class with a bitmap shape on it)                 */
 } infoli_info;
 infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
 

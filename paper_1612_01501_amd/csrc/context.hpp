@@ -116,6 +116,7 @@ struct infoli_ctx {
     std::vector<double> deg_of;     // mean gap-junction degree per network
     int tuned = 0;                  // networks whose tiles came from timing runs
     int tune_cached = 0;            // networks whose tiles came from the tuning cache
+    int tune_mode = -1;             // whole-step launch mode the tuner chose (-1: none)
 
     // device memory
     std::vector<void*> allocs;

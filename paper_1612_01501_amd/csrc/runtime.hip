@@ -690,6 +690,33 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
     return ms / reps;
 }
 
+// Timings within kTieMargin of the fastest count as equal; among those the
+// choice follows a fixed preference, so that runs on different boxes (and
+// timing noise) agree.
+constexpr float kTieMargin = 0.03f;
+
+// Preference among equally fast shapes: chunk stream, bitmap, chunked
+// gathers, gathers, column blocks; then the wider workgroup; then fewer
+// lanes per row, fewer rows, no LDS staging.
+int64_t pref_key(const TuneChoice& t) {
+    static const int rank[5] = {3, 1, 4, 2, 0};   // by bm: 0 gathers .. 4 stream
+    return ((((int64_t)rank[t.bm] * 2 + (t.block == 256 ? 1 : 0)) * 1024 + t.L) * 1024 + t.R) * 2 + t.lds;
+}
+
+// The preferred entry among those within kTieMargin of the fastest; none
+// (block 0) when v is empty.
+TuneChoice pick_shape(const std::vector<std::pair<float, TuneChoice>>& v) {
+    TuneChoice none{0, 0, 0, 0, 0};
+    if (v.empty()) return none;
+    float best = 1e30f;
+    for (const auto& e : v) best = std::min(best, e.first);
+    const TuneChoice* pick = nullptr;
+    for (const auto& e : v)
+        if (e.first <= best * (1.0f + kTieMargin) && (!pick || pref_key(e.second) < pref_key(*pick)))
+            pick = &e.second;
+    return *pick;
+}
+
 void apply_choice(infoli_ctx* c, const std::vector<int>& ks, TuneChoice best) {
     for (int k : ks)   // a cached choice this context cannot honour falls back to gathers
         if ((best.bm == 1 && c->inst[k].bits_off < 0) || (best.bm == 2 && c->inst[k].blk_off < 0) ||
@@ -804,29 +831,21 @@ void autotune(infoli_ctx* c) {
                 n = std::max(n, c->inst[k].n);
                 deg = std::max(deg, c->deg_of[k]);
             }
-            float best_ms = 1e30f, best256_ms = 1e30f, best256nc_ms = 1e30f, best1024_ms = 1e30f;
-            std::vector<std::pair<float, TuneChoice>> timed;
+            std::vector<std::pair<float, TuneChoice>> timed, all, all256, all256nc, all1024;
             bool all_rows = c->d_ca != nullptr;    // every network of the class has the chunked rows layout
             for (int k : ks) all_rows = all_rows && c->inst[k].ca_off >= 0;
+            // every shape timed; the class's choices picked at the end (ties
+            // by the fixed preference), best256 also as the search goes on
             auto consider = [&](const TuneChoice& t) {
                 const float ms = time_shape(c, ks, t, d_tmp);
-                if (t.block == 256) timed.push_back({ms, t});
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
+                all.push_back({ms, t});
+                if (t.block == 256) {
+                    timed.push_back({ms, t});
+                    all256.push_back({ms, t});
+                    if (t.bm != 3) all256nc.push_back({ms, t});
+                    best256 = pick_shape(all256);
                 }
-                if (t.block == 256 && ms < best256_ms) {
-                    best256_ms = ms;
-                    best256 = t;
-                }
-                if (t.block == 256 && t.bm != 3 && ms < best256nc_ms) {
-                    best256nc_ms = ms;
-                    best256nc = t;
-                }
-                if (t.block == 1024 && ms < best1024_ms) {
-                    best1024_ms = ms;
-                    best1024 = t;
-                }
+                if (t.block == 1024) all1024.push_back({ms, t});
                 if (t.bm == 1) (t.block == 256 ? bm256 : bm1024) = t;
             };
             for (int L = 4; L <= 256; L *= 2) {
@@ -883,6 +902,10 @@ void autotune(infoli_ctx* c) {
                         consider(TuneChoice{L, R, 0, 2, 1024});
                     }
                 }
+            best = pick_shape(all);
+            if (!all256.empty()) best256 = pick_shape(all256);
+            if (!all256nc.empty()) best256nc = pick_shape(all256nc);
+            if (!all1024.empty()) best1024 = pick_shape(all1024);
             std::stable_sort(timed.begin(), timed.end(),
                              [](const auto& x, const auto& y) { return x.first < y.first; });
             for (const auto& tt : timed) {
@@ -976,8 +999,30 @@ void autotune(infoli_ctx* c) {
                 if ((m & 16) && c->grp[1].tiles.empty()) continue;
                 mode_ms[m] = std::min(mode_ms[m], time_step(c, !(m & 2)));
             }
-        for (int m = 1; m < kStepModes; ++m)
-            if (mode_ms[m] < mode_ms[mode]) mode = m;
+        // the modes within 10 % of the fastest timed again, interleaved,
+        // three more rounds; then within kTieMargin the lowest mode number
+        // (the plainer arrangement) wins
+        float fastest = 1e30f;
+        for (int m = 0; m < kStepModes; ++m) fastest = std::min(fastest, mode_ms[m]);
+        std::vector<int> close;
+        for (int m = 0; m < kStepModes; ++m)
+            if (mode_ms[m] <= 1.10f * fastest) close.push_back(m);
+        if (close.size() > 1)
+            for (int round = 0; round < 3; ++round)
+                for (int m : close) {
+                    apply_all(m);
+                    c->grp[1].block = wide_block(m);
+                    finalize_tiles(c);
+                    mode_ms[m] = std::min(mode_ms[m], time_step(c, !(m & 2)));
+                }
+        fastest = 1e30f;
+        for (int m : close) fastest = std::min(fastest, mode_ms[m]);
+        mode = close.empty() ? 0 : close.back();
+        for (int m : close)
+            if (mode_ms[m] <= fastest * (1.0f + kTieMargin)) {
+                mode = m;
+                break;
+            }
         // Refinement in the whole step: a class timed alone can rank shapes
         // differently from the full step. Every class with at least 5 % of
         // the step's pairs tries its fastest 256-thread alternatives with
@@ -1017,7 +1062,7 @@ void autotune(infoli_ctx* c) {
                     finalize_tiles(c);
                     alt_ms = std::min(alt_ms, time_step(c, !(mode & 2)));
                 }
-                if (alt_ms < 0.98f * cur_ms) refine[o.second] = a;
+                if (alt_ms < (1.0f - kTieMargin) * cur_ms) refine[o.second] = a;
                 else apply_choice(c, classes[key], now);
             }
         }
@@ -1036,6 +1081,7 @@ void autotune(infoli_ctx* c) {
         }
     }
     c->fork_groups = !(mode & 2);
+    c->tune_mode = mode;
 }
 
 void launch_persistent(infoli_ctx* c, int64_t n_steps, bool dry = false);
@@ -1773,9 +1819,11 @@ infoli_status infoli_get_info(const infoli_ctx* ctx, infoli_info* info) {
     info->tune_cached = ctx->tune_cached;
     info->n_tiles_wide = (int32_t)ctx->grp[1].tiles.size();
     info->wide_threads = ctx->grp[1].block;
+    info->tune_mode = ctx->tune_mode;
     for (const InstDesc& d : ctx->inst) {
         info->n_bitmap += d.conn == CONN_CSR && d.bitmap;
         info->n_blocked += d.conn == CONN_CSR && d.blocked;
+        info->n_stream += d.conn == CONN_CSR && d.blocked && d.stream;
     }
     return INFOLI_OK;
 }

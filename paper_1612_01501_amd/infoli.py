@@ -86,7 +86,8 @@ class Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("tuned", ctypes.c_int32),
                 ("tune_cached", ctypes.c_int32), ("n_tiles_wide", ctypes.c_int32),
                 ("n_bitmap", ctypes.c_int32), ("n_blocked", ctypes.c_int32),
-                ("wide_threads", ctypes.c_int32)]
+                ("wide_threads", ctypes.c_int32), ("n_stream", ctypes.c_int32),
+                ("tune_mode", ctypes.c_int32)]
 
 
 class TrainCfg(ctypes.Structure):
