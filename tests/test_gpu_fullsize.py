@@ -4,7 +4,7 @@ shapes, steps replayed from HIP graphs).
 
 Bounds as in test_gpu_parity.py: per state variable, max |gpu - oracle_f32| /
 max |oracle_f32| <= max(1e-4, 2 x the fp32 oracle's distance from fp64), and
-against fp64 <= max(1e-4, 1.25 x that distance); spike counts within +-1 and
+against fp64 <= max(1e-4, 1.5 x that distance); spike counts within +-1 and
 matched spike times within 0.1 ms.
 
 Explicit Euler on the coupling is stable while dt * lambda_max / C_m <= 2
@@ -23,7 +23,7 @@ import numpy as np
 import pytest
 
 from paper_1612_01501_amd import inputs as I
-from test_gpu_parity import check_state_bounds, compare_spikes, gap_bound, per_var_error
+from test_gpu_parity import check_state_bounds, compare_spikes, gap_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -192,26 +192,33 @@ def test_config4_plain_full_size(infoli, o32, o64):
 
 
 def test_config3_unstable_networks_scaled_spikes(infoli, o32, o64):
-    """The batch networks above the Euler limit, degree-scaled, stepped as
-    one batch for 2,000 steps under their pulses plus the 25 ms validation
-    pulse: states against the oracle and spikes of every cell."""
+    """Eight of the batch networks above the Euler limit, degree-scaled,
+    stepped as one batch for 2,000 steps under a 6 uA/cm^2 pulse held 25 ms
+    (steps 400-900), which makes every cell fire: all state variables
+    against both oracles and the spikes of every cell.
+
+    Their own pulses (5 ms, 2-10 uA/cm^2) fire none of the scaled cells, and
+    holding the strongest of them for 25 ms drives the model itself past
+    what forward Euler at dt = 0.05 ms follows: the axon voltage of the fp64
+    oracle leaves any physical range after ~150 steps of a 9.6 uA/cm^2
+    drive, so the drive is the one the 4,096-cell spike check uses."""
     nets = [n for n in I.config3() if dt_lambda(n) > 2.0]
     assert len(nets) > 40
     nets = [companion(n) for n in nets[:8]]
     for n in nets:
         assert dt_lambda(n) <= 2.0
-        n.pulses = [I.Pulse(400, 900, n.pulses[0].amplitude)]
+        n.pulses = [I.Pulse(400, 900, 6.0)]
     x0s = [infoli.initial_state(n) for n in nets]
     sim, got, spikes, info, paths = run_batch(infoli, nets, x0s, 2000, 100)
     sim.close()
+    note(f"c3 scaled batch on {sorted(set(paths))}")
     fired = 0
     for k, net in enumerate(nets):
         ref = o32.run(net, 2000, x0=x0s[k], trace_every=100, trace_cells=net.n)
         r64 = o64.run(net, 2000, x0=x0s[k].astype(np.float64), trace_every=100, trace_cells=net.n)
-        e32 = per_var_error(got[k][:10], ref["trace"][:10])
-        floor = per_var_error(ref["trace"][:10], r64["trace"][:10])
-        assert np.all(e32 <= np.maximum(1e-4, 2 * floor)), (net.label, e32, floor)
+        check_state_bounds(got[k], ref["trace"], r64["trace"], net.label)
         compare_spikes(spikes[k][0], spikes[k][1], ref["counts"], ref["times"], 64)
+        assert np.all(ref["counts"] >= 1), net.label
         fired += int(ref["counts"].sum())
         note(f"c3 {net.label}: {int(ref['counts'].sum())} spikes checked")
-    assert fired > 0
+    assert fired > 8 * 851

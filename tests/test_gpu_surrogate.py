@@ -42,22 +42,106 @@ def test_mlp_forward_matches_oracle(infoli, batch):
 
 @pytest.mark.parametrize("batch", [64, 4096])
 def test_mlp_gradients_match_oracle(infoli, batch):
-    """GPU loss and gradients against the emulated-BF16 oracle: relative error
-    (2-norm over each parameter block) <= 1e-3."""
+    """GPU loss and gradients against the emulated-BF16 oracle, element by
+    element: |g - g_ref| <= 1e-3 x the largest |g_ref| of the element's
+    parameter block (the scale floor: BF16 rounding points that fp32 and
+    fp64 sums send different ways move single elements by up to ~1e-4 of
+    that scale), and the 2-norm of each block's error <= 1e-3 of its own."""
     w = _params(5)
     x, t = I.mlp_batch(batch, 6)
     loss, g = infoli.mlp_loss_grad(w, x, t)
     rl, rg = M.loss_and_grad(w.astype(np.float64), x, t, bf16=True)
     assert loss == pytest.approx(rl, rel=1e-4)
     gp, rp = M.unpack(g.astype(np.float64)), M.unpack(rg)
-    worst = 0.0
+    worst = worst_el = 0.0
     for name, _ in M.SHAPES:
-        a, b = gp[name][:14] if name in ("W3", "b3") else gp[name], rp[name][:14] if name in ("W3", "b3") else rp[name]
-        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        a, b = gp[name], rp[name]
+        if name in ("W3", "b3"):                    # rows 14, 15 are padding outputs
+            assert np.all(a[14:] == 0), name
+            a, b = a[:14], b[:14]
+        scale = np.abs(b).max()
+        assert scale > 0, name
+        el = np.abs(a - b) / scale
+        worst_el = max(worst_el, float(el.max()))
+        assert np.all(el <= 1e-3), (name, np.unravel_index(np.argmax(el), el.shape), el.max())
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
         worst = max(worst, rel)
         assert rel <= 1e-3, (name, rel)
-    assert np.all(gp["W3"][14:] == 0) and np.all(gp["b3"][14:] == 0)
-    print(f"gradients B={batch}: worst block relative error {worst:.2e}")
+    print(f"gradients B={batch}: worst element error / block scale {worst_el:.2e}, "
+          f"worst block relative error {worst:.2e}")
+
+
+def _bf16_other(v):
+    """For float32 values v, the BF16 value on the far side of v from its
+    nearest BF16 value (the one a rounding tie can go to instead)."""
+    r = M.bf16_round(v)
+    u = r.view(np.uint32).astype(np.int64)
+    away = np.abs(v) > np.abs(r)
+    o = np.where(away, u + 0x10000, u - 0x10000).astype(np.uint32)
+    return r, o.view(np.float32)
+
+
+def test_surrogate_candidates_match_oracle(infoli, o32):
+    """One macro step in which no cell is checked and every cell passes the
+    guards, so each cell takes its MLP candidate x + out_std * y + out_mean,
+    y = MLP((feature - in_mean) * in_rstd) over the 14 states, the gap current
+    and the evoked input. Compared element by element with the oracle MLP
+    (emulated BF16) fed the fp32 oracle's state, gap current and input, on
+    1,000 cells (a ragged last wave) of a 50-degree network. Distinct
+    per-feature normalisation constants make a permuted feature or output
+    fail. The GPU's gap current differs from the oracle's by up to the fp32
+    gap bound; where that can move the BF16 rounding of the normalised gap
+    feature (the oracle's value within that distance of a rounding tie) the
+    candidate may match the oracle at either BF16 neighbour."""
+    from test_gpu_parity import gap_bound
+    net = I.config4(seed=3, n=1000, degree=50.0)
+    xs = o32.run(net, 60)["x"]                        # gates spread by the jitter
+    ig = o32.gap(net, xs[VD])
+    ia = o32.iapp(net, 0)
+    feats = np.concatenate([xs, ig[None], ia[None]]).T.astype(np.float32)      # [n][16]
+    mean = feats.astype(np.float64).mean(axis=0)
+    std = feats.astype(np.float64).std(axis=0)
+    rstd = 1.0 / np.maximum(std, 1e-3 * np.maximum(np.abs(mean), 1.0))
+    k = np.arange(16)
+    out_mean = 1e-3 * (k - 7.5)
+    out_std = 0.01 * (1.0 + 0.25 * k)
+    norm = np.concatenate([mean, rstd, out_mean, out_std]).astype(np.float32)
+    w = _params(11)
+
+    sim = infoli.Simulator(net, init_states=[xs], step_mode="graph")
+    sim.surrogate_set(w, norm)
+    r = sim.step_surrogate(1, mode="mlp", sample_every=0)
+    got = sim.read_state(0).astype(np.float64).T                             # [n][14]
+    sim.close()
+    assert r["checked"] == 0 and r["guarded"] == 0 and r["plain_cell_macro_steps"] == 0, r
+
+    f32 = np.float32
+    nm, nr = norm[:16], norm[16:32]
+    xn = ((feats - nm) * nr).astype(np.float32)        # the kernel's order: (raw - mean) * rstd
+    wd = w.astype(np.float64)
+
+    def candidate(xin):
+        y, _ = M.forward(wd, xin, bf16=True)
+        return y, xs.T.astype(np.float64) + (y[:, :14] * norm[48:62] + norm[32:46])
+
+    y, ref = candidate(xn)
+    tol = 2e-3 * (1.0 + np.abs(y[:, :14])) * norm[48:62] + 2 * np.finfo(f32).eps * np.abs(ref)
+    ok = np.abs(got - ref) <= tol
+    # the gap feature near a BF16 rounding tie: either neighbour
+    r14, o14 = _bf16_other(xn[:, 14])
+    mid = 0.5 * (r14.astype(np.float64) + o14)
+    near = np.abs(xn[:, 14] - mid) <= 1.01 * gap_bound(net, xs[VD]) * nr[14] + 4 * np.finfo(f32).eps * np.abs(mid)
+    alt = xn.copy()
+    alt[:, 14] = o14
+    y2, ref2 = candidate(alt)
+    ok2 = np.abs(got - ref2) <= 2e-3 * (1.0 + np.abs(y2[:, :14])) * norm[48:62] + 2 * np.finfo(f32).eps * np.abs(ref2)
+    cell_ok = np.all(ok, axis=1) | (near & np.all(ok2, axis=1))
+    bad = np.nonzero(~cell_ok)[0]
+    err = (np.abs(got - ref) / tol).max()
+    print(f"surrogate candidates: max error / bound {err:.2e}, {int(near.sum())} cells near a gap-feature tie")
+    assert bad.size == 0, (bad[:8], (np.abs(got - ref) / tol)[bad[:8]].max(axis=1))
+    # the step moved every cell by its MLP increment (not a copy of the state)
+    assert np.all(np.any(got != xs.T, axis=1))
 
 
 def test_adam_step_matches_oracle(infoli):
