@@ -437,6 +437,30 @@ infoli_status infoli_mlp_loss_grad(const float *params, const float *x, const fl
 infoli_status infoli_mlp_adam_step(float *params, float *m, float *v, const float *grad, int64_t t,
                                    float lr, float beta1, float beta2, float eps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the loss and
+ * gradient of infoli_mlp_loss_grad on device data, queued on `stream`
+ * (a hipStream_t; NULL = the null stream) and not waited for. Same kernels
+ * and summation order, so the results equal infoli_mlp_loss_grad's bit for
+ * bit.
+ *   d_params [INFOLI_MLP_PARAMS], d_x and d_t [batch][16] row-major fp32,
+ *   d_grad [INFOLI_MLP_PARAMS] (written), d_loss [1] (written; may be NULL):
+ *   device memory of the current device, owned by the caller, left in place
+ *   until the queued work has run.
+ *   batch: a multiple of 16, at most 8192 (else INFOLI_E_INVALID_ARG, with
+ *   the limit in the message). Host or other-device pointers:
+ *   INFOLI_E_INVALID_ARG; nothing is queued on any error.
+ * The call allocates nothing: its staging (bf16 weights, split-K partial
+ * gradients, transposed activations; 10,284,800 bytes) is a static device
+ * array that each GPU holds from the first call on it until the process
+ * ends. Every call on one GPU uses that one array: calls whose queued work
+ * overlaps on a GPU (two streams, two threads) race and give wrong results;
+ * serialise them. Each call writes all the staging it reads, so nothing
+ * from an earlier call carries over. The parameters are not checked for
+ * NaN or infinity (they stay on the device). */
+infoli_status infoli_mlp_loss_grad_noalloc(const float *d_params, const float *d_x, const float *d_t,
+                                           int32_t batch, float *d_loss, float *d_grad, void *stream);
+
 /* Names of state variables ("Vd", "Ca", ...); NULL when out of range. */
 const char *infoli_state_var_name(int32_t v);
 

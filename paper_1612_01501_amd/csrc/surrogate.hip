@@ -4,6 +4,8 @@
 #include "context.hpp"
 #include "surrogate_kernel.hpp"
 
+#include <mutex>
+
 using namespace infoli_rt;
 
 namespace {
@@ -139,6 +141,95 @@ void launch_macro(infoli_ctx* c, hipStream_t st, const infoli_drift_cfg& dc, int
     const unsigned lblocks = (unsigned)std::min<int64_t>((cells + 63) / 64, 2048);
     hipLaunchKernelGGL(k_plain_list, dim3(lblocks), dim3(kListBlock), 0, st, a, s, c->state[from],
                        c->state[from ^ 1], step0);
+}
+
+// ---------------------------------------------------------------- staging without allocation
+// Largest batch of infoli_mlp_loss_grad_noalloc and the staging memory it
+// needs: the bf16 weights, the split-K partial gradients, the six transposed
+// activation buffers and the per-wave loss sums, each start 256-byte aligned.
+constexpr int32_t kNoAllocMaxBatch = 8192;
+
+constexpr size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+constexpr size_t staging_bytes(int32_t batch) {
+    return round256(sizeof(uint16_t) * kNumParams) + round256(sizeof(float) * kNumParams * kGradSplits) +
+           2 * round256(sizeof(uint16_t) * 16 * (size_t)batch) + 4 * round256(sizeof(uint16_t) * kHid * (size_t)batch) +
+           round256(sizeof(float) * (size_t)(batch / 16));
+}
+
+constexpr size_t kScratchBytes = staging_bytes(kNoAllocMaxBatch);     // 10,284,800 bytes
+
+// Carves the staging buffers of one call out of `base` (device address).
+struct Staging {
+    uint16_t* wb;
+    float* part;
+    TrainBufs tb;
+};
+
+Staging carve(unsigned char* base, int32_t batch) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base + off;
+        off += round256(bytes);
+        return p;
+    };
+    Staging st;
+    st.wb = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * kNumParams));
+    st.part = reinterpret_cast<float*>(take(sizeof(float) * kNumParams * kGradSplits));
+    st.tb.xT = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * 16 * (size_t)batch));
+    st.tb.dyT = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * 16 * (size_t)batch));
+    st.tb.h1T = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * kHid * (size_t)batch));
+    st.tb.h2T = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * kHid * (size_t)batch));
+    st.tb.dz2T = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * kHid * (size_t)batch));
+    st.tb.dz1T = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * kHid * (size_t)batch));
+    st.tb.loss_part = reinterpret_cast<float*>(take(sizeof(float) * (size_t)(batch / 16)));
+    if (off != staging_bytes(batch) || off > kScratchBytes) fail(INFOLI_E_DEVICE, "staging layout mismatch");
+    return st;
+}
+
+}  // namespace
+
+// Staging memory of infoli_mlp_loss_grad_noalloc: one copy on each GPU the
+// library runs on, held until the process ends. Host code never uses this
+// name as an address (on the host it names a stand-in): the device address
+// comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64] = {};     // per device ordinal; nullptr until looked up
+
+// Device address of `scratch` on the current device, looked up on the first
+// call there with that device current.
+unsigned char* scratch_on_current_device() {
+    int dev = -1;
+    HIPX(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) fail(INFOLI_E_DEVICE, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(INFOLI_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_addr[dev] = p;
+    }
+    return static_cast<unsigned char*>(g_scratch_addr[dev]);
+}
+
+// A caller's pointer must be device memory of the current device (a host
+// pointer would fault the kernels instead of failing here).
+void check_device_ptr(const void* p, int dev, const char* what) {
+    if (!p) fail(INFOLI_E_INVALID_ARG, "%s is NULL", what);
+    hipPointerAttribute_t at{};
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();            // leave no error for the next call to report
+        fail(INFOLI_E_INVALID_ARG, "%s is not device memory", what);
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        fail(INFOLI_E_INVALID_ARG, "%s is not device memory", what);
+    if (at.device != dev) fail(INFOLI_E_INVALID_ARG, "%s is on device %d, not the current device %d", what, at.device, dev);
 }
 
 }  // namespace
@@ -489,6 +580,33 @@ infoli_status infoli_mlp_adam_step(float* params, float* m, float* v, const floa
         HIPX(hipMemcpy(params, dp, sizeof(float) * kNumParams, hipMemcpyDeviceToHost));
         HIPX(hipMemcpy(m, dm, sizeof(float) * kNumParams, hipMemcpyDeviceToHost));
         HIPX(hipMemcpy(v, dv, sizeof(float) * kNumParams, hipMemcpyDeviceToHost));
+    });
+}
+
+infoli_status infoli_mlp_loss_grad_noalloc(const float* d_params, const float* d_x, const float* d_t, int32_t batch,
+                                           float* d_loss, float* d_grad, void* stream) {
+    return guarded(nullptr, [&] {
+        if (batch < 16 || batch % 16 != 0)
+            fail(INFOLI_E_INVALID_ARG, "batch %d: need a positive multiple of 16", batch);
+        if (batch > kNoAllocMaxBatch)
+            fail(INFOLI_E_INVALID_ARG, "batch %d exceeds the no-allocation limit of %d", batch, kNoAllocMaxBatch);
+        int dev = -1;
+        HIPX(hipGetDevice(&dev));
+        check_device_ptr(d_params, dev, "params");
+        check_device_ptr(d_x, dev, "x");
+        check_device_ptr(d_t, dev, "t");
+        check_device_ptr(d_grad, dev, "grad");
+        if (d_loss) check_device_ptr(d_loss, dev, "loss");
+        const Staging sg = carve(scratch_on_current_device(), batch);
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        hipLaunchKernelGGL(k_mlp_to_bf16, dim3((kNumParams + 255) / 256), dim3(256), 0, st, d_params, sg.wb);
+        hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((batch + 63) / 64), dim3(256), 0, st, d_params, sg.wb, d_x, d_t,
+                           (int64_t)batch, batch, 0ull, 0ull, sg.tb);
+        hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles * kGradSplits), dim3(64), 0, st, sg.tb, batch, sg.part,
+                           d_loss);
+        hipLaunchKernelGGL(k_grad_reduce, dim3((kNumParams + 255) / 256), dim3(256), 0, st, sg.part, kGradSplits,
+                           d_grad);
+        HIPX(hipGetLastError());
     });
 }
 

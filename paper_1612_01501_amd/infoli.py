@@ -36,6 +36,7 @@ EXPORTS = (
     "infoli_default_train_cfg", "infoli_default_drift_cfg", "infoli_surrogate_train",
     "infoli_surrogate_get", "infoli_surrogate_set", "infoli_step_surrogate",
     "infoli_mlp_forward", "infoli_mlp_loss_grad", "infoli_mlp_adam_step",
+    "infoli_mlp_loss_grad_noalloc",
 )
 MLP_PARAMS = 20752
 SURROGATE_MODE = {"mlp": 0, "plain_hold": 1}
@@ -167,6 +168,7 @@ def lib():
                                         ctypes.POINTER(DriftReport)]
     L.infoli_mlp_forward.argtypes = [_PF, _PF, ctypes.c_int32, _PF]
     L.infoli_mlp_loss_grad.argtypes = [_PF, _PF, _PF, ctypes.c_int32, _PF, _PF]
+    L.infoli_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp]
     L.infoli_mlp_adam_step.argtypes = [_PF, _PF, _PF, _PF, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, ctypes.c_float]
     for name in EXPORTS:
@@ -264,6 +266,14 @@ def mlp_loss_grad(params, x, t):
     loss = np.zeros(1, np.float32)
     _check(lib().infoli_mlp_loss_grad(_fptr(p), _fptr(xx), _fptr(tt), xx.shape[0], _fptr(loss), _fptr(g)))
     return float(loss[0]), g
+
+
+def mlp_loss_grad_noalloc(params_ptr: int, x_ptr: int, t_ptr: int, batch: int, loss_ptr: int,
+                          grad_ptr: int, stream: int = 0):
+    """infoli_mlp_loss_grad_noalloc on device addresses (e.g. a tensor's
+    data_ptr()); queued on `stream` (a HIP stream handle, 0 = null stream)."""
+    _check(lib().infoli_mlp_loss_grad_noalloc(params_ptr, x_ptr, t_ptr, int(batch), loss_ptr or None,
+                                              grad_ptr, stream or None))
 
 
 def mlp_adam_step(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
