@@ -91,6 +91,77 @@ def measured_traffic(key):
     return entry["bytes_per_launch"]
 
 
+def _counter_rows(run_dir):
+    """Per-dispatch values of one rocprofv3 --pmc run (its *counter_collection.csv
+    under run_dir): list of (dispatch id, kernel name, counter, value)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit(f"{run_dir}: expected one counter_collection.csv, found {len(files)}")
+    with open(files[0]) as fh:
+        return [(int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]))
+                for r in csv.DictReader(fh)]
+
+
+def _per_dispatch(rows, counter, name_part, last):
+    """The counter summed per dispatch over the `last` dispatches of the
+    kernel whose name contains name_part (the timed ones come last)."""
+    per = {}
+    for d, k, c, v in rows:
+        if c == counter and name_part in k:
+            per[d] = per.get(d, 0.0) + v
+    ids = sorted(per)
+    if last and len(ids) < last:
+        raise SystemExit(f"only {len(ids)} dispatches of {name_part!r} with {counter}, expected >= {last}")
+    ids = ids[-last:] if last else ids
+    return [per[d] for d in ids]
+
+
+def ingest_traffic(run_root):
+    """Turn the four counter runs under run_root (copy_fetch, copy_write: the
+    plain copy of --copy-probe-mb; fetch, write: the benchmark, whose JSON
+    lines are fetch.json and write.json) into the HBM bytes per step-kernel
+    launch, stored in the traffic file under the benchmark's traffic key."""
+    with open(os.path.join(run_root, "copy.json")) as fh:
+        copy = json.loads(fh.read().strip().splitlines()[-1])
+    runs = {}
+    for k in ("fetch", "write"):
+        with open(os.path.join(run_root, f"{k}.json")) as fh:
+            runs[k] = json.loads(fh.read().strip().splitlines()[-1])
+    key = runs["fetch"]["roofline"]["traffic_key"]
+    if runs["write"]["roofline"]["traffic_key"] != key:
+        raise SystemExit("the FETCH_SIZE and WRITE_SIZE runs ran different configurations")
+    r = runs["fetch"]
+    n = r["steps"] + r["warmup"]
+    kname = r["roofline"]["kernel"].replace("infoli::", "")
+    cf = _per_dispatch(_counter_rows(os.path.join(run_root, "copy_fetch")), "FETCH_SIZE", "", 0)
+    cw = _per_dispatch(_counter_rows(os.path.join(run_root, "copy_write")), "WRITE_SIZE", "", 0)
+    copy_kib = copy["copy_probe_bytes_read"] / 1024.0
+    # the copy is the largest dispatch of its run
+    fetch_factor = copy_kib / max(cf)
+    write_factor = copy_kib / max(cw)
+    f = _per_dispatch(_counter_rows(os.path.join(run_root, "fetch")), "FETCH_SIZE", kname, n)
+    w = _per_dispatch(_counter_rows(os.path.join(run_root, "write")), "WRITE_SIZE", kname, n)
+    fk, wk = float(np.mean(f)), float(np.mean(w))
+    entry = {"kernel": r["roofline"]["kernel"], "dispatches": [len(f), len(w)],
+             "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+             "fetch_factor": round(fetch_factor, 4), "write_factor": round(write_factor, 4),
+             "bytes_per_launch": int(round(1024.0 * (fk * fetch_factor + wk * write_factor))),
+             "algorithmic_bytes_per_launch": r["roofline"].get("algorithmic_bytes_per_launch"),
+             "kernel_sources_sha256": kernel_source_hash()}
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            table = json.load(fh)
+    except (OSError, ValueError):
+        table = {}
+    table[key] = entry
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps({key: entry}))
+
+
 def tuned_config(info, sim, nets):
     """What the library runs for these networks, as chosen at init."""
     return {"tiles": info["n_tiles"], "tiles_wide": info["n_tiles_wide"], "wide_threads": info["wide_threads"],
@@ -479,11 +550,13 @@ SURR_DT = 10000          # the surrogate comparison's length in dt, whatever --s
 SURR_SAMPLES = 25
 
 
-def surrogate_leg(net, x0, sim, torch, infoli, log):
+def surrogate_leg(net, x0, sim, torch, infoli, log, load=None, save=None):
     """Plain method against the trained MLP surrogate on the same network
     and initial state for SURR_DT time steps (SURR_DT / 4 macro steps), with
     the two ablations (held gap without MLP; MLP without fallback). `sim` is
-    the plain context, rewound to x0 at step 0 for each run."""
+    the plain context, rewound to x0 at step 0 for each run. `load`: take
+    the weights and normalisation from this .npz instead of training;
+    `save`: write the trained ones there."""
     V = [I.IDX_VD, I.IDX_VS, I.IDX_VA]
     every = SURR_DT // 4 // SURR_SAMPLES            # macro steps per sample
     cap = sim.spike_cap
@@ -498,9 +571,17 @@ def surrogate_leg(net, x0, sim, torch, infoli, log):
     ca, ta = sim.read_spikes(0)
     log("surrogate leg: plain reference done")
     t0 = time.perf_counter()
-    rep, _ = sim.surrogate_train(I.mlp_init_params(5000))
+    if load:
+        with np.load(load) as z:
+            sim.surrogate_set(z["params"], z["norm"])
+        rep = {"loaded_from": load}
+    else:
+        rep, _ = sim.surrogate_train(I.mlp_init_params(5000))
+        if save:
+            params, norm = sim.surrogate_get()
+            np.savez(save, params=params, norm=norm)
     train_wall = time.perf_counter() - t0
-    log(f"surrogate leg: trained ({train_wall:.1f} s)")
+    log(f"surrogate leg: {'loaded' if load else 'trained'} ({train_wall:.1f} s)")
 
     def run(**drift):
         sim.write_state(0, x0, 0)
@@ -592,7 +673,8 @@ def run_c4(nets, desc, steps, warmup, args, torch, infoli):
     x0 = infoli.initial_state(net)
     chunk = graph_chunk_for(steps)
     stream = torch.cuda.current_stream().cuda_stream
-    sim = infoli.Simulator(net, init_states=[x0], stream=stream, step_mode="graph", graph_chunk=chunk,
+    mode = "launch" if args.mode == "launch" else "graph"
+    sim = infoli.Simulator(net, init_states=[x0], stream=stream, step_mode=mode, graph_chunk=chunk,
                            csr_path=args.csr_path)
     info = sim.info()
     paths = [sim.gap_path(0)[0]]
@@ -610,16 +692,18 @@ def run_c4(nets, desc, steps, warmup, args, torch, infoli):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"c4: {desc}", "cells": cells, "gap_pairs_per_step": pairs,
-                   "step_mode": "graph", "graph_chunk": chunk, **tuned_config(info, sim, nets)},
+                   "step_mode": mode, "graph_chunk": chunk, **tuned_config(info, sim, nets)},
         "gap_pairs_per_s": pairs * steps / wall,
         "device_ms_per_step": dev_ms / steps,
         "roofline": roofline(nets, launch_s, kernel, paths),
         "stability": stability(nets),
     }
-    out["roofline"]["traffic"] = measured_traffic(traffic_key("c4", kernel, paths, info))
+    out["roofline"]["traffic_key"] = traffic_key("c4", kernel, paths, info)
+    out["roofline"]["traffic"] = measured_traffic(out["roofline"]["traffic_key"])
     log(f"c4: plain {dev_ms / steps * 1e3:.2f} us/step")
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_leg(net, x0, sim, torch, infoli, log)
+        out["surrogate"] = surrogate_leg(net, x0, sim, torch, infoli, log, args.load_surrogate,
+                                         args.save_surrogate)
         params, norm = sim.surrogate_get()
         out["surrogate"]["spiking_validation_pulse"] = spiking_accuracy_leg(params, norm, infoli, log)
     sim.close()
@@ -794,7 +878,16 @@ def main():
                     help="only run Table 4's experiment batches (per size, five densities)")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--save-surrogate", default=None, metavar="NPZ",
+                    help="c4: write the trained surrogate's weights and normalisation here")
+    ap.add_argument("--load-surrogate", default=None, metavar="NPZ",
+                    help="c4: use these weights and normalisation instead of training")
+    ap.add_argument("--ingest-traffic", default=None, metavar="DIR",
+                    help="only read the rocprofv3 FETCH_SIZE/WRITE_SIZE runs under DIR into the traffic file")
     args = ap.parse_args()
+    if args.ingest_traffic:
+        ingest_traffic(args.ingest_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the per-step Vd exchange across GPUs is not implemented)", file=sys.stderr)
@@ -863,8 +956,8 @@ def main():
         "roofline": roofline(nets, launch_s, step_kernel_name(info, nets, paths), paths),
         "stability": stability(nets),
     }
-    out["roofline"]["traffic"] = measured_traffic(traffic_key(args.workload, step_kernel_name(info, nets, paths),
-                                                              paths, info))
+    out["roofline"]["traffic_key"] = traffic_key(args.workload, step_kernel_name(info, nets, paths), paths, info)
+    out["roofline"]["traffic"] = measured_traffic(out["roofline"]["traffic_key"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -564,8 +564,9 @@ void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
 // For every class of CSR network (log-spaced size and degree buckets) the
 // candidate tile shapes (lanes per row, rows per tile, LDS staging of Vd) are
 // timed on the network's own device data with dry launches (they write only
-// the next-state buffer) and the fastest is kept, in memory and in an
-// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v11.txt).
+// the next-state buffer) replayed from graphs, as steps run, and the fastest
+// is kept, in memory and in an
+// on-disk cache (INFOLI_TUNE_CACHE, else ~/.cache/infoli-tune-v13.txt).
 struct TuneChoice {
     int L, R, lds, bm;     // lanes per row, rows per tile, Vd in LDS,
                            // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers,
@@ -577,7 +578,7 @@ std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v12.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v13.txt";
     return "";
 }
 
@@ -639,14 +640,69 @@ void append_tune_line(const std::string& path, const std::string& line) {
     std::fclose(f);
 }
 
+// Optional record of the tuner's timings (INFOLI_TUNE_LOG: a file the
+// lines are appended to), for checking what a run chose and why.
+void tune_log(const char* fmt, ...) {
+    const char* p = std::getenv("INFOLI_TUNE_LOG");
+    if (!p || !*p) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    append_tune_line(p, buf);
+}
+
 void append_tune_cache(const std::string& path, const std::string& key, const TuneChoice& t) {
     char buf[64];
     snprintf(buf, sizeof buf, "|%d %d %d %d %d", t.L, t.R, t.lds, t.bm, t.block);
     append_tune_line(path, key + buf);
 }
 
-// Average duration of a dry launch of the tiles of networks `ks` (one size
-// and degree class) shaped by t.
+// Device time of one repetition of `launch` (which queues one step's dry
+// launches on the stream it is given, reading the state buffer of the parity
+// it is given) as the library runs steps: `reps` (even) repetitions captured
+// into a graph, alternating the state buffers as consecutive steps do (each
+// reads what the previous one wrote), the graph replayed `trials` times after
+// one warm-up replay, the fastest replay kept. Host-launched repetitions of a
+// step of a few microseconds measure the host's launch rate as much as the
+// kernels and ranked shapes differently from box to box; repetitions that all
+// read one buffer timed about 2 us under the real step of the 4,096-cell mix.
+template <typename F>
+float time_replayed(infoli_ctx* c, F&& launch, int reps, int trials) {
+    hipGraph_t g = nullptr;
+    HIPX(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int w = 0; w < reps; ++w) launch(c->cap_stream, c->cur ^ (w & 1));
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess) fail(INFOLI_E_DEVICE, "tuning capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) fail(INFOLI_E_DEVICE, "tuning graph instantiation failed: %s", hipGetErrorString(e));
+    struct Release {       // on every exit: the replays drained, then the graph destroyed
+        infoli_ctx* c;
+        hipGraphExec_t ex;
+        ~Release() {
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipGraphExecDestroy(ex);
+        }
+    } release{c, ex};
+    HIPX(hipGraphLaunch(ex, c->stream));
+    float best = 1e30f;
+    for (int t = 0; t < trials; ++t) {
+        HIPX(hipEventRecord(c->ev0, c->stream));
+        HIPX(hipGraphLaunch(ex, c->stream));
+        HIPX(hipEventRecord(c->ev1, c->stream));
+        HIPX(hipEventSynchronize(c->ev1));
+        float ms = 0.0f;
+        HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        best = std::min(best, ms / reps);
+    }
+    return best;
+}
+
+// Duration of a dry launch of the tiles of networks `ks` (one size and
+// degree class) shaped by t, replayed from a graph.
 float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t, Tile* d_tmp) {
     std::vector<std::pair<double, Tile>> planned;
     size_t lds = 16;
@@ -676,18 +732,10 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
     a.tiles = d_tmp;
     a.dry = 1;
     const int block = t.block;
-    for (int w = 0; w < 2; ++w)
-        launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0, var);
-    HIPX(hipEventRecord(c->ev0, c->stream));
-    const int reps = 8;
-    for (int w = 0; w < reps; ++w)
-        launch_tiles(c, c->stream, a, block, (unsigned)tl.size(), lds, c->cur, c->step, 0, var);
-    HIPX(hipEventRecord(c->ev1, c->stream));
-    HIPX(hipGetLastError());
-    HIPX(hipEventSynchronize(c->ev1));
-    float ms = 0.0f;
-    HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    return ms / reps;
+    const unsigned ntiles = (unsigned)tl.size();
+    return time_replayed(
+        c, [&](hipStream_t st, int from) { launch_tiles(c, st, a, block, ntiles, lds, from, c->step, 0, var); }, 10,
+        3);
 }
 
 // Timings within kTieMargin of the fastest count as equal; among those the
@@ -734,25 +782,13 @@ void apply_choice(infoli_ctx* c, const std::vector<int>& ks, TuneChoice best) {
     }
 }
 
-// Average duration of a dry whole step (both launch groups) as finalised;
-// the smallest of five averages of 40 steps.
+// Duration of a dry whole step (both launch groups) as finalised, replayed
+// from a graph: the fastest of four replays of 20 steps.
 float time_step(infoli_ctx* c, bool fork) {
     StepArgs a = make_args(c, false);
     a.dry = 1;
-    for (int w = 0; w < 3; ++w) launch_groups(c, c->stream, a, c->cur, c->step, 0, fork);
-    const int reps = 40;
-    float best = 1e30f;
-    for (int trial = 0; trial < 5; ++trial) {
-        HIPX(hipEventRecord(c->ev0, c->stream));
-        for (int w = 0; w < reps; ++w) launch_groups(c, c->stream, a, c->cur, c->step, 0, fork);
-        HIPX(hipEventRecord(c->ev1, c->stream));
-        HIPX(hipGetLastError());
-        HIPX(hipEventSynchronize(c->ev1));
-        float ms = 0.0f;
-        HIPX(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        best = std::min(best, ms / reps);
-    }
-    return best;
+    return time_replayed(c, [&](hipStream_t st, int from) { launch_groups(c, st, a, from, c->step, 0, fork); }, 20,
+                         4);
 }
 
 uint64_t fnv1a(const std::string& s) {
@@ -769,7 +805,7 @@ uint64_t fnv1a(const std::string& s) {
 // 256-thread workgroups); then, for the whole mix of networks, the faster of
 // the per-class best shapes and the all-256 shapes, with the two launch
 // groups as concurrent branches or one after the other, timed as whole steps.
-void autotune(infoli_ctx* c) {
+void autotune_shapes(infoli_ctx* c) {
     if (c->opt.lanes_per_row || c->opt.tile_rows) return;   // shapes given by the caller
     const std::string path = tune_cache_path();
     std::map<std::string, TuneChoice> cache;
@@ -838,6 +874,8 @@ void autotune(infoli_ctx* c) {
             // by the fixed preference), best256 also as the search goes on
             auto consider = [&](const TuneChoice& t) {
                 const float ms = time_shape(c, ks, t, d_tmp);
+                tune_log("class %s shape L%d R%d lds%d path%d block%d: %.2f us", key.c_str(), t.L, t.R, t.lds,
+                         t.bm, t.block, 1e3f * ms);
                 all.push_back({ms, t});
                 if (t.block == 256) {
                     timed.push_back({ms, t});
@@ -998,6 +1036,7 @@ void autotune(infoli_ctx* c) {
                 if ((m & 2) && !both) continue;
                 if ((m & 16) && c->grp[1].tiles.empty()) continue;
                 mode_ms[m] = std::min(mode_ms[m], time_step(c, !(m & 2)));
+                tune_log("step mode %d round %d: %.2f us", m, round, 1e3f * mode_ms[m]);
             }
         // the modes within 10 % of the fastest timed again, interleaved,
         // three more rounds; then within kTieMargin the lowest mode number
@@ -1014,6 +1053,7 @@ void autotune(infoli_ctx* c) {
                     c->grp[1].block = wide_block(m);
                     finalize_tiles(c);
                     mode_ms[m] = std::min(mode_ms[m], time_step(c, !(m & 2)));
+                    tune_log("step mode %d retimed: %.2f us", m, 1e3f * mode_ms[m]);
                 }
         fastest = 1e30f;
         for (int m : close) fastest = std::min(fastest, mode_ms[m]);
@@ -1066,6 +1106,7 @@ void autotune(infoli_ctx* c) {
                 else apply_choice(c, classes[key], now);
             }
         }
+        tune_log("step mode chosen: %d", mode);
         std::string line = ctx_key;
         line += "|" + std::to_string(mode);
         for (int r : refine) line += " " + std::to_string(r);
@@ -1082,6 +1123,26 @@ void autotune(infoli_ctx* c) {
     }
     c->fork_groups = !(mode & 2);
     c->tune_mode = mode;
+}
+
+// The tuner's timed steps advance the state like real ones (they alternate
+// the two buffers); the initial state is kept aside and put back afterwards.
+void autotune(infoli_ctx* c) {
+    const size_t bytes = sizeof(float) * NSV * (size_t)c->stride;
+    struct Saved {         // on every exit: the stream drained, then the copy freed
+        infoli_ctx* c;
+        void* p = nullptr;
+        ~Saved() {
+            (void)hipStreamSynchronize(c->stream);
+            if (p) (void)hipFree(p);
+        }
+    } sv{c};
+    HIPX(hipMalloc(&sv.p, bytes));
+    void* saved = sv.p;
+    HIPX(hipMemcpyAsync(saved, c->state[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+    autotune_shapes(c);
+    HIPX(hipMemcpyAsync(c->state[c->cur], saved, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPX(hipStreamSynchronize(c->stream));
 }
 
 void launch_persistent(infoli_ctx* c, int64_t n_steps, bool dry = false);

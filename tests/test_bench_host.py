@@ -185,3 +185,47 @@ def test_stream_kernel_variant_name():
     plain = I.Network(n=3, conn="csr", g=0.04, row_ptr=rp, col=col)
     assert bench.step_kernel_name(info, [plain], ["csr_stream"]) == "infoli::k_step<1024, 3>"
     assert bench.step_kernel_name(info, [plain], ["csr_chunked"]) == "infoli::k_step<1024, 2>"
+
+
+def _pmc_csv(path, rows):
+    os.makedirs(path, exist_ok=True)
+    cols = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size",
+            "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count",
+            "Accum_VGPR_Count", "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    with open(os.path.join(path, "run_counter_collection.csv"), "w") as fh:
+        fh.write(",".join(f'"{c}"' for c in cols) + "\n")
+        for d, k, c, v in rows:
+            fh.write(f'{d},{d},"Agent 1",1,1,1,64,1,"{k}",64,0,0,8,0,32,"{c}",{v},0,1\n')
+
+
+def test_traffic_ingest_takes_the_timed_dispatches(tmp_path, monkeypatch):
+    """Counter runs -> bytes per launch: the copy calibrates each counter, the
+    tuner's earlier dispatches of the same kernel are dropped, and the entry
+    lands under the benchmark's traffic key with the source hash."""
+    root = str(tmp_path)
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", os.path.join(root, "traffic.json"))
+    mib = 4
+    with open(os.path.join(root, "copy.json"), "w") as fh:
+        fh.write(json.dumps({"copy_probe_bytes_read": mib << 20, "copy_probe_bytes_written": mib << 20}) + "\n")
+    _pmc_csv(os.path.join(root, "copy_fetch"), [(1, "fill", "FETCH_SIZE", 1.0), (2, "copy", "FETCH_SIZE", 2048.0)])
+    _pmc_csv(os.path.join(root, "copy_write"), [(1, "fill", "WRITE_SIZE", 4096.0), (2, "copy", "WRITE_SIZE", 4096.0)])
+    kern = "void infoli::k_step<1024, 3>(infoli::StepArgs, float const*, float*, long, int)"
+    line = {"steps": 3, "warmup": 1, "roofline": {"kernel": "infoli::k_step<1024, 3>", "traffic_key": "c4|k|p|wide1024",
+                                                   "algorithmic_bytes_per_launch": 1000}}
+    for k, c, v in (("fetch", "FETCH_SIZE", 10.0), ("write", "WRITE_SIZE", 3.0)):
+        with open(os.path.join(root, f"{k}.json"), "w") as fh:
+            fh.write("log line\n" + json.dumps(line) + "\n")
+        # two tuner dispatches (other sizes), then warmup + timed ones; a second
+        # counter of another name is ignored
+        rows = [(1, kern, c, 999.0), (2, kern, c, 555.0)] + [(d, kern, c, v) for d in (3, 4, 5, 6)]
+        rows += [(7, "other", c, 1e6), (3, kern, "GRBM_COUNT", 7.0)]
+        _pmc_csv(os.path.join(root, k), rows)
+    bench.ingest_traffic(root)
+    table = json.load(open(bench.TRAFFIC_FILE))
+    e = table["c4|k|p|wide1024"]
+    assert e["dispatches"] == [4, 4]
+    assert e["fetch_factor"] == 2.0 and e["write_factor"] == 1.0
+    assert e["bytes_per_launch"] == 1024 * (10 * 2 + 3 * 1)
+    assert e["kernel_sources_sha256"] == bench.kernel_source_hash()
+    assert bench.measured_traffic("c4|k|p|wide1024") == 1024 * 23
+    assert bench.measured_traffic("c4|k|p|wide512") is None

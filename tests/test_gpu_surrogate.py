@@ -308,3 +308,46 @@ def test_trained_surrogate_accuracy_and_gain(infoli):
         k = min(ca[i], cb[i], ta.shape[1])
         assert np.max(np.abs(np.sort(ta[i, :k]) - np.sort(tb[i, :k]))) <= 0.5
     assert t_surr < t_plain
+
+
+def test_mlp_gain_over_held_gap(infoli):
+    """What the learned part gains over the same macro step without it (the
+    gap current held for four plain steps), at 65,536 cells of mean degree
+    1,000: both macro steps, and the plain method, timed on the device over
+    500 macro steps (2,000 dt) after a warm-up. Printed: each one's device
+    time per 4 dt and the two gains. Asserted: the surrogate beats the plain
+    method, and the held-gap step (gap current once per 4 dt, four exact cell
+    updates) beats the MLP step: a cell's MLP evaluation (41k MFMA flops,
+    256 SiLU activations, guards, the drift re-check of 1/64 cells) costs
+    more than four exact cell updates, and the gap current, which both
+    compute once per macro step, is most of either step."""
+    net = I.config4()
+    x0 = infoli.initial_state(net)
+    sim, rep, _ = _trained(infoli, net, x0)
+    params, norm = sim.surrogate_get()
+    sim.close()
+    per4 = {}
+    for mode in ("mlp", "plain_hold"):
+        s = infoli.Simulator(net, init_states=[x0], step_mode="graph")
+        s.surrogate_set(params, norm)
+        s.step_surrogate(25, mode=mode)
+        ms = sum(s.step_surrogate(50, mode=mode)["ms"] for _ in range(10))
+        per4[mode] = ms / 500
+        s.close()
+    plain = infoli.Simulator(net, init_states=[x0], step_mode="graph", graph_chunk=100)
+    plain.step(100)
+    plain.sync()
+    ms = 0.0
+    for _ in range(10):
+        plain.step(200)
+        plain.sync()
+        ms += plain.last_step_ms()
+    plain.close()
+    per4["plain"] = ms / 500
+    gain_plain = per4["plain"] / per4["mlp"]
+    gain_hold = per4["plain_hold"] / per4["mlp"]
+    print(f"per 4 dt at 65,536 cells: plain {per4['plain'] * 1e3:.1f} us, held gap {per4['plain_hold'] * 1e3:.1f} us, "
+          f"MLP {per4['mlp'] * 1e3:.1f} us; surrogate vs plain {gain_plain:.2f}x, "
+          f"MLP gain over held gap {gain_hold:.2f}x")
+    assert gain_plain > 1.0
+    assert gain_hold < 1.0, "the MLP step now beats the held-gap step: the design's reading of the gain is out of date"
