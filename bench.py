@@ -239,18 +239,23 @@ def build_workload(name):
     return nets, desc
 
 
+# Issue slots: one slot is one wave64 lane of a full-rate FP32 VALU
+# operation (FMA class). The lane-slot peak is MI355X's FP32 vector peak,
+# 157.3 TFLOP/s = 78.6 T FMA/s = 256 CUs x 128 lanes x 2.4 GHz; plain
+# (unpacked) v_fma_f32 reaches it (a register-only loop: 6.27e13 FMA/s at the
+# clock under load). The transcendentals v_exp_f32 and v_rcp_f32 cost
+# EXP_SLOTS = 3.3 slots each (the same loop: 1.89e13 exp/s, 3.3x fewer), and
+# do not overlap with the FMA-class operations around them (the pair term's
+# sub / mul / exp / fma mix runs at 7.7 slots per pair, not max(3, 3.3)).
+LANE_SLOTS_PER_S = 256 * 128 * 2.4e9
+EXP_SLOTS = 3.3
 # Uniform all-to-all kernel: per directed pair one v_sub, one v_mul, one
 # v_exp_f32 and one v_fma (w = g factored out, the linear 0.2*dV part in
-# closed form). Full-rate VALU ops cost 1 lane-slot; v_exp_f32 issues at half
-# rate on gfx950 (a register-only loop measures 16.3 T exp/s against 34.1 T
-# fma/s), so it costs EXP_SLOTS = 2. 256 CUs x 64 lanes x 2.4 GHz.
-LANE_SLOTS_PER_S = 256 * 64 * 2.4e9
-EXP_SLOTS = 2
+# closed form).
 UNIFORM_SLOTS_PER_PAIR = 3 + EXP_SLOTS
 # Compartment update per cell-step: 278 VALU instructions in its compiled
-# form, of which 39 transcendental (21 v_exp_f32, 18 v_rcp_f32) at half rate,
-# costing a second slot each.
-CELL_SLOTS = 278 + 39
+# form, of which 39 transcendental (21 v_exp_f32, 18 v_rcp_f32).
+CELL_SLOTS = 278 - 39 + 39 * EXP_SLOTS
 
 
 def algorithmic_bytes(nets, paths=None):
@@ -280,16 +285,16 @@ def algorithmic_bytes(nets, paths=None):
     return b
 
 
-# CSR edge: v_sub, v_mul, v_mul, v_exp_f32 (2 slots), v_fma, v_add and two
-# address operations for the 16-bit column gather.
-CSR_SLOTS_PER_EDGE = 9
+# CSR edge: v_sub, v_mul, v_mul, v_exp_f32, v_fma, v_add and two address
+# operations for the 16-bit column gather.
+CSR_SLOTS_PER_EDGE = 7 + EXP_SLOTS
 # Simplified gap junctions, per CSR edge: v_sub, v_fma and the two address
 # operations.
 SGJ_SLOTS_PER_EDGE = 4
 # Coupling bitmap: every (row, column) pair is evaluated and masked by its
 # bit, the row's 64-bit word of 64 senders serving as the lane mask of one
-# select: v_sub, v_mul, v_exp_f32 (2 slots), v_fma, v_cndmask, v_fmac.
-BITMAP_SLOTS_PER_PAIR = 7
+# select: v_sub, v_mul, v_exp_f32, v_fma, v_cndmask, v_fmac.
+BITMAP_SLOTS_PER_PAIR = 5 + EXP_SLOTS
 
 
 def slots_of(n, path=None):

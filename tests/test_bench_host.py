@@ -62,10 +62,11 @@ def test_roofline_bound_per_workload_kind():
     assert mixed["bound"] == "alu" and mixed["unit"] == "T lane-slots/s"
     # composite: per network the larger of bytes at the HBM peak and slots
     # (compartment updates and pair work) at the lane-slot peak, summed
-    u = (5 * 10 * 10 + bench.CELL_SLOTS * 10) / bench.LANE_SLOTS_PER_S
+    u = (bench.UNIFORM_SLOTS_PER_PAIR * 10 * 10 + bench.CELL_SLOTS * 10) / bench.LANE_SLOTS_PER_S
     c_bytes = (116 * 3 + 2 * 2 + 8 * 3) / 8e12
     c_slots = (bench.CSR_SLOTS_PER_EDGE * 2 + bench.CELL_SLOTS * 3) / bench.LANE_SLOTS_PER_S
-    assert mixed["slots_per_launch"] == 5 * 100 + bench.CELL_SLOTS * 13 + bench.CSR_SLOTS_PER_EDGE * 2
+    assert mixed["slots_per_launch"] == pytest.approx(
+        bench.UNIFORM_SLOTS_PER_PAIR * 100 + bench.CELL_SLOTS * 13 + bench.CSR_SLOTS_PER_EDGE * 2)
     assert mixed["composite_roofline_us"] == pytest.approx((max(116 * 10 / 8e12, u) + max(c_bytes, c_slots)) * 1e6)
     assert mixed["composite_frac"] == pytest.approx(mixed["composite_roofline_us"] * 1e-6 / 1e-6)
 
@@ -73,7 +74,7 @@ def test_roofline_bound_per_workload_kind():
 def test_csr_roofline_takes_the_larger_bound():
     """All-CSR launches: bound = the larger of bytes at the HBM peak and issue
     slots at the lane-slot peak, each network counted in its path's form."""
-    n = 64
+    n = 128
     edges = [(i, j) for i in range(n) for j in range(n) if i != j and (i + j) % 2 == 1]
     rp, col = _csr(n, edges)
     net = I.Network(n=n, conn="csr", g=0.04, row_ptr=rp, col=col)
@@ -81,11 +82,11 @@ def test_csr_roofline_takes_the_larger_bound():
     gath = bench.roofline([net], launch, paths=["csr_gather"])
     b_g = 116 * n + 2 * len(edges) + 8 * n
     s_g = bench.CELL_SLOTS * n + bench.CSR_SLOTS_PER_EDGE * len(edges)
-    assert gath["algorithmic_bytes_per_launch"] == b_g and gath["slots_per_launch"] == s_g
+    assert gath["algorithmic_bytes_per_launch"] == b_g and gath["slots_per_launch"] == pytest.approx(s_g)
     bit = bench.roofline([net], launch, paths=["csr_bitmap"])
-    b_b = 116 * n + 4 * n * 2
+    b_b = 116 * n + 4 * n * ((n + 31) // 32)
     s_b = bench.CELL_SLOTS * n + bench.BITMAP_SLOTS_PER_PAIR * n * n
-    assert bit["algorithmic_bytes_per_launch"] == b_b and bit["slots_per_launch"] == s_b
+    assert bit["algorithmic_bytes_per_launch"] == b_b and bit["slots_per_launch"] == pytest.approx(s_b)
     for r, b, sl in ((gath, b_g, s_g), (bit, b_b, s_b)):
         t_hbm, t_alu = b / 8e12, sl / bench.LANE_SLOTS_PER_S
         assert r["hbm_frac"] == pytest.approx(t_hbm / launch) and r["alu_frac"] == pytest.approx(t_alu / launch)
@@ -94,7 +95,20 @@ def test_csr_roofline_takes_the_larger_bound():
     assert bit["bound"] == "alu" and bit["unit"] == "T lane-slots/s" and bit["gap_paths"] == ["csr_bitmap"]
     # simplified gap junctions cost fewer slots per edge
     sgj = I.Network(n=n, conn="csr", g=0.04, row_ptr=rp, col=col, gap="sgj")
-    assert bench.slots_of(sgj) == bench.CELL_SLOTS * n + bench.SGJ_SLOTS_PER_EDGE * len(edges)
+    assert bench.slots_of(sgj) == pytest.approx(bench.CELL_SLOTS * n + bench.SGJ_SLOTS_PER_EDGE * len(edges))
+
+
+def test_issue_slot_peak_is_the_published_fp32_peak():
+    """One lane-slot per FMA lane: the lane-slot peak is MI355X's FP32 vector
+    peak (157.3 TFLOP/s, two flops per FMA); a transcendental costs the
+    measured 3.3 slots, in every slot count that has one."""
+    assert bench.LANE_SLOTS_PER_S == pytest.approx(157.3e12 / 2, rel=1e-3)
+    e = bench.EXP_SLOTS
+    assert e == pytest.approx(3.3)
+    assert bench.UNIFORM_SLOTS_PER_PAIR == pytest.approx(3 + e)
+    assert bench.CSR_SLOTS_PER_EDGE == pytest.approx(7 + e)
+    assert bench.BITMAP_SLOTS_PER_PAIR == pytest.approx(5 + e)
+    assert bench.CELL_SLOTS == pytest.approx(239 + 39 * e)
 
 
 def test_step_kernel_variant_names():
