@@ -811,7 +811,7 @@ def rt_sweep(args, torch, infoli):
                                    "paper_table3_context": PAPER_TABLE3}}), flush=True)
 
 
-# Table 4's scenario (Section 3.3): per network size a batch of five
+# Table 4's scenario (Section 3.2): per network size a batch of five
 # realistic-gap experiments at 100, 75, 50, 25 and 0 % density, 40 s of
 # brain time (800,000 steps) each. The average time per step that BrainFrame
 # (the best fabric per experiment) reaches there, derived from Table 4's

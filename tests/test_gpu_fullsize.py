@@ -9,13 +9,13 @@ matched spike times within 0.1 ms.
 
 Explicit Euler on the coupling is stable while dt * lambda_max / C_m <= 2
 (lambda_max of the weighted graph Laplacian, bounded by twice the largest
-row sum of the weights). The 50 % network of the 4,096-cell workload (2 x
-0.04 x ~2,150 x 0.05 = 8.6) and 61 of the 256 batch networks lie above it:
-there rounding differences grow by |1 - dt * lambda| per step, so their
-states are compared over one step only (test_gpu_parity.py), and their
-trajectories and spikes are checked on companions whose conductance is
-scaled to 0.04 * 96 / (mean degree), the summed coupling of the 96-cell
-network.
+row sum of the weights). The 50 % network of the 4,096-cell workload (4.35
+by its largest eigenvalue, 8.66 by the bound) and 37 of the 256 batch
+networks (82 by the bound) lie above it: there rounding differences grow by
+|1 - dt * lambda| per step, so their states are compared over one step only
+(test_gpu_parity.py), and the trajectories and spikes of the networks above
+the bound are checked on companions whose conductance is scaled to
+0.04 * 96 / (mean degree), the summed coupling of the 96-cell network.
 """
 import sys
 
