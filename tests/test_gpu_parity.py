@@ -739,6 +739,41 @@ def test_stream_path_step_and_gap(infoli, o32, o64, n, deg, wide):
     assert per_var_error(xk1[None], ref[None]).max() <= 1e-5
 
 
+@pytest.mark.parametrize("n", [65537, 131072, 131073])
+def test_sizes_at_the_column_layout_limits(infoli, o32, o64, n):
+    """Networks at the limits of the column layouts: 65,537 cells (the first
+    size whose plain CSR columns are 32-bit), 131,072 (eight column blocks,
+    the largest network the chunk stream takes, its last block full) and
+    131,073 (nine blocks: the chunk stream refuses it and it keeps the plain
+    32-bit gathers; on the column blocks, a last block of one cell). Each on
+    the path it reports; gap currents against fp64 after 20 steps and one
+    step against the oracle."""
+    net = I.config4(seed=n % 97, n=n, degree=40)
+    x0 = infoli.initial_state(net)
+    expect = {65537: ((5, ("csr_stream", True)), (1, ("csr_gather", False))),
+              131072: ((5, ("csr_stream", True)),),
+              131073: ((5, ("csr_gather", False)), (3, None))}[n]
+    for csr_path, want in expect:
+        print(f"column-layout limit n={n} csr_path={csr_path}", flush=True)
+        sim = infoli.Simulator(net, init_states=[x0], csr_path=csr_path, step_mode="graph", graph_chunk=20)
+        got = sim.gap_path(0)
+        if want is not None:
+            assert got == want, (csr_path, got)
+        else:
+            assert got[1] and got[0] in ("csr_gather", "csr_chunked"), got
+        sim.step(20)
+        xk = sim.read_state(0)
+        ig = sim.read_gap_current(0).astype(np.float64)
+        sim.step(1)
+        xk1 = sim.read_state(0)
+        sim.close()
+        tol = gap_bound(net, xk[0])
+        ref_ig = o64.gap(net, xk[0].astype(np.float64))
+        assert np.all(np.abs(ig - ref_ig) <= tol), (csr_path, np.max(np.abs(ig - ref_ig) / tol))
+        ref = o32.run(net, 1, x0=xk, step0=20)["x"]
+        assert per_var_error(xk1[None], ref[None]).max() <= 1e-5, csr_path
+
+
 def test_stream_path_trajectory_and_repeatability(infoli, o32, o64):
     """400 steps of a 20,000-cell network on the chunk stream against the
     oracle (every state variable, subthreshold pulse), and a second run
