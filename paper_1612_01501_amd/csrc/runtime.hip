@@ -248,9 +248,29 @@ int group_for(const InstDesc& d) {
     return 0;
 }
 
+// The chunk stream's gathers address LDS by column alone, which holds while
+// its kernel variants have no static LDS (their staged block starts at LDS
+// address 0); read from the compiled kernels once.
+bool stream_kernels_ok() {
+    static const bool ok = [] {
+        hipFuncAttributes a1{}, a2{};
+        if (hipFuncGetAttributes(&a1, reinterpret_cast<const void*>(&k_step<1024, kVarStream>)) != hipSuccess ||
+            hipFuncGetAttributes(&a2, reinterpret_cast<const void*>(&k_step<512, kVarStream>)) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return a1.sharedSizeBytes == 0 && a2.sharedSizeBytes == 0;
+    }();
+    return ok;
+}
+
+// The chunk stream can run with this context's column blocks.
+bool stream_ok(const infoli_ctx* c) { return c->blk_cols == kStreamCols && stream_kernels_ok(); }
+
 size_t lds_floats_for(const infoli_ctx* c, const InstDesc& d, int block) {
     if (d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0)   // block, own voltages, sums, offsets
-        return (size_t)(block >= 1024 ? stream_lds_floats<1024>(c->blk_cols) : stream_lds_floats<512>(c->blk_cols));
+        return (size_t)(block >= 1024 ? stream_lds_floats<1024>(c->blk_cols) : stream_lds_floats<512>(c->blk_cols)) +
+               kMaxTileRows;   // the row sums (no static LDS in the stream variant)
     if (d.conn == CONN_CSR && d.blocked)   // the column block, then the tile rows' own voltages
         return d.cb_off >= 0 ? (size_t)c->blk_cols + kSelfSlots : (size_t)std::min(d.n, c->blk_cols);
     if (d.conn == CONN_UNIFORM) return (size_t)std::min(d.n, kChunk) + 8 * (size_t)(block / 64);
@@ -274,13 +294,13 @@ void finalize_tiles(infoli_ctx* c) {
         for (int k = 0; k < c->n_inst; ++k) {
             const InstDesc& d = c->inst[k];
             const bool st = d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0 && !d.has_w && !d.pcell &&
-                            d.nblk <= kStreamMaxBlocks && c->blk_cols == kStreamCols;
+                            d.nblk <= kStreamMaxBlocks && stream_ok(c);
             if (!st) mixed[group_for(d)] = true;
         }
         for (int k = 0; k < c->n_inst; ++k) {
             InstDesc& d = c->inst[k];
             if (d.stream && (mixed[group_for(d)] || d.has_w || d.pcell || d.cb_off < 0 || !d.blocked ||
-                             d.nblk > kStreamMaxBlocks || c->blk_cols != kStreamCols))
+                             d.nblk > kStreamMaxBlocks || !stream_ok(c)))
                 d.stream = 0;
         }
     }
@@ -920,7 +940,7 @@ void autotune_shapes(infoli_ctx* c) {
             bool all_cb = c->d_rtag != nullptr;
             for (int k : ks)
                 all_cb = all_cb && c->inst[k].cb_off >= 0 && !c->inst[k].has_w && !c->inst[k].pcell &&
-                         c->inst[k].nblk <= kStreamMaxBlocks && c->blk_cols == kStreamCols;
+                         c->inst[k].nblk <= kStreamMaxBlocks && stream_ok(c);
             if (all_cb)
                 for (int blk : {1024, 512}) {
                     InstDesc d = c->inst[ks[0]];
@@ -1459,7 +1479,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     if (c->opt.csr_path == 5)
         for (int k = 0; k < ninst; ++k)
             if (c->inst[k].cb_off >= 0 && !c->inst[k].has_w && !c->inst[k].pcell &&
-                c->inst[k].nblk <= kStreamMaxBlocks && c->blk_cols == kStreamCols) {
+                c->inst[k].nblk <= kStreamMaxBlocks && stream_ok(c)) {
                 InstDesc d = c->inst[k];
                 d.blocked = d.stream = 1;
                 const int blk = c->opt.wide_threads ? c->opt.wide_threads : 1024;

@@ -675,15 +675,18 @@ __device__ __forceinline__ uint32_t col_hi_bytes(uint32_t w) {
     return r;
 }
 
-// One chunk's eight terms (voltages prescaled, staged in LDS).
+// One chunk's eight terms (voltages prescaled, staged in LDS). The staged
+// block is the first thing in LDS (the stream variant of k_step has no
+// static LDS; the runtime checks it before it offers the stream), so a
+// column's LDS address is the column times four, with no base to add.
+typedef const __attribute__((address_space(3))) float lds_float;
 template <bool SGJ>
-__device__ __forceinline__ float chunk_terms(const uint4 q, const float* src, float vi) {
+__device__ __forceinline__ float chunk_terms(const uint4 q, float vi) {
     const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
-    const char* base = reinterpret_cast<const char*>(src);
     float v[kChunkCols];
 #pragma unroll
     for (int e = 0; e < kChunkCols; ++e)
-        v[e] = *reinterpret_cast<const float*>(base + ((e & 1) ? col_hi_bytes(wd[e >> 1]) : col_lo_bytes(wd[e >> 1])));
+        v[e] = *(lds_float*)(size_t)((e & 1) ? col_hi_bytes(wd[e >> 1]) : col_lo_bytes(wd[e >> 1]));
     float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
     for (int e = 0; e < kChunkCols; e += 2) {
@@ -792,14 +795,14 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
             // block, in which the scheduler overlaps two sweeps at a time
 #pragma unroll
             for (int i = 0; i < SW; ++i) {
-                dst[i * 64] = chunk_terms<SGJ>(q[i], s_vd, s_self[tg[i]]);
+                dst[i * 64] = chunk_terms<SGJ>(q[i], s_self[tg[i]]);
                 if (i & 1) __builtin_amdgcn_sched_barrier(0);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < SW; ++i) {
                 if (i < p.np) {
-                    const float sum = chunk_terms<SGJ>(q[i], s_vd, s_self[tg[i]]);
+                    const float sum = chunk_terms<SGJ>(q[i], s_self[tg[i]]);
                     if (slot + i * 64 < m) dst[i * 64] = sum;
                 }
             }
@@ -1101,17 +1104,10 @@ __device__ __forceinline__ float evoked_input(const StepArgs& a, const InstDesc&
 // the only gap path it compiles.
 enum : int { kVarAll = 0, kVarNoGap = 1, kVarNoW = 2, kVarStream = 3 };
 
-template <int BLOCK, int VAR = kVarAll>
-__global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restrict__ xin,
-                                                float* __restrict__ xout, int64_t step_arg,
-                                                int32_t step_off) {
-    __shared__ float s_ig[kMaxTileRows];
-    __shared__ float s_part[BLOCK];
-    __shared__ double s_red[BLOCK / 64];
-    // Vd staging, sized per launch: the largest all-to-all chunk
-    // (min(n, kChunk) + 8 per wave) or the largest LDS-staged CSR network
-    extern __shared__ float4 s_v4[];
-
+template <int BLOCK, int VAR>
+__device__ __forceinline__ void step_body(const StepArgs& a, const float* __restrict__ xin, float* __restrict__ xout,
+                                          int64_t step_arg, int32_t step_off, float* s_ig, float* s_part,
+                                          double* s_red, float4* s_v4) {
     if (a.list_reset && blockIdx.x == 0 && threadIdx.x == 0) *a.list_reset = 0u;
     const Tile t = a.tiles[blockIdx.x];
     const InstDesc& d = a.inst[t.inst];
@@ -1220,6 +1216,27 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restr
             }
             a.spike_count[cell] = c + 1;
         }
+    }
+}
+
+// The step. Vd staging in dynamic LDS, sized per launch: the largest
+// all-to-all chunk (min(n, kChunk) + 8 per wave) or the largest LDS-staged
+// CSR network. The chunk stream variant has no static LDS, so its staged
+// voltages start at LDS address 0 (a gather's address is its column times
+// four, with no base to add) and its row sums follow the stream's region.
+template <int BLOCK, int VAR = kVarAll>
+__global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, const float* __restrict__ xin,
+                                                float* __restrict__ xout, int64_t step_arg,
+                                                int32_t step_off) {
+    extern __shared__ float4 s_v4[];
+    if constexpr (VAR == kVarStream) {
+        float* s_ig = reinterpret_cast<float*>(s_v4) + stream_lds_floats<BLOCK>(kStreamCols);
+        step_body<BLOCK, VAR>(a, xin, xout, step_arg, step_off, s_ig, nullptr, nullptr, s_v4);
+    } else {
+        __shared__ float s_ig[kMaxTileRows];
+        __shared__ float s_part[BLOCK];
+        __shared__ double s_red[BLOCK / 64];
+        step_body<BLOCK, VAR>(a, xin, xout, step_arg, step_off, s_ig, s_part, s_red, s_v4);
     }
 }
 
