@@ -167,9 +167,11 @@ typedef struct infoli_options {
                                     4 => edge gathers from 16-byte column chunks
                                     (<= 65,536 cells); 5 => the column blocks read as one
                                     flat stream of chunks per tile (> 8,192 cells, at most
-                                    8 column blocks, one weight g, network parameters; needs
-                                    ~100 KB of LDS per workgroup, else
-                                    INFOLI_E_UNSUPPORTED); other networks keep the default */
+                                    8 column blocks, one weight g, network parameters, the
+                                    network's first cell at a multiple of 4 in the batch's
+                                    flattened cells; needs ~138 KB of LDS per workgroup,
+                                    else INFOLI_E_UNSUPPORTED); other networks keep the
+                                    default */
     int32_t output_ring_steps;   /* 0 => off; R > 0 => every plain step also writes the axon
                                     voltage of every cell into a device ring of R steps,
                                     read out with infoli_output_copy_async                 */

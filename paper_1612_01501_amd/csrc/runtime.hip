@@ -294,13 +294,13 @@ void finalize_tiles(infoli_ctx* c) {
         for (int k = 0; k < c->n_inst; ++k) {
             const InstDesc& d = c->inst[k];
             const bool st = d.conn == CONN_CSR && d.blocked && d.stream && d.cb_off >= 0 && !d.has_w && !d.pcell &&
-                            d.nblk <= kStreamMaxBlocks && stream_ok(c);
+                            d.nblk <= kStreamMaxBlocks && d.cell_off % 4 == 0 && stream_ok(c);
             if (!st) mixed[group_for(d)] = true;
         }
         for (int k = 0; k < c->n_inst; ++k) {
             InstDesc& d = c->inst[k];
             if (d.stream && (mixed[group_for(d)] || d.has_w || d.pcell || d.cb_off < 0 || !d.blocked ||
-                             d.nblk > kStreamMaxBlocks || !stream_ok(c)))
+                             d.nblk > kStreamMaxBlocks || d.cell_off % 4 != 0 || !stream_ok(c)))
                 d.stream = 0;
         }
     }
@@ -940,7 +940,7 @@ void autotune_shapes(infoli_ctx* c) {
             bool all_cb = c->d_rtag != nullptr;
             for (int k : ks)
                 all_cb = all_cb && c->inst[k].cb_off >= 0 && !c->inst[k].has_w && !c->inst[k].pcell &&
-                         c->inst[k].nblk <= kStreamMaxBlocks && stream_ok(c);
+                         c->inst[k].nblk <= kStreamMaxBlocks && c->inst[k].cell_off % 4 == 0 && stream_ok(c);
             if (all_cb)
                 for (int blk : {1024, 512}) {
                     InstDesc d = c->inst[ks[0]];
@@ -1479,7 +1479,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     if (c->opt.csr_path == 5)
         for (int k = 0; k < ninst; ++k)
             if (c->inst[k].cb_off >= 0 && !c->inst[k].has_w && !c->inst[k].pcell &&
-                c->inst[k].nblk <= kStreamMaxBlocks && stream_ok(c)) {
+                c->inst[k].nblk <= kStreamMaxBlocks && c->inst[k].cell_off % 4 == 0 && stream_ok(c)) {
                 InstDesc d = c->inst[k];
                 d.blocked = d.stream = 1;
                 const int blk = c->opt.wide_threads ? c->opt.wide_threads : 1024;

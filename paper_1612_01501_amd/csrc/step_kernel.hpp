@@ -819,16 +819,21 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
     // all C slots are loaded and stored, past the network's last cell too:
     // the state buffer holds 14 rows of at least n > C / 2 cells after Vd,
     // and no column entry names a slot past the block's end
-    float sv[STAGE];
+    // (four voltages per load and store: the network's Vd row starts on a
+    // 16-byte boundary, which the runtime requires of stream networks)
+    constexpr int STAGE4 = STAGE / 4;
+    float4 sv[STAGE4];
     auto load_voltages = [&](int b) {
-        const float* src = vd + b * C + threadIdx.x;
+        const float4* src = reinterpret_cast<const float4*>(vd + b * C) + threadIdx.x;
 #pragma unroll
-        for (int u = 0; u < STAGE; ++u) sv[u] = src[u * BLOCK];
+        for (int u = 0; u < STAGE4; ++u) sv[u] = src[u * BLOCK];
     };
     auto store_voltages = [&]() {
-        float* dst = s_vd + threadIdx.x;
+        float4* dst = reinterpret_cast<float4*>(s_vd) + threadIdx.x;
 #pragma unroll
-        for (int u = 0; u < STAGE; ++u) dst[u * BLOCK] = sv[u] * kPreScale;
+        for (int u = 0; u < STAGE4; ++u)
+            dst[u * BLOCK] = make_float4(sv[u].x * kPreScale, sv[u].y * kPreScale, sv[u].z * kPreScale,
+                                         sv[u].w * kPreScale);
     };
 
     constexpr int NS = kStreamSets;

@@ -774,6 +774,30 @@ def test_sizes_at_the_column_layout_limits(infoli, o32, o64, n):
         assert per_var_error(xk1[None], ref[None]).max() <= 1e-5, csr_path
 
 
+def test_stream_needs_an_aligned_first_cell(infoli, o32, o64):
+    """The chunk stream stages a network's voltages four at a time, so with
+    the stream asked for, a network whose first cell is not at a multiple of
+    four in the batch's flattened cells keeps its default path (the plain
+    gathers); one at a multiple of four takes the stream. Both against fp64
+    gap currents and one oracle step."""
+    big = I.config4(seed=11, n=20000, degree=100)
+    for lead, want in ((3, ("csr_gather", False)), (4, ("csr_stream", True))):
+        nets = [I.Network(n=lead, conn="none"), big]
+        x0s = [infoli.initial_state(n) for n in nets]
+        sim = infoli.Simulator(nets, init_states=x0s, csr_path=5, step_mode="graph", graph_chunk=20)
+        assert sim.gap_path(1) == want, (lead, sim.gap_path(1))
+        sim.step(20)
+        xk = sim.read_state(1)
+        ig = sim.read_gap_current(1).astype(np.float64)
+        sim.step(1)
+        xk1 = sim.read_state(1)
+        sim.close()
+        tol = gap_bound(big, xk[0])
+        assert np.all(np.abs(ig - o64.gap(big, xk[0].astype(np.float64))) <= tol), lead
+        ref = o32.run(big, 1, x0=xk, step0=20)["x"]
+        assert per_var_error(xk1[None], ref[None]).max() <= 1e-5, lead
+
+
 def test_stream_path_trajectory_and_repeatability(infoli, o32, o64):
     """400 steps of a 20,000-cell network on the chunk stream against the
     oracle (every state variable, subthreshold pulse), and a second run
