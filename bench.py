@@ -253,6 +253,9 @@ EXP_SLOTS = 3.3
 # v_exp_f32 and one v_fma (w = g factored out, the linear 0.2*dV part in
 # closed form).
 UNIFORM_SLOTS_PER_PAIR = 3 + EXP_SLOTS
+# The same networks with each unordered pair once (k_pairs_sym): per pair
+# one v_sub, v_mul, v_exp_f32 and two v_fma (the row's sum and the column's).
+SYM_SLOTS_PER_PAIR = 4 + EXP_SLOTS
 # Compartment update per cell-step: 278 VALU instructions in its compiled
 # form, of which 39 transcendental (21 v_exp_f32, 18 v_rcp_f32).
 CELL_SLOTS = 278 - 39 + 39 * EXP_SLOTS
@@ -301,7 +304,10 @@ def slots_of(n, path=None):
     """Issue slots of one network's step: its compartment updates plus its
     pair or edge work in the form the path evaluates it."""
     s = CELL_SLOTS * n.n
-    if n.conn == "uniform":
+    if n.conn == "uniform" and path == "uniform_sym":
+        own = (n.n + 63) // 64 * 64 * 64
+        s += SYM_SLOTS_PER_PAIR * (n.n * n.n - own) / 2 + UNIFORM_SLOTS_PER_PAIR * own
+    elif n.conn == "uniform":
         s += UNIFORM_SLOTS_PER_PAIR * n.n * n.n
     elif n.conn == "csr" and path == "csr_bitmap":
         s += BITMAP_SLOTS_PER_PAIR * n.n * n.n
@@ -317,6 +323,9 @@ def step_kernel_name(info, nets, paths=None):
     only), 2 when none has per-edge weights or per-cell parameters, else 0."""
     if info["step_mode"] == 3:
         return "infoli::k_persist"
+    if paths and any(p == "uniform_sym" for p in paths):
+        rest = step_kernel_name(info, nets, [p if p != "uniform_sym" else "uniform" for p in paths])
+        return "infoli::k_pairs_sym + " + rest
     if paths and all(p == "csr_stream" for p in paths):
         return f"infoli::k_step<{info.get('wide_threads', 1024)}, 3>"
     if all(n.conn == "none" and n.cell_params is None for n in nets):
@@ -354,6 +363,22 @@ def roofline(nets, launch_s, kernel="infoli::k_step<256, 2>", paths=None):
                 "frac": achieved / peak, "traffic": None, "kernel": kernel,
                 "slots_per_launch": slots, "composite_roofline_us": t_roof * 1e6,
                 "composite_frac": t_roof / launch_s}
+    if all(n.conn == "uniform" and n.gap == "rgj" for n in nets) and all(p == "uniform_sym" for p in paths):
+        # each unordered pair once: issue slots of the pair kernel's work
+        # (a block's own 64 x 64 pairs ordered, as it evaluates them) and of
+        # the compartment updates, at the lane-slot peak
+        slots = 0.0
+        for n in nets:
+            blocks = (n.n + 63) // 64
+            own = blocks * 64 * 64
+            slots += SYM_SLOTS_PER_PAIR * (n.n * n.n - own) / 2 + UNIFORM_SLOTS_PER_PAIR * own + CELL_SLOTS * n.n
+        achieved = slots / launch_s / 1e12
+        peak = LANE_SLOTS_PER_S / 1e12
+        ordered = sum(n.n * n.n for n in nets) / launch_s
+        return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T lane-slots/s",
+                "frac": achieved / peak, "traffic": None, "kernel": kernel, "slots_per_launch": slots,
+                "slots_per_unordered_pair": SYM_SLOTS_PER_PAIR, "gap_paths": ["uniform_sym"],
+                "ordered_pair_frac": ordered / (LANE_SLOTS_PER_S / UNIFORM_SLOTS_PER_PAIR)}
     if all(n.conn == "uniform" and n.gap == "rgj" for n in nets):
         pairs = sum(n.n * n.n for n in nets)       # the kernel evaluates the diagonal too
         achieved = pairs / launch_s / 1e9

@@ -178,6 +178,16 @@ typedef struct infoli_options {
     int32_t wide_threads;        /* workgroup size of the wide launch group (all-to-all
                                     networks of >= 4,096 cells, column blocks, wide bitmap
                                     tiles): 0 => timed by the tuner (else 1024); 512 or 1024 */
+    int32_t pair_path;           /* all-to-all networks with the realistic gap term:
+                                    0 => library choice (each unordered pair once from
+                                    4,096 cells on, every ordered pair below); 1 => every
+                                    ordered pair; 2 => each unordered pair once (the pair
+                                    term of Section 2.3.1, Algorithm 1, is odd in dV,
+                                    so the pair (j, i) gives minus the term of (i, j)).
+                                    Once costs
+                                    64 x (B/2 + waves + 1) x B floats of partial sums per
+                                    network of B = ceil(n/64) blocks (8.4 MB at 16,384
+                                    cells)                                                 */
 } infoli_options;
 
 typedef struct infoli_ctx infoli_ctx;
@@ -312,6 +322,9 @@ infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
  *   CSR_STREAM  the CSR_CHUNKED columns of each column block (relative to
  *               the block) as one contiguous run per tile, plus one byte per
  *               chunk naming its row (Vd staged block by block).
+ *   UNIFORM_SYM all-to-all, each unordered pair once: a separate kernel
+ *               writes per-block partial sums, the step adds them per cell
+ *               in a fixed order (option pair_path).
  * (The persistent step mode walks CSR rows from the gather format.)
  * *path receives the code; *vd_blocked (either pointer may be NULL) receives
  * 1 when the network's Vd is staged in LDS one column block at a time (CSR
@@ -324,7 +337,8 @@ typedef enum infoli_gap_path {
     INFOLI_PATH_CSR_GATHER = 3,
     INFOLI_PATH_CSR_CHUNKED = 4,
     INFOLI_PATH_CSR_BITMAP = 5,
-    INFOLI_PATH_CSR_STREAM = 6
+    INFOLI_PATH_CSR_STREAM = 6,
+    INFOLI_PATH_UNIFORM_SYM = 7
 } infoli_gap_path;
 infoli_status infoli_get_gap_path(const infoli_ctx *ctx, int32_t instance, int32_t *path, int32_t *vd_blocked);
 

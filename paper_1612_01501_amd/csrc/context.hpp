@@ -146,6 +146,7 @@ struct infoli_ctx {
     int32_t* d_flags = nullptr;
     int64_t* d_step = nullptr;
     float* d_cparams = nullptr;     // per-cell parameters [20][stride], networks that have them
+    float* d_psym = nullptr;        // partial sums of the networks whose pairs are taken once
 
     int64_t step = 0;               // absolute index of the next step to run
     // output streaming: Va after each step in a device ring, copied out on

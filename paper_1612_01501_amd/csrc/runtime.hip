@@ -202,6 +202,15 @@ void infoli_rt::launch_tiles(infoli_ctx* c, hipStream_t st, const StepArgs& a, i
 
 void infoli_rt::launch_groups(infoli_ctx* c, hipStream_t st, const StepArgs& a, int from, int64_t step_arg,
                               int32_t off, bool fork) {
+    // the unordered pairs of all-to-all networks first: their step reads the sums
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstDesc& d = c->inst[k];
+        if (!d.sym) continue;
+        const int64_t groups = (int64_t)sym_blocks(d.n) * sym_shares(d.n, d.sym_ki);
+        hipLaunchKernelGGL(k_pairs_sym, dim3((unsigned)groups), dim3(256), 0, st,
+                           c->state[from] + (int64_t)SV_VD * c->stride + d.cell_off, d.n, d.sym_ki,
+                           c->d_psym + d.psym_off);
+    }
     const bool both = !c->grp[0].tiles.empty() && !c->grp[1].tiles.empty();
     if (fork && both) {
         HIPX(hipEventRecord(c->fork_ev, st));
@@ -418,6 +427,33 @@ void build_blocks(infoli_ctx* c, const infoli_network_spec* specs) {
 // relative to the block start padded with C + (i mod kSelfSlots) to whole
 // chunks; per row and block the first chunk ([n][nblk + 1]). Per-edge
 // weights follow the same layout, 0 on padding.
+// All-to-all networks whose pairs are taken once (k_pairs_sym): the
+// realistic gap term (the simplified one has its O(n) closed form), tiled
+// steps; from kSymCells cells on by default. Row blocks per workgroup:
+// about 2,048 workgroups (8,192 waves) per launch, 4 to 16 row blocks each
+// (the column sums' lane reduction is paid once per wave).
+void build_sym(infoli_ctx* c) {
+    int64_t total = 0;
+    for (int k = 0; k < c->n_inst; ++k) {
+        InstDesc& d = c->inst[k];
+        d.sym = 0;
+        d.psym_off = 0;
+        d.sym_ki = 0;
+        const bool want = c->opt.pair_path == 2 || (c->opt.pair_path == 0 && d.n >= kSymCells);
+        if (d.conn != CONN_UNIFORM || d.sgj || !want || c->opt.step_mode == INFOLI_MODE_PERSISTENT) continue;
+        const int64_t work = (int64_t)sym_blocks(d.n) * sym_kmax(d.n);
+        d.sym = 1;
+        d.sym_ki = (int32_t)std::min<int64_t>(kSymMaxKi, std::max<int64_t>(4, work / 2048));
+        d.psym_off = total;
+        total += sym_floats(d.n, d.sym_ki);
+    }
+    if (total == 0) return;
+    c->d_psym = c->alloc<float>((size_t)total);
+    HIPX(hipMemset(c->d_psym, 0, sizeof(float) * (size_t)total));
+    HIPX(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDesc) * c->n_inst, hipMemcpyHostToDevice));
+    HIPX(hipDeviceSynchronize());
+}
+
 void build_chunks(infoli_ctx* c, const infoli_network_spec* specs) {
     const int C = c->blk_cols;
     int64_t nca = 0, ncb = 0, nchunks = 0;
@@ -1220,6 +1256,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         fail(INFOLI_E_INVALID_ARG, "output_ring_steps must be in [0, 2^20]");
     if (c->opt.wide_threads != 0 && c->opt.wide_threads != 512 && c->opt.wide_threads != 1024)
         fail(INFOLI_E_INVALID_ARG, "wide_threads must be 0, 512 or 1024");
+    if (c->opt.pair_path < 0 || c->opt.pair_path > 2) fail(INFOLI_E_INVALID_ARG, "pair_path must be 0, 1 or 2");
     for (int k = 0; k < ninst; ++k) validate_spec(specs[k], k);
     for (int k = 1; k < ninst; ++k) {
         if (specs[k].step0 != specs[0].step0) fail(INFOLI_E_INVALID_ARG, "all networks must share step0");
@@ -1465,6 +1502,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
     build_bitmaps(c, specs);
     build_blocks(c, specs);
     build_chunks(c, specs);
+    build_sym(c);
     if (c->opt.autotune && c->opt.csr_path == 0) autotune(c);
     if (c->opt.csr_path == 3)
         for (int k = 0; k < ninst; ++k)
@@ -1518,6 +1556,7 @@ StepArgs infoli_rt::make_args(const infoli_ctx* c, bool device_step) {
     a.ca = c->d_ca;
     a.cb = c->d_cb;
     a.chk = c->d_chk;
+    a.psym = c->d_psym;
     a.chkw = c->d_chkw;
     a.rtag = c->d_rtag;
     a.blk_cols = c->blk_cols;
@@ -1922,7 +1961,8 @@ infoli_status infoli_get_gap_path(const infoli_ctx* ctx, int32_t instance, int32
         // else chunked rows or plain gathers
         const InstDesc& d = ctx->inst[instance];
         int32_t p = INFOLI_PATH_NONE, blk = 0;
-        if (d.conn == CONN_UNIFORM) p = INFOLI_PATH_UNIFORM;
+        if (d.conn == CONN_UNIFORM)
+            p = d.sym && ctx->opt.step_mode != INFOLI_MODE_PERSISTENT ? INFOLI_PATH_UNIFORM_SYM : INFOLI_PATH_UNIFORM;
         else if (d.conn == CONN_DENSE) p = INFOLI_PATH_DENSE;
         else if (d.conn == CONN_CSR) {
             const bool wide = ctx->group_of.size() > (size_t)instance && ctx->group_of[instance] == 1;

@@ -74,13 +74,16 @@ struct InstDesc {
     int32_t sgj;           // simplified (linear) gap junctions: term w * dV
     int32_t pcell;         // per-cell parameters in StepArgs::cparams
     int32_t stream;        // blocked: the flat chunk stream (row tags) instead of row groups
-    int32_t pad_desc;
+    int32_t sym;           // UNIFORM: each unordered pair once (k_pairs_sym), partial sums in psym
     int64_t bits_off;      // bitmap: offset of the network's first word
     int64_t blk_off;       // blocked: offset of the network's [n][nblk] block starts
     int64_t ca_off;        // chunked rows: offset of the [n + 1] row chunk starts, -1 none
     int64_t chk_off;       // chunked rows: first chunk of the network
     int64_t cb_off;        // chunked blocks: offset of the [n][nblk + 1] chunk starts, -1 none
     int64_t chkb_off;      // chunked blocks: first chunk of the network
+    int64_t psym_off;      // sym: offset of the network's partial sums in StepArgs::psym
+    int32_t sym_ki;        // sym: row blocks per wave of k_pairs_sym
+    int32_t pad_sym;
     CellParams p;
 };
 
@@ -130,6 +133,7 @@ struct StepArgs {
     int32_t out_slots;         // output ring: slots (steps), 0 => none
     float* out_ring;           // [out_slots][stride]: Va after step s in slot s mod out_slots
     const float* cparams;      // [20][stride]: per-cell parameters (networks with pcell)
+    const float* psym;         // partial row sums of the sym networks (k_pairs_sym)
 };
 
 // The parameters of one cell: the network's, or the cell's own (SoA rows).
@@ -175,6 +179,26 @@ __device__ __forceinline__ float pair_factor(float dv) {
     else return PS ? gap_factor_ps(dv) : gap_factor(dv);
 }
 
+// Blocks of the all-to-all path that takes each unordered pair once
+// (k_pairs_sym below).
+constexpr int kSymCells = 4096;     // all-to-all networks from this size on (library choice)
+constexpr int kSymMaxKi = 16;       // row blocks per workgroup, at most
+
+__host__ __device__ constexpr int sym_blocks(int n) { return (n + 63) / 64; }
+__host__ __device__ constexpr int sym_kmax(int n) { return sym_blocks(n) / 2; }
+__host__ __device__ constexpr int sym_shares(int n, int ki) {       // workgroups per column block
+    return sym_kmax(n) > ki ? (sym_kmax(n) + ki - 1) / ki : 1;
+}
+// floats of a network's partial sums: [B][K][64] row sums of block pairs,
+// [B][S][64] column sums, [B][64] own-block row sums, then B fp64 sums of
+// each block's voltages (a multiple of 64 floats in all)
+__host__ __device__ constexpr int64_t sym_vsum_off(int n, int ki) {
+    return (int64_t)sym_blocks(n) * 64 * (sym_kmax(n) + sym_shares(n, ki) + 1);
+}
+__host__ __device__ constexpr int64_t sym_floats(int n, int ki) {
+    return (sym_vsum_off(n, ki) + 2 * (int64_t)sym_blocks(n) + 63) / 64 * 64;
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d, const Tile& t,
                                             const float* __restrict__ vd, float* s_ig,
@@ -193,8 +217,39 @@ __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d
     if (d.sgj) {
         // simplified: g (n Vd_i - sum_j Vd_j), the sum in fp64
         for (int k = threadIdx.x; k < n; k += BLOCK) vsum += (double)vd[k];
+    } else if (d.sym) {
+        // the realistic form's linear part from the blocks' sums k_pairs_sym wrote
+        const double* bs = reinterpret_cast<const double*>(a.psym + d.psym_off + sym_vsum_off(n, d.sym_ki));
+        for (int k = threadIdx.x; k < sym_blocks(n); k += BLOCK) vsum += bs[k];
     }
-    for (int c0 = 0; c0 < (d.sgj ? 0 : n); c0 += kChunk) {
+    if (d.sym && !d.sgj && valid) {
+        // the row's partial sums from k_pairs_sym, in a fixed order: its
+        // block's own pairs, its row sums of block pairs (k = 1 .. KR), the
+        // column sums of its block; each wave adds a consecutive run,
+        // loading a batch at a time so that the loads overlap
+        const int r = t.row0 + lane, R = r >> 6, l = r & 63;
+        const int B = sym_blocks(n), K = sym_kmax(n), S = sym_shares(n, d.sym_ki);
+        const int KR = (B & 1) ? (B - 1) / 2 : B / 2 - 1 + (R >= B / 2 ? 1 : 0);
+        const float* P = a.psym + d.psym_off;
+        const float* prow = P + (int64_t)R * K * 64 + l;
+        const float* pcol = P + (int64_t)B * K * 64 + (int64_t)R * S * 64 + l;
+        const float* pdiag = P + (int64_t)B * K * 64 + (int64_t)B * S * 64 + (int64_t)R * 64 + l;
+        const int E = 1 + KR + S, per = (E + W - 1) / W;
+        const int q0 = wave * per, q1 = min(E, q0 + per);
+        constexpr int kQ = 16;
+        for (int qb = q0; qb < q1; qb += kQ) {
+            float v[kQ];
+#pragma unroll
+            for (int u = 0; u < kQ; ++u) {
+                const int q = qb + u;
+                v[u] = q >= q1 ? 0.0f : q == 0 ? *pdiag : q <= KR ? prow[(int64_t)(q - 1) * 64]
+                                                                   : pcol[(int64_t)(q - 1 - KR) * 64];
+            }
+#pragma unroll
+            for (int u = 0; u < kQ; ++u) acc0 += v[u];
+        }
+    }
+    for (int c0 = 0; c0 < (d.sgj || d.sym ? 0 : n); c0 += kChunk) {
         const int cn = min(kChunk, n - c0);
         // per-wave share, a multiple of 8 values; the tail is padded with a
         // sentinel whose term is exactly -0
@@ -239,6 +294,125 @@ __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d
         const float lin = (float)((double)n * (double)vi - tot);
         s_ig[lane] = d.sgj ? d.g * lin : d.g * (0.8f * (e * kInvPreScale) + 0.2f * lin);
     }
+}
+
+// ---------------------------------------------------------------- all-to-all, each unordered pair once
+// The pair term dV * f(dV) (Section 2.3.1, Algorithm 1) is odd in dV, and
+// exactly so in floating point:
+// the difference of (j, i) is minus that of (i, j), its square and the
+// factor are the same, so its term is minus the other. An all-to-all
+// network with one weight g therefore needs each unordered pair once.
+// Cells form blocks of 64 (B blocks; the last one padded with kSentinel,
+// whose terms against any cell are zero). The pairs of distinct blocks
+// {J, J + k mod B}, 1 <= k <= B / 2 (k = B / 2 only for J < B / 2 when B is
+// even, so that each block pair is taken once), belong to column block J.
+// A wave holds J's 64 voltages in scalar registers and takes sym_ki row
+// blocks I = J + k in turn, lanes being I's cells: per pair one difference,
+// square, exponential and two fused multiply-adds, one into the row's sum
+// (written for (I, k)) and one into the column's (added over the wave's row
+// blocks, then over its lanes). Each block's own 64 x 64 ordered pairs give
+// its row sums directly. The step adds a cell's partial sums in a fixed
+// order, so results do not depend on scheduling.
+// Halving step of a lane-transposed sum: v[0 .. 2H) are sums of 2H
+// consecutive columns over this lane; afterwards v[0 .. H) hold the sums over
+// this lane and lane ^ H of the half of them selected by bit H of the lane.
+// After H = 8, 4, 2, 1 a lane holds column (lane & 15)'s sum over the 16
+// lanes that share its bits 4 and 5.
+template <int H>
+__device__ __forceinline__ void sym_halve(float* v, int lane) {
+    const bool hi = (lane & H) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const float send = hi ? v[i] : v[i + H];
+        const float keep = hi ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, H, 64);
+    }
+}
+
+// One workgroup of four waves per (column block J, share s of its row
+// blocks); wave w takes J's columns 16w .. 16w + 15 in scalar registers.
+// Per row block the four waves' row sums meet in LDS and are added in wave
+// order. vd: the network's Vd row; P: its partial sums.
+static __global__ __launch_bounds__(256) void k_pairs_sym(const float* __restrict__ vd, int n, int ki,
+                                                          float* __restrict__ P) {
+    __shared__ float s_row[4][kSymMaxKi + 1][64];
+    const int B = sym_blocks(n), K = sym_kmax(n), S = sym_shares(n, ki);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int g = blockIdx.x;
+    if (g >= B * S) return;
+    const int J = g / S, s = g - J * S;
+    float* prow = P;                                   // [B][K][64]
+    float* pcol = P + (int64_t)B * K * 64;             // [B][S][64]
+    float* pdiag = pcol + (int64_t)B * S * 64;         // [B][64]
+    double* bsum = reinterpret_cast<double*>(P + sym_vsum_off(n, ki));   // [B]
+    const int cj = J * 64 + lane;
+    const float vraw = cj < n ? vd[cj] : 0.0f;
+    const float vc = cj < n ? vraw * kPreScale : kSentinel;
+    float sc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sc[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vc), 16 * w + u));
+    // row blocks J + k, k in [k0, k1], of this workgroup
+    const int KJ = (B - 1) / 2 + ((B % 2 == 0 && J < B / 2) ? 1 : 0);
+    const int k0 = 1 + s * ki, k1 = min(KJ, s * ki + ki);
+    if (s == 0) {
+        // the block's own pairs, ordered, row sums only (a cell's term with
+        // itself is exactly zero); wave 0 also sums the block's voltages
+        float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 16; u += 2) {
+            const float d0 = vc - sc[u], d1 = vc - sc[u + 1];
+            a0 = fmaf(d0, __builtin_amdgcn_exp2f(-(d0 * d0)), a0);
+            a1 = fmaf(d1, __builtin_amdgcn_exp2f(-(d1 * d1)), a1);
+        }
+        s_row[w][kSymMaxKi][lane] = a0 + a1;
+        if (w == 0) {
+            double t = (double)vraw;
+            for (int m = 32; m > 0; m >>= 1) t += __shfl_xor(t, m, 64);
+            if (lane == 0) bsum[J] = t;
+        }
+    }
+    float acol[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acol[u] = 0.0f;
+    auto row_v = [&](int k) {
+        const int i = ((J + k) % B) * 64 + lane;
+        return i < n ? vd[i] * kPreScale : kSentinel;
+    };
+    float vnext = k0 <= k1 ? row_v(k0) : 0.0f;
+    for (int k = k0; k <= k1; ++k) {
+        const float vi = vnext;
+        if (k < k1) vnext = row_v(k + 1);
+        float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 16; u += 2) {
+            const float d0 = vi - sc[u], d1 = vi - sc[u + 1];
+            const float e0 = __builtin_amdgcn_exp2f(-(d0 * d0)), e1 = __builtin_amdgcn_exp2f(-(d1 * d1));
+            a0 = fmaf(d0, e0, a0);
+            a1 = fmaf(d1, e1, a1);
+            acol[u] = fmaf(-d0, e0, acol[u]);
+            acol[u + 1] = fmaf(-d1, e1, acol[u + 1]);
+        }
+        s_row[w][k - k0][lane] = a0 + a1;
+    }
+    // column sums over the 64 lanes: lane l ends with column 16w + (l & 15)'s
+    sym_halve<8>(acol, lane);
+    sym_halve<4>(acol, lane);
+    sym_halve<2>(acol, lane);
+    sym_halve<1>(acol, lane);
+    float c = acol[0];
+    c += __shfl_xor(c, 16, 64);
+    c += __shfl_xor(c, 32, 64);
+    if (lane < 16) pcol[((int64_t)J * S + s) * 64 + 16 * w + lane] = c;
+    __syncthreads();
+    // row sums: the four waves' parts in wave order; wave w stores rows
+    // blocks k0 + w, k0 + w + 4, .. (and wave 0 the block's own)
+    for (int q = w; q <= k1 - k0; q += 4)
+        prow[((int64_t)((J + k0 + q) % B) * K + (k0 + q - 1)) * 64 + lane] =
+            ((s_row[0][q][lane] + s_row[1][q][lane]) + s_row[2][q][lane]) + s_row[3][q][lane];
+    if (s == 0 && w == 0)
+        pdiag[(int64_t)J * 64 + lane] = ((s_row[0][kSymMaxKi][lane] + s_row[1][kSymMaxKi][lane]) +
+                                         s_row[2][kSymMaxKi][lane]) + s_row[3][kSymMaxKi][lane];
 }
 
 template <int BLOCK>

@@ -76,7 +76,7 @@ class Options(ctypes.Structure):
                 ("tile_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("csr_path", ctypes.c_int32), ("output_ring_steps", ctypes.c_int32),
-                ("wide_threads", ctypes.c_int32)]
+                ("wide_threads", ctypes.c_int32), ("pair_path", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -284,7 +284,7 @@ def mlp_adam_step(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e
 
 
 GAP_KIND = {"rgj": 0, "sgj": 1}
-GAP_PATH = ("none", "uniform", "dense", "csr_gather", "csr_chunked", "csr_bitmap", "csr_stream")
+GAP_PATH = ("none", "uniform", "dense", "csr_gather", "csr_chunked", "csr_bitmap", "csr_stream", "uniform_sym")
 
 
 class _SpecHolder:

@@ -1095,3 +1095,85 @@ def test_headline_mix_as_tuned(infoli, o32, o64):
         assert np.all(np.abs(ig[k] - ref_ig) <= tol), (k, np.max(np.abs(ig[k] - ref_ig) / tol))
         ref = o32.run(net, 1, x0=xk[k], step0=100)["x"]
         assert per_var_error(xk1[k][None], ref[None]).max() <= 1e-5
+
+
+# ------------------------------------------------------------------ all-to-all, each unordered pair once
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 128, 200, 777, 1000, 4097, 8193])
+def test_unordered_pairs_gap_current(infoli, o32, o64, n):
+    """pair_path=2: k_pairs_sym evaluates each unordered pair once and the step
+    adds the partial sums. Sizes: one block, one block plus one cell, even and
+    odd block counts, one or several waves per column block. Gap currents
+    against the fp64 oracle within the per-row bound, beside the ordered
+    pairs' (pair_path=1)."""
+    rs = I.rng(n + 101)
+    net = I.Network(n=n, conn="uniform", g=0.04, jitter=rs.uniform(-15, 15, (3, n)))
+    x0 = infoli.initial_state(net)
+    ref = o64.gap(net, x0[0].astype(np.float64))
+    tol = gap_bound(net, x0[0])
+    for pp, name in ((2, "uniform_sym"), (1, "uniform")):
+        sim = infoli.Simulator(net, init_states=[x0], pair_path=pp, step_mode="graph")
+        assert sim.gap_path(0)[0] == name
+        got = sim.read_gap_current(0).astype(np.float64)
+        sim.close()
+        err = np.max(np.abs(got - ref) / tol)
+        print(f"n={n} {name}: gap err / bound {err:.2e}")
+        assert err <= 1.0
+
+
+def test_unordered_pairs_trajectory(infoli, o32, o64):
+    """777 cells under a 25 ms pulse (every cell fires): 1,000 steps with each
+    unordered pair once against both oracles, spikes matched."""
+    net = I.config2(seed=1, n=777, pulse=True)
+    net.pulses = [I.Pulse(100, 600, 6.0)]
+    x0 = infoli.initial_state(net)
+    got, c, t = gpu_trace(infoli, net, 1000, 50, x0, pair_path=2, step_mode="graph")
+    ref = o32.run(net, 1000, x0=x0, trace_every=50, trace_cells=net.n)
+    r64 = o64.run(net, 1000, x0=x0.astype(np.float64), trace_every=50, trace_cells=net.n)
+    check_state_bounds(got, ref["trace"], r64["trace"], "uniform_sym n=777")
+    compare_spikes(c, t, ref["counts"], ref["times"], 64)
+    assert c.min() >= 1
+
+
+def test_unordered_pairs_by_default_from_4096_cells(infoli):
+    """Library choice: the realistic all-to-all form takes each unordered pair
+    once from 4,096 cells on; below that, in the simplified form (its closed
+    form) and in the persistent mode every network keeps its own path."""
+    def path(n, **kw):
+        net = I.Network(n=n, conn="uniform", g=0.04 * 96 / n, jitter=I.voltage_jitter(n, 5), **kw)
+        sim = infoli.Simulator(net, autotune=0)
+        p = sim.gap_path(0)[0]
+        sim.close()
+        return p
+    assert path(4096) == "uniform_sym"
+    assert path(4095) == "uniform"
+    assert path(4096, gap="sgj") == "uniform"
+    net = I.Network(n=1000, conn="uniform", g=0.04, jitter=I.voltage_jitter(1000, 6))
+    sim = infoli.Simulator(net, pair_path=2, step_mode="persistent")
+    assert sim.gap_path(0)[0] == "uniform"
+    sim.close()
+
+
+def test_unordered_pairs_bitwise_repeatable(infoli):
+    """Partial sums are added in a fixed order: graph replays, single launches
+    and a second context give bitwise equal states; identical cells stay
+    bitwise in sync."""
+    net = I.config2(seed=3, n=5000, pulse=True)
+    x0 = infoli.initial_state(net)
+    runs = []
+    for mode in ("graph", "graph", "launch"):
+        sim = infoli.Simulator(net, init_states=[x0], step_mode=mode, graph_chunk=50, autotune=0)
+        assert sim.gap_path(0)[0] == "uniform_sym"
+        sim.step(300)
+        runs.append(sim.read_state(0))
+        sim.close()
+    np.testing.assert_array_equal(runs[0], runs[1])
+    np.testing.assert_array_equal(runs[0], runs[2])
+    same = I.Network(n=300, conn="uniform", g=0.04, pulses=[I.Pulse(100, 600, 6.0)])
+    sim = infoli.Simulator(same, pair_path=2, step_mode="graph")
+    assert sim.gap_path(0)[0] == "uniform_sym"
+    sim.step(1500)
+    x = sim.read_state(0)
+    c, _ = sim.read_spikes(0)
+    sim.close()
+    assert np.all(x == x[:, :1])
+    assert np.all(c == c[0]) and c[0] >= 1
