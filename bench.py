@@ -134,16 +134,22 @@ def ingest_traffic(run_root):
         raise SystemExit("the FETCH_SIZE and WRITE_SIZE runs ran different configurations")
     r = runs["fetch"]
     n = r["steps"] + r["warmup"]
-    kname = r["roofline"]["kernel"].replace("infoli::", "")
+    # a step of two kernels ("A + B") adds both kernels' bytes
+    parts = [p.strip().replace("infoli::", "")
+             for p in r["roofline"]["kernel"].split("(concurrent")[0].split(" + ")]
     cf = _per_dispatch(_counter_rows(os.path.join(run_root, "copy_fetch")), "FETCH_SIZE", "", 0)
     cw = _per_dispatch(_counter_rows(os.path.join(run_root, "copy_write")), "WRITE_SIZE", "", 0)
     copy_kib = copy["copy_probe_bytes_read"] / 1024.0
     # the copy is the largest dispatch of its run
     fetch_factor = copy_kib / max(cf)
     write_factor = copy_kib / max(cw)
-    f = _per_dispatch(_counter_rows(os.path.join(run_root, "fetch")), "FETCH_SIZE", kname, n)
-    w = _per_dispatch(_counter_rows(os.path.join(run_root, "write")), "WRITE_SIZE", kname, n)
-    fk, wk = float(np.mean(f)), float(np.mean(w))
+    frows = _counter_rows(os.path.join(run_root, "fetch"))
+    wrows = _counter_rows(os.path.join(run_root, "write"))
+    fk = wk = 0.0
+    for kname in parts:
+        f = _per_dispatch(frows, "FETCH_SIZE", kname, n)
+        w = _per_dispatch(wrows, "WRITE_SIZE", kname, n)
+        fk, wk = fk + float(np.mean(f)), wk + float(np.mean(w))
     entry = {"kernel": r["roofline"]["kernel"], "dispatches": [len(f), len(w)],
              "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
              "fetch_factor": round(fetch_factor, 4), "write_factor": round(write_factor, 4),
@@ -798,6 +804,11 @@ def rt_sweep(args, torch, infoli):
     steps in the library's automatic launch mode."""
     budget = args.rt_budget_us
     cases = ["RGJ 100%", "RGJ 75%", "RGJ 50%", "RGJ 25%", "SGJ 100%", "SGJ 75%", "SGJ 50%", "SGJ 25%", "NGJ"]
+    if args.rt_case:
+        unknown = sorted(set(args.rt_case) - set(cases))
+        if unknown:
+            raise SystemExit(f"--rt-case: unknown {unknown}; one of {cases}")
+        cases = [c for c in cases if c in args.rt_case]
     max_edges = 2.6e8
     out = []
     for case in cases:
@@ -904,6 +915,8 @@ def main():
     ap.add_argument("--rt-sweep", action="store_true",
                     help="only run the real-time size sweep (largest network per use case within the budget)")
     ap.add_argument("--rt-budget-us", type=float, default=50.0)
+    ap.add_argument("--rt-case", action="append", default=[],
+                    help="with --rt-sweep: only this use case (repeatable), e.g. 'RGJ 100%%'")
     ap.add_argument("--paper-batches", action="store_true",
                     help="only run Table 4's experiment batches (per size, five densities)")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,

@@ -179,8 +179,9 @@ typedef struct infoli_options {
                                     networks of >= 4,096 cells, column blocks, wide bitmap
                                     tiles): 0 => timed by the tuner (else 1024); 512 or 1024 */
     int32_t pair_path;           /* all-to-all networks with the realistic gap term:
-                                    0 => library choice (each unordered pair once from
-                                    4,096 cells on, every ordered pair below); 1 => every
+                                    0 => library choice (each unordered pair once for a
+                                    context's only network from 4,096 cells on, every
+                                    ordered pair below and in batches); 1 => every
                                     ordered pair; 2 => each unordered pair once (the pair
                                     term of Section 2.3.1, Algorithm 1, is odd in dV,
                                     so the pair (j, i) gives minus the term of (i, j)).

@@ -429,7 +429,7 @@ void build_blocks(infoli_ctx* c, const infoli_network_spec* specs) {
 // weights follow the same layout, 0 on padding.
 // All-to-all networks whose pairs are taken once (k_pairs_sym): the
 // realistic gap term (the simplified one has its O(n) closed form), tiled
-// steps; from kSymCells cells on by default. Row blocks per workgroup:
+// steps; by default a context's only network, from kSymCells cells on. Row blocks per workgroup:
 // about 2,048 workgroups (8,192 waves) per launch, 4 to 16 row blocks each
 // (the column sums' lane reduction is paid once per wave).
 void build_sym(infoli_ctx* c) {
@@ -439,7 +439,11 @@ void build_sym(infoli_ctx* c) {
         d.sym = 0;
         d.psym_off = 0;
         d.sym_ki = 0;
-        const bool want = c->opt.pair_path == 2 || (c->opt.pair_path == 0 && d.n >= kSymCells);
+        // by default only a lone network: in a batch the ordered tiles share one
+        // launch with the other networks' tiles, which measured faster than the
+        // pair kernel running ahead of that launch (Table 4's batches of 5,760
+        // and 7,680 cells: 41.6 / 61.8 us per step against 47.5 / 70.5)
+        const bool want = c->opt.pair_path == 2 || (c->opt.pair_path == 0 && d.n >= kSymCells && c->n_inst == 1);
         if (d.conn != CONN_UNIFORM || d.sgj || !want || c->opt.step_mode == INFOLI_MODE_PERSISTENT) continue;
         const int64_t work = (int64_t)sym_blocks(d.n) * sym_kmax(d.n);
         d.sym = 1;

@@ -243,3 +243,22 @@ def test_traffic_ingest_takes_the_timed_dispatches(tmp_path, monkeypatch):
     assert e["kernel_sources_sha256"] == bench.kernel_source_hash()
     assert bench.measured_traffic("c4|k|p|wide1024") == 1024 * 23
     assert bench.measured_traffic("c4|k|p|wide512") is None
+
+
+def test_unordered_pair_roofline_counts_its_own_work():
+    """Each unordered pair once: 7.3 slots per pair of distinct blocks (v_sub,
+    v_mul, the exponential, two v_fma), the ordered 6.3 inside each 64-cell
+    block, 368 per cell; the two kernels of the step are named."""
+    n = 200                                    # 4 blocks: 4 x 64 x 64 own pairs
+    net = I.Network(n=n, conn="uniform", g=0.04)
+    own = 4 * 64 * 64
+    slots = 7.3 * (n * n - own) / 2 + 6.3 * own + bench.CELL_SLOTS * n
+    r = bench.roofline([net], 1e-6, "k", ["uniform_sym"])
+    assert r["bound"] == "alu" and r["unit"] == "T lane-slots/s"
+    assert r["slots_per_launch"] == pytest.approx(slots)
+    assert r["frac"] == pytest.approx(slots / 1e-6 / bench.LANE_SLOTS_PER_S)
+    assert r["ordered_pair_frac"] == pytest.approx(n * n / 1e-6 / (bench.LANE_SLOTS_PER_S / 6.3))
+    assert bench.slots_of(net, "uniform_sym") == pytest.approx(slots)
+    info = {"step_mode": 0, "n_tiles_wide": 4, "n_tiles": 4, "wide_threads": 1024}
+    assert bench.step_kernel_name(info, [net], ["uniform_sym"]) == \
+        "infoli::k_pairs_sym + infoli::k_step<1024, 2>"

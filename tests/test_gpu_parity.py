@@ -1136,8 +1136,9 @@ def test_unordered_pairs_trajectory(infoli, o32, o64):
 
 def test_unordered_pairs_by_default_from_4096_cells(infoli):
     """Library choice: the realistic all-to-all form takes each unordered pair
-    once from 4,096 cells on; below that, in the simplified form (its closed
-    form) and in the persistent mode every network keeps its own path."""
+    once from 4,096 cells on in a context of one network; below that, in a
+    batch, in the simplified form (its closed form) and in the persistent mode
+    every network keeps its own path (pair_path=2 asks for it in a batch)."""
     def path(n, **kw):
         net = I.Network(n=n, conn="uniform", g=0.04 * 96 / n, jitter=I.voltage_jitter(n, 5), **kw)
         sim = infoli.Simulator(net, autotune=0)
@@ -1147,6 +1148,15 @@ def test_unordered_pairs_by_default_from_4096_cells(infoli):
     assert path(4096) == "uniform_sym"
     assert path(4095) == "uniform"
     assert path(4096, gap="sgj") == "uniform"
+    # in a batch the ordered tiles share the launch with the other networks
+    big = I.Network(n=5000, conn="uniform", g=0.01, jitter=I.voltage_jitter(5000, 7))
+    small = I.Network(n=100, conn="none")
+    sim = infoli.Simulator([big, small], autotune=0)
+    assert sim.gap_path(0)[0] == "uniform"
+    sim.close()
+    sim = infoli.Simulator([big, small], autotune=0, pair_path=2)
+    assert sim.gap_path(0)[0] == "uniform_sym"
+    sim.close()
     net = I.Network(n=1000, conn="uniform", g=0.04, jitter=I.voltage_jitter(1000, 6))
     sim = infoli.Simulator(net, pair_path=2, step_mode="persistent")
     assert sim.gap_path(0)[0] == "uniform"
