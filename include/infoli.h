@@ -159,7 +159,7 @@ typedef struct infoli_options {
     int32_t check_finite;        /* 1 => a NaN/Inf state makes infoli_sync fail            */
     int32_t autotune;            /* CSR tile shapes: 0 => built-in rule; 1 => timed on the
                                     device at init, cached on disk (INFOLI_TUNE_CACHE, else
-                                    ~/.cache/infoli-tune-v13.txt); 2 => timed, cache ignored */
+                                    ~/.cache/infoli-tune-v14.txt); 2 => timed, cache ignored */
     int32_t csr_path;            /* CSR networks: 0 => tuned choice; 1 => edge gathers;
                                     2 => coupling bitmap (one weight g, <= 16,384 cells;
                                     in the wide group when wide_threads is set);

@@ -632,13 +632,14 @@ struct TuneChoice {
                            // path (0 gathers, 1 bitmap, 2 blocked, 3 chunked gathers,
                            // 4 blocked chunk stream)
     int block;             // workgroup size timed (256 or 1024; the wide group may run 512)
+    int rnd = kStreamRound;   // chunk stream: chunks per round (kStreamRound or half of it)
 };
 
 std::string tune_cache_path() {
     const char* p = std::getenv("INFOLI_TUNE_CACHE");
     if (p && *p) return p;
     const char* h = std::getenv("HOME");
-    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v13.txt";
+    if (h && *h) return std::string(h) + "/.cache/infoli-tune-v14.txt";
     return "";
 }
 
@@ -680,8 +681,9 @@ std::map<std::string, TuneChoice> read_tune_cache(const std::string& path,
             continue;
         }
         TuneChoice t;
-        if (std::sscanf(bar + 1, "%d %d %d %d %d", &t.L, &t.R, &t.lds, &t.bm, &t.block) == 5 &&
-            (t.block == 256 || t.block == 1024) && t.L >= 4 && t.L <= 1024 &&
+        if (std::sscanf(bar + 1, "%d %d %d %d %d %d", &t.L, &t.R, &t.lds, &t.bm, &t.block, &t.rnd) == 6 &&
+            (t.block == 256 || t.block == 512 || t.block == 1024) && t.L >= 4 && t.L <= 1024 &&
+            (t.rnd == kStreamRound || t.rnd == kStreamRound / 2) &&
             (t.L & (t.L - 1)) == 0 && t.R >= 1 && t.R <= kMaxTileRows && (t.lds == 0 || t.lds == 1) &&
             (t.bm >= 0 && t.bm <= 4))
             m[line] = t;
@@ -715,7 +717,7 @@ void tune_log(const char* fmt, ...) {
 
 void append_tune_cache(const std::string& path, const std::string& key, const TuneChoice& t) {
     char buf[64];
-    snprintf(buf, sizeof buf, "|%d %d %d %d %d", t.L, t.R, t.lds, t.bm, t.block);
+    snprintf(buf, sizeof buf, "|%d %d %d %d %d %d", t.L, t.R, t.lds, t.bm, t.block, t.rnd);
     append_tune_line(path, key + buf);
 }
 
@@ -775,6 +777,7 @@ float time_shape(infoli_ctx* c, const std::vector<int>& ks, const TuneChoice& t,
         d.bitmap = t.bm == 1;
         d.blocked = t.bm == 2 || t.bm == 4;
         d.stream = t.bm == 4;
+        d.stream_round = t.bm == 4 ? t.rnd : kStreamRound;
         d.chunked = t.bm == 3;
         HIPX(hipMemcpy(c->d_inst + k, &d, sizeof(d), hipMemcpyHostToDevice));
         append_tiles(planned, k, d.n, t.R, 0.0);
@@ -836,6 +839,7 @@ void apply_choice(infoli_ctx* c, const std::vector<int>& ks, TuneChoice best) {
         c->inst[k].bitmap = best.bm == 1;
         c->inst[k].blocked = best.bm == 2 || best.bm == 4;
         c->inst[k].stream = best.bm == 4;
+        c->inst[k].stream_round = best.bm == 4 ? best.rnd : kStreamRound;
         c->inst[k].chunked = best.bm == 3;
         c->inst[k].wide = best.block == 1024;
         c->rows_of[k] = best.R;
@@ -934,8 +938,8 @@ void autotune_shapes(infoli_ctx* c) {
             // by the fixed preference), best256 also as the search goes on
             auto consider = [&](const TuneChoice& t) {
                 const float ms = time_shape(c, ks, t, d_tmp);
-                tune_log("class %s shape L%d R%d lds%d path%d block%d: %.2f us", key.c_str(), t.L, t.R, t.lds,
-                         t.bm, t.block, 1e3f * ms);
+                tune_log("class %s shape L%d R%d lds%d path%d block%d round%d: %.2f us", key.c_str(), t.L, t.R, t.lds,
+                         t.bm, t.block, t.rnd, 1e3f * ms);
                 all.push_back({ms, t});
                 if (t.block == 256) {
                     timed.push_back({ms, t});
@@ -986,7 +990,8 @@ void autotune_shapes(infoli_ctx* c) {
                     InstDesc d = c->inst[ks[0]];
                     d.blocked = d.stream = 1;
                     if (lds_floats_for(c, d, blk) * sizeof(float) + kStaticLds <= (size_t)c->lds_max)
-                        consider(TuneChoice{64, kSelfSlots, 0, 4, blk});
+                        for (int rnd : {kStreamRound, kStreamRound / 2})
+                            consider(TuneChoice{64, kSelfSlots, 0, 4, blk, rnd});
                 }
             // the column-blocked path, when every network of the class has it
             bool all_blk = c->d_blk != nullptr;
@@ -1303,6 +1308,7 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         d.sgj = s.gap_kind == INFOLI_GAP_SIMPLIFIED ? 1 : 0;
         d.pcell = s.cell_params ? 1 : 0;
         d.stream_off = -1;
+        d.stream_round = kStreamRound;
         std::memcpy(&d.p, s.params ? s.params : kDefaultParams, sizeof(CellParams));
         cells += s.n_cells;
         if (s.conn == INFOLI_CONN_DENSE) {

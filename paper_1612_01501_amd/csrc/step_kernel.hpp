@@ -83,7 +83,7 @@ struct InstDesc {
     int64_t chkb_off;      // chunked blocks: first chunk of the network
     int64_t psym_off;      // sym: offset of the network's partial sums in StepArgs::psym
     int32_t sym_ki;        // sym: row blocks per wave of k_pairs_sym
-    int32_t pad_sym;
+    int32_t stream_round;  // stream: chunks per round (0: kStreamRound)
     CellParams p;
 };
 
@@ -887,6 +887,9 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
     constexpr int STAGE = kStreamCols / BLOCK;            // block voltages staged per thread (C = kStreamCols)
     constexpr int SW = kStreamSweeps;
     static_assert(OWN >= 1 && OWN <= 64, "owners per row");
+    // chunks per round: the descriptor's (the tuner times kStreamRound and
+    // half of it), else kStreamRound; the LDS holds two rounds of kStreamRound
+    const int RND = (d.stream_round >= 64 && d.stream_round <= kStreamRound) ? d.stream_round : kStreamRound;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // descriptor fields in registers: read once, not again inside the loop
@@ -933,14 +936,14 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
     auto first_round_from = [&](int b0) {    // the first piece of the first round of block b0 or later
         for (int b = b0; b < nblk; ++b) {
             const int r0 = uni(s_off[b * nr1]), re = uni(s_off[b * nr1 + nrows]);
-            if (r0 < re) return piece_of(b, re, r0, min(re, r0 + kStreamRound), 0);
+            if (r0 < re) return piece_of(b, re, r0, min(re, r0 + RND), 0);
         }
         return StreamPiece{nblk, 0, 0, 0, 0, 0, 0, 1};
     };
     // within a block from registers only; LDS is read at block changes
     auto next_piece = [&](const StreamPiece& p) {
         if (p.j + 1 < p.npieces) return piece_of(p.b, p.re, p.r0, p.r1, p.j + 1);
-        if (p.r1 < p.re) return piece_of(p.b, p.re, p.r1, min(p.re, p.r1 + kStreamRound), 0);
+        if (p.r1 < p.re) return piece_of(p.b, p.re, p.r1, min(p.re, p.r1 + RND), 0);
         return first_round_from(p.b + 1);
     };
     auto next_block = [&](int b) {     // the next block with chunks after b, nblk if none
@@ -988,7 +991,13 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
             const int rlo = max(s_off[p.b * nr1 + orow], p.r0), rhi = min(s_off[p.b * nr1 + orow + 1], p.r1);
             for (int c = rlo + oq; c < rhi; c += OWN) part += sums[c - p.r0];
         }
-        rowacc += wave_sum_xor(part, OWN);
+        // the OWN owners of a row are the lanes of a quad (or half of one):
+        // add them through DPP, in wave_sum_xor's order, without a trip to LDS
+        static_assert(OWN == 2 || OWN == 4, "owners per row");
+        if constexpr (OWN == 4)
+            part += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(part), 0x4E, 0xF, 0xF, false));
+        part += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(part), 0xB1, 0xF, 0xF, false));
+        rowacc += part;
     };
     // all C slots are loaded and stored, past the network's last cell too:
     // the state buffer holds 14 rows of at least n > C / 2 cells after Vd,
@@ -1021,7 +1030,7 @@ __device__ __forceinline__ void gap_stream_blocked(const StepArgs& a, const Inst
     {
         const int g0 = uni(cb[t.row0]), g1 = uni(cb[t.row1]);
         if (nblk > 0 && g0 < g1) {
-            cur = piece_of(0, g1, g0, min(g1, g0 + kStreamRound), 0);
+            cur = piece_of(0, g1, g0, min(g1, g0 + RND), 0);
             load_voltages(0);
             load(q[0], tg[0], cur);
         }
