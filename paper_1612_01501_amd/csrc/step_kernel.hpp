@@ -82,7 +82,7 @@ struct InstDesc {
     int64_t cb_off;        // chunked blocks: offset of the [n][nblk + 1] chunk starts, -1 none
     int64_t chkb_off;      // chunked blocks: first chunk of the network
     int64_t psym_off;      // sym: offset of the network's partial sums in StepArgs::psym
-    int32_t sym_ki;        // sym: row blocks per wave of k_pairs_sym
+    int32_t sym_ki;        // sym: row blocks per workgroup of k_pairs_sym
     int32_t stream_round;  // stream: chunks per round (0: kStreamRound)
     CellParams p;
 };
@@ -306,13 +306,15 @@ __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d
 // whose terms against any cell are zero). The pairs of distinct blocks
 // {J, J + k mod B}, 1 <= k <= B / 2 (k = B / 2 only for J < B / 2 when B is
 // even, so that each block pair is taken once), belong to column block J.
-// A wave holds J's 64 voltages in scalar registers and takes sym_ki row
-// blocks I = J + k in turn, lanes being I's cells: per pair one difference,
-// square, exponential and two fused multiply-adds, one into the row's sum
-// (written for (I, k)) and one into the column's (added over the wave's row
-// blocks, then over its lanes). Each block's own 64 x 64 ordered pairs give
-// its row sums directly. The step adds a cell's partial sums in a fixed
-// order, so results do not depend on scheduling.
+// A workgroup of four waves takes sym_ki row blocks I = J + k in turn,
+// lanes being I's cells, each wave with 16 of J's voltages in scalar
+// registers: per pair one difference, square, exponential and two fused
+// multiply-adds, one into the row's sum (the four waves' parts added in LDS,
+// written for (I, k)) and one into the column's (added over the row blocks,
+// then over the lanes). Each block's own 64 x 64 ordered pairs give its row
+// sums directly. The step adds a cell's partial sums in a fixed order, so
+// results do not depend on scheduling.
+
 // Halving step of a lane-transposed sum: v[0 .. 2H) are sums of 2H
 // consecutive columns over this lane; afterwards v[0 .. H) hold the sums over
 // this lane and lane ^ H of the half of them selected by bit H of the lane.
@@ -805,14 +807,15 @@ __device__ __forceinline__ void gap_chunks_blocked(const StepArgs& a, const Inst
 // ---------------------------------------------------------------- chunk stream
 // Column blocks read as one flat stream per tile: in the block-major layout
 // the chunks of the tile's rows in block b are one contiguous run
-// [cb[b][row0], cb[b][row1]). A round is that run (cut at kStreamRound
-// chunks); every wave takes a contiguous share of the round's 64-chunk
+// [cb[b][row0], cb[b][row1]). A round is that run, cut at the network's
+// round size (kStreamRound or half of it, as the tuner timed them); every
+// wave takes a contiguous share of the round's 64-chunk
 // sweeps (lane l the l-th chunk of a sweep: one coalesced 1 KB load), in
 // pieces of kStreamSweeps sweeps. A one-byte tag per chunk (its row mod 256)
 // selects the row's own voltage; the chunk's eight terms go to an LDS slot of
 // their own. Waves run a round's pieces without synchronising; at the round's
-// end the OWN threads owning each row add that row's slots in a fixed order
-// (bitwise reproducible). Two register sets alternate: while one piece is
+// end the OWN threads owning each row (lanes of one quad) add that row's
+// slots in a fixed order (bitwise reproducible). Two register sets alternate: while one piece is
 // summed the next piece's loads are in flight, and the next block's voltages
 // load during the current block. kStreamSets register sets rotate, so that
 // the loads of kStreamSets - 1 pieces are in flight while one is summed.
@@ -820,7 +823,7 @@ constexpr int kStreamSweeps = 4;
 constexpr int kStreamSets = 2;
 constexpr int kStreamMaxBlocks = 8;    // column blocks whose chunk offsets a tile keeps in LDS
 constexpr int kStreamCols = 16384;     // the column block (C) the stream is compiled for
-constexpr int kStreamRound = 8192;     // chunk sums of one round in LDS (two buffers)
+constexpr int kStreamRound = 8192;     // largest round: chunk sums of two rounds fit in LDS
 constexpr size_t kStaticLds = 8192;    // bound on k_step's static LDS (s_ig, s_part, s_red)
 
 // LDS floats of a stream tile: block voltages, own voltages, chunk sums of

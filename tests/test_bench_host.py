@@ -262,3 +262,16 @@ def test_unordered_pair_roofline_counts_its_own_work():
     info = {"step_mode": 0, "n_tiles_wide": 4, "n_tiles": 4, "wide_threads": 1024}
     assert bench.step_kernel_name(info, [net], ["uniform_sym"]) == \
         "infoli::k_pairs_sym + infoli::k_step<1024, 2>"
+
+
+def test_source_hash_ignores_comments_only():
+    """The traffic records are keyed by the kernel sources' code: comments and
+    layout do not count, string literals and code do."""
+    a = 'int x = 1; // one\n/* two */ const char* s = "a // b";\n'
+    b = 'int  x = 1;\n\n const char* s = "a // b"; // other words\n'
+    c = 'int x = 2; const char* s = "a // b";'
+    d = 'int x = 1; const char* s = "a /* b";'
+    assert bench.code_of(a) == bench.code_of(b)
+    assert bench.code_of(a) != bench.code_of(c)
+    assert bench.code_of(a) != bench.code_of(d)
+    assert "a // b" in bench.code_of(a)
