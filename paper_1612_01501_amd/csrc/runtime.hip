@@ -808,10 +808,13 @@ constexpr float kTieMargin = 0.03f;
 
 // Preference among equally fast shapes: chunk stream, bitmap, chunked
 // gathers, gathers, column blocks; then the wider workgroup; then fewer
-// lanes per row, fewer rows, no LDS staging.
+// lanes per row, fewer rows, no LDS staging; then the smaller round of the
+// chunk stream (its rounds of 4,096 chunks timed 3-4 % faster than 8,192 at
+// 65,536 cells of degree 1,000, close to the margin).
 int64_t pref_key(const TuneChoice& t) {
     static const int rank[5] = {3, 1, 4, 2, 0};   // by bm: 0 gathers .. 4 stream
-    return ((((int64_t)rank[t.bm] * 2 + (t.block == 256 ? 1 : 0)) * 1024 + t.L) * 1024 + t.R) * 2 + t.lds;
+    return (((((int64_t)rank[t.bm] * 2 + (t.block == 256 ? 1 : 0)) * 1024 + t.L) * 1024 + t.R) * 2 + t.lds) * 2 +
+           (t.rnd < kStreamRound ? 0 : 1);
 }
 
 // The preferred entry among those within kTieMargin of the fastest; none
