@@ -202,7 +202,8 @@ def tuned_config(info, sim, nets):
             "gap_paths": sorted(set(sim.gap_path(k)[0] for k in range(len(nets)))),
             "step_kernel": step_kernel_name(info, nets, [sim.gap_path(k)[0] for k in range(len(nets))]),
             "tuned_networks": info["tuned"], "tune_cached_networks": info["tune_cached"],
-            "csr_stream_networks": info["n_stream"], "tune_mode": info["tune_mode"]}
+            "csr_stream_networks": info["n_stream"], "tune_mode": info["tune_mode"],
+            "stream_round": info["stream_round"], "unordered_pair_networks": info["n_sym"]}
 
 
 WORKLOADS = {

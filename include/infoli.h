@@ -305,6 +305,9 @@ typedef struct infoli_info {
                                    4 no chunked 256-thread gathers, 8 every class in its
                                    1024-thread shape, 16 wide group of 512 threads, 32
                                    every class with a bitmap shape on it)                 */
+    int32_t stream_round;       /* chunks per round of the chunk stream networks (the
+                                   largest; 8,192 or 4,096 as the tuner timed), 0 none    */
+    int32_t n_sym;              /* all-to-all networks taking each unordered pair once  */
 } infoli_info;
 infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
 

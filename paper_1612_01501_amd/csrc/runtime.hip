@@ -1957,6 +1957,11 @@ infoli_status infoli_get_info(const infoli_ctx* ctx, infoli_info* info) {
         info->n_bitmap += d.conn == CONN_CSR && d.bitmap;
         info->n_blocked += d.conn == CONN_CSR && d.blocked;
         info->n_stream += d.conn == CONN_CSR && d.blocked && d.stream;
+        if (d.conn == CONN_CSR && d.blocked && d.stream)
+            info->stream_round = std::max(info->stream_round,
+                                          d.stream_round >= 64 && d.stream_round <= kStreamRound ? d.stream_round
+                                                                                                 : kStreamRound);
+        info->n_sym += d.conn == CONN_UNIFORM && d.sym && ctx->opt.step_mode != INFOLI_MODE_PERSISTENT;
     }
     return INFOLI_OK;
 }

@@ -88,7 +88,7 @@ class Info(ctypes.Structure):
                 ("tune_cached", ctypes.c_int32), ("n_tiles_wide", ctypes.c_int32),
                 ("n_bitmap", ctypes.c_int32), ("n_blocked", ctypes.c_int32),
                 ("wide_threads", ctypes.c_int32), ("n_stream", ctypes.c_int32),
-                ("tune_mode", ctypes.c_int32)]
+                ("tune_mode", ctypes.c_int32), ("stream_round", ctypes.c_int32), ("n_sym", ctypes.c_int32)]
 
 
 class TrainCfg(ctypes.Structure):

@@ -495,6 +495,43 @@ def test_autotuner_times_caches_and_stays_exact(infoli, o32, tmp_path, monkeypat
         assert per_var_error(out[0][k][None], ref[None]).max() <= TOL_STATE
 
 
+def test_stream_round_is_tuned_cached_and_exact(infoli, o32, o64, tmp_path, monkeypatch):
+    """The chunk stream's round size (8,192 or 4,096 chunks) is timed with its
+    shapes, reported by infoli_get_info, written to the tuning cache and read
+    back; the forced stream (csr_path=5) keeps 8,192. The tuned context's
+    gap currents against fp64 and one step against the oracle; the cached
+    context reproduces it bitwise."""
+    monkeypatch.setenv("INFOLI_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    net = I.config4(seed=5, n=40000, degree=300)
+    x0 = infoli.initial_state(net)
+    states, rounds = [], []
+    for mode in (2, 1):
+        sim = infoli.Simulator(net, init_states=[x0], autotune=mode, step_mode="graph", graph_chunk=50)
+        info = sim.info()
+        rounds.append(info["stream_round"])
+        if sim.gap_path(0)[0] == "csr_stream":
+            assert info["stream_round"] in (4096, 8192) and info["n_stream"] == 1
+        else:
+            assert info["stream_round"] == 0
+        assert info["tune_cached"] == (1 if mode == 1 else 0)
+        sim.step(50)
+        xk = sim.read_state(0)
+        ig = sim.read_gap_current(0).astype(np.float64)
+        sim.step(1)
+        states.append((xk, sim.read_state(0)))
+        sim.close()
+    print(f"tuned round {rounds[0]}, cached {rounds[1]}")
+    assert rounds[0] == rounds[1]
+    np.testing.assert_array_equal(states[0][1], states[1][1])
+    tol = gap_bound(net, xk[0])
+    assert np.all(np.abs(ig - o64.gap(net, xk[0].astype(np.float64))) <= tol)
+    ref = o32.run(net, 1, x0=states[0][0], step0=50)["x"]
+    assert per_var_error(states[0][1][None], ref[None]).max() <= 1e-5
+    sim = infoli.Simulator(net, init_states=[x0], csr_path=5)
+    assert sim.info()["stream_round"] == 8192
+    sim.close()
+
+
 def test_cached_wide_step_mode_is_read_back(infoli, o32, tmp_path, monkeypatch):
     """A whole-step choice with the high mode bits set (wide group in
     512-thread workgroups) is taken from the cache as stored: the second
