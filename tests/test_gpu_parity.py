@@ -1194,6 +1194,26 @@ def test_unordered_pairs_by_default_from_4096_cells(infoli):
     sim = infoli.Simulator([big, small], autotune=0, pair_path=2)
     assert sim.gap_path(0)[0] == "uniform_sym"
     sim.close()
+
+
+def test_unordered_pairs_in_a_batch_match_standalone_bitwise(infoli):
+    """A network taking each unordered pair once inside a batch (behind a CSR
+    network, so its cells start past the first ones, graph steps with forked
+    launch groups) steps bitwise like the same network alone."""
+    big = I.config2(seed=4, n=4500, pulse=True)
+    csr = I.config1(0.1, seed=6, n=700)
+    x0s = [infoli.initial_state(n) for n in (csr, big)]
+    sim = infoli.Simulator([csr, big], init_states=x0s, pair_path=2, autotune=0, step_mode="graph",
+                           graph_chunk=50)
+    assert sim.gap_path(1)[0] == "uniform_sym"
+    sim.step(600)
+    batch = sim.read_state(1)
+    sim.close()
+    sim = infoli.Simulator(big, init_states=[x0s[1]], pair_path=2, autotune=0, step_mode="graph",
+                           graph_chunk=50)
+    sim.step(600)
+    np.testing.assert_array_equal(sim.read_state(0), batch)
+    sim.close()
     net = I.Network(n=1000, conn="uniform", g=0.04, jitter=I.voltage_jitter(1000, 6))
     sim = infoli.Simulator(net, pair_path=2, step_mode="persistent")
     assert sim.gap_path(0)[0] == "uniform"
