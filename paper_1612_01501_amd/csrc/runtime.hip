@@ -429,9 +429,10 @@ void build_blocks(infoli_ctx* c, const infoli_network_spec* specs) {
 // weights follow the same layout, 0 on padding.
 // All-to-all networks whose pairs are taken once (k_pairs_sym): the
 // realistic gap term (the simplified one has its O(n) closed form), tiled
-// steps; by default a context's only network, from kSymCells cells on. Row blocks per workgroup:
-// about 2,048 workgroups (8,192 waves) per launch, 4 to 16 row blocks each
-// (the column sums' lane reduction is paid once per wave).
+// steps; by default a context's only network, from kSymCells cells on. Row
+// blocks per workgroup: the most of 16, 8, 4 that still leaves at least 512
+// workgroups (measured best at 4,096, 8,192 and 16,384 cells; the column
+// sums' lane reduction is paid once per workgroup's share).
 void build_sym(infoli_ctx* c) {
     int64_t total = 0;
     for (int k = 0; k < c->n_inst; ++k) {
@@ -445,9 +446,13 @@ void build_sym(infoli_ctx* c) {
         // and 7,680 cells: 41.6 / 61.8 us per step against 47.5 / 70.5)
         const bool want = c->opt.pair_path == 2 || (c->opt.pair_path == 0 && d.n >= kSymCells && c->n_inst == 1);
         if (d.conn != CONN_UNIFORM || d.sgj || !want || c->opt.step_mode == INFOLI_MODE_PERSISTENT) continue;
-        const int64_t work = (int64_t)sym_blocks(d.n) * sym_kmax(d.n);
         d.sym = 1;
-        d.sym_ki = (int32_t)std::min<int64_t>(kSymMaxKi, std::max<int64_t>(4, work / 2048));
+        d.sym_ki = 4;
+        for (int ki : {kSymMaxKi, kSymMaxKi / 2})
+            if ((int64_t)sym_blocks(d.n) * sym_shares(d.n, ki) >= 512) {
+                d.sym_ki = ki;
+                break;
+            }
         d.psym_off = total;
         total += sym_floats(d.n, d.sym_ki);
     }
