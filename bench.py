@@ -359,6 +359,9 @@ def step_kernel_name(info, nets, paths=None):
     if paths and any(p == "uniform_sym" for p in paths):
         rest = step_kernel_name(info, nets, [p if p != "uniform_sym" else "uniform" for p in paths])
         return "infoli::k_pairs_sym + " + rest
+    if paths and any(p == "uniform_sum" for p in paths):
+        rest = step_kernel_name(info, nets, [p if p != "uniform_sum" else "uniform" for p in paths])
+        return "infoli::k_vsum + " + rest
     if paths and all(p == "csr_stream" for p in paths):
         return f"infoli::k_step<{info.get('wide_threads', 1024)}, 3>"
     if all(n.conn == "none" and n.cell_params is None for n in nets):

@@ -188,7 +188,12 @@ typedef struct infoli_options {
                                     Once costs
                                     64 x (B/2 + waves + 1) x B floats of partial sums per
                                     network of B = ceil(n/64) blocks (8.4 MB at 16,384
-                                    cells)                                                 */
+                                    cells). With the simplified term (the closed form of
+                                    Section 2.3.2 needs the sum of all voltages): 0 =>
+                                    that sum once per step by a separate kernel for a
+                                    context's only network from 20,480 cells on, else by
+                                    every tile; 1 => by every tile; 2 => once per step
+                                    (8 bytes per 4,096 cells)                              */
 } infoli_options;
 
 typedef struct infoli_ctx infoli_ctx;
@@ -307,7 +312,8 @@ typedef struct infoli_info {
                                    every class with a bitmap shape on it)                 */
     int32_t stream_round;       /* chunks per round of the chunk stream networks (the
                                    largest; 8,192 or 4,096 as the tuner timed), 0 none    */
-    int32_t n_sym;              /* all-to-all networks taking each unordered pair once  */
+    int32_t n_sym;              /* all-to-all networks taking each unordered pair once,
+                                   or (simplified term) their voltage sum once per step  */
 } infoli_info;
 infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
 
@@ -329,6 +335,10 @@ infoli_status infoli_get_info(const infoli_ctx *ctx, infoli_info *info);
  *   UNIFORM_SYM all-to-all, each unordered pair once: a separate kernel
  *               writes per-block partial sums, the step adds them per cell
  *               in a fixed order (option pair_path).
+ *   UNIFORM_SUM all-to-all with the simplified term: a separate kernel
+ *               writes fp64 sums of the voltages of each 4,096 cells, and
+ *               every tile adds those instead of all n voltages (option
+ *               pair_path).
  * (The persistent step mode walks CSR rows from the gather format.)
  * *path receives the code; *vd_blocked (either pointer may be NULL) receives
  * 1 when the network's Vd is staged in LDS one column block at a time (CSR
@@ -342,7 +352,8 @@ typedef enum infoli_gap_path {
     INFOLI_PATH_CSR_CHUNKED = 4,
     INFOLI_PATH_CSR_BITMAP = 5,
     INFOLI_PATH_CSR_STREAM = 6,
-    INFOLI_PATH_UNIFORM_SYM = 7
+    INFOLI_PATH_UNIFORM_SYM = 7,
+    INFOLI_PATH_UNIFORM_SUM = 8
 } infoli_gap_path;
 infoli_status infoli_get_gap_path(const infoli_ctx *ctx, int32_t instance, int32_t *path, int32_t *vd_blocked);
 

@@ -206,6 +206,12 @@ void infoli_rt::launch_groups(infoli_ctx* c, hipStream_t st, const StepArgs& a, 
     for (int k = 0; k < c->n_inst; ++k) {
         const InstDesc& d = c->inst[k];
         if (!d.sym) continue;
+        if (d.sgj) {
+            hipLaunchKernelGGL(k_vsum, dim3((unsigned)vsum_groups(d.n)), dim3(256), 0, st,
+                               c->state[from] + (int64_t)SV_VD * c->stride + d.cell_off, d.n,
+                               reinterpret_cast<double*>(c->d_psym + d.psym_off));
+            continue;
+        }
         const int64_t groups = (int64_t)sym_blocks(d.n) * sym_shares(d.n, d.sym_ki);
         hipLaunchKernelGGL(k_pairs_sym, dim3((unsigned)groups), dim3(256), 0, st,
                            c->state[from] + (int64_t)SV_VD * c->stride + d.cell_off, d.n, d.sym_ki,
@@ -253,7 +259,7 @@ void append_tiles(std::vector<std::pair<double, Tile>>& out, int k, int n, int r
 // otherwise.
 int group_for(const InstDesc& d) {
     if (d.conn == CONN_CSR && (d.blocked || d.wide)) return 1;
-    if (d.conn == CONN_UNIFORM && (d.n >= 4096 || d.wide)) return 1;
+    if (d.conn == CONN_UNIFORM && !(d.sgj && d.sym) && (d.n >= 4096 || d.wide)) return 1;
     return 0;
 }
 
@@ -282,6 +288,7 @@ size_t lds_floats_for(const infoli_ctx* c, const InstDesc& d, int block) {
                kMaxTileRows;   // the row sums (no static LDS in the stream variant)
     if (d.conn == CONN_CSR && d.blocked)   // the column block, then the tile rows' own voltages
         return d.cb_off >= 0 ? (size_t)c->blk_cols + kSelfSlots : (size_t)std::min(d.n, c->blk_cols);
+    if (d.conn == CONN_UNIFORM && d.sgj && d.sym) return 4;
     if (d.conn == CONN_UNIFORM) return (size_t)std::min(d.n, kChunk) + 8 * (size_t)(block / 64);
     if (d.conn == CONN_CSR && d.bitmap) return bitmap_lds_floats(d.n);
     if (d.conn == CONN_CSR && d.vd_lds) return (size_t)d.n;
@@ -427,12 +434,20 @@ void build_blocks(infoli_ctx* c, const infoli_network_spec* specs) {
 // relative to the block start padded with C + (i mod kSelfSlots) to whole
 // chunks; per row and block the first chunk ([n][nblk + 1]). Per-edge
 // weights follow the same layout, 0 on padding.
+// A simplified all-to-all network whose voltage sum k_vsum takes once per
+// step (tiled steps; by default a context's only network, from kSgjSumCells
+// cells on); its tiles take a row per thread.
+bool sum_once(const infoli_ctx* c, const InstDesc& d) {
+    const bool want = c->opt.pair_path == 2 || (c->opt.pair_path == 0 && d.n >= kSgjSumCells && c->n_inst == 1);
+    return d.conn == CONN_UNIFORM && d.sgj && want && c->opt.step_mode != INFOLI_MODE_PERSISTENT;
+}
+
 // All-to-all networks whose pairs are taken once (k_pairs_sym): the
-// realistic gap term (the simplified one has its O(n) closed form), tiled
-// steps; by default a context's only network, from kSymCells cells on. Row
-// blocks per workgroup: the most of 16, 8, 4 that still leaves at least 512
-// workgroups (measured best at 4,096, 8,192 and 16,384 cells; the column
-// sums' lane reduction is paid once per workgroup's share).
+// realistic gap term, tiled steps; by default a context's only network, from
+// kSymCells cells on. Row blocks per workgroup: the most of 16, 8, 4 that
+// still leaves at least 512 workgroups (measured best at 4,096, 8,192 and
+// 16,384 cells; the column sums' lane reduction is paid once per workgroup's
+// share). Simplified networks that sum_once picks get the group sums' room.
 void build_sym(infoli_ctx* c) {
     int64_t total = 0;
     for (int k = 0; k < c->n_inst; ++k) {
@@ -444,16 +459,23 @@ void build_sym(infoli_ctx* c) {
         // launch with the other networks' tiles, which measured faster than the
         // pair kernel running ahead of that launch (Table 4's batches of 5,760
         // and 7,680 cells: 41.6 / 61.8 us per step against 47.5 / 70.5)
+        if (d.sgj) {
+            if (!sum_once(c, d)) continue;
+            d.sym = 1;
+            d.psym_off = total;
+            total += vsum_floats(d.n);
+            continue;
+        }
         const bool want = c->opt.pair_path == 2 || (c->opt.pair_path == 0 && d.n >= kSymCells && c->n_inst == 1);
-        if (d.conn != CONN_UNIFORM || d.sgj || !want || c->opt.step_mode == INFOLI_MODE_PERSISTENT) continue;
+        if (d.conn != CONN_UNIFORM || !want || c->opt.step_mode == INFOLI_MODE_PERSISTENT) continue;
         d.sym = 1;
+        d.psym_off = total;
         d.sym_ki = 4;
         for (int ki : {kSymMaxKi, kSymMaxKi / 2})
             if ((int64_t)sym_blocks(d.n) * sym_shares(d.n, ki) >= 512) {
                 d.sym_ki = ki;
                 break;
             }
-        d.psym_off = total;
         total += sym_floats(d.n, d.sym_ki);
     }
     if (total == 0) return;
@@ -1381,7 +1403,10 @@ void build_context(infoli_ctx* c, const infoli_network_spec* specs, int32_t nins
         InstDesc& d = c->inst[k];
         int rows;
         switch (d.conn) {
-            case CONN_UNIFORM: rows = kUniformRows; c->deg_of[k] = d.n; break;
+            case CONN_UNIFORM:   // one row per lane; a row per thread when the sum is taken once
+                rows = sum_once(c, d) ? kMaxTileRows : kUniformRows;
+                c->deg_of[k] = d.n;
+                break;
             case CONN_DENSE: rows = c->opt.tile_rows ? c->opt.tile_rows : 16; c->deg_of[k] = d.n; break;
             case CONN_CSR: {
                 const double deg = (double)specs[k].nnz / d.n;
@@ -1985,7 +2010,9 @@ infoli_status infoli_get_gap_path(const infoli_ctx* ctx, int32_t instance, int32
         const InstDesc& d = ctx->inst[instance];
         int32_t p = INFOLI_PATH_NONE, blk = 0;
         if (d.conn == CONN_UNIFORM)
-            p = d.sym && ctx->opt.step_mode != INFOLI_MODE_PERSISTENT ? INFOLI_PATH_UNIFORM_SYM : INFOLI_PATH_UNIFORM;
+            p = !d.sym || ctx->opt.step_mode == INFOLI_MODE_PERSISTENT ? INFOLI_PATH_UNIFORM
+                : d.sgj                                                ? INFOLI_PATH_UNIFORM_SUM
+                                                                       : INFOLI_PATH_UNIFORM_SYM;
         else if (d.conn == CONN_DENSE) p = INFOLI_PATH_DENSE;
         else if (d.conn == CONN_CSR) {
             const bool wide = ctx->group_of.size() > (size_t)instance && ctx->group_of[instance] == 1;

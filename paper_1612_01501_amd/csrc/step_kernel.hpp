@@ -74,7 +74,9 @@ struct InstDesc {
     int32_t sgj;           // simplified (linear) gap junctions: term w * dV
     int32_t pcell;         // per-cell parameters in StepArgs::cparams
     int32_t stream;        // blocked: the flat chunk stream (row tags) instead of row groups
-    int32_t sym;           // UNIFORM: each unordered pair once (k_pairs_sym), partial sums in psym
+    int32_t sym;           // UNIFORM: sums a kernel ahead of the step wrote into psym: each
+                           // unordered pair once (k_pairs_sym), or for the simplified term the
+                           // voltage sum (k_vsum)
     int64_t bits_off;      // bitmap: offset of the network's first word
     int64_t blk_off;       // blocked: offset of the network's [n][nblk] block starts
     int64_t ca_off;        // chunked rows: offset of the [n + 1] row chunk starts, -1 none
@@ -199,6 +201,17 @@ __host__ __device__ constexpr int64_t sym_floats(int n, int ki) {
     return (sym_vsum_off(n, ki) + 2 * (int64_t)sym_blocks(n) + 63) / 64 * 64;
 }
 
+// The simplified term's closed form g (n Vd_i - sum_j Vd_j) needs one sum of
+// all voltages. Each tile adding all n of them is O(n^2 / 64) loads per
+// step; from kSgjSumCells cells on, a context's only such network has k_vsum
+// write one fp64 sum per kVsumCells cells ahead of the step instead (one
+// more launch; measured 0.9 us slower per step at 16,384 cells, 4.9 us
+// faster at 20,480).
+constexpr int kVsumCells = 4096;
+constexpr int kSgjSumCells = 20480;
+__host__ __device__ constexpr int vsum_groups(int n) { return (n + kVsumCells - 1) / kVsumCells; }
+__host__ __device__ constexpr int64_t vsum_floats(int n) { return (2 * (int64_t)vsum_groups(n) + 63) / 64 * 64; }
+
 template <int BLOCK>
 __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d, const Tile& t,
                                             const float* __restrict__ vd, float* s_ig,
@@ -294,6 +307,27 @@ __device__ __forceinline__ void gap_uniform(const StepArgs& a, const InstDesc& d
         const float lin = (float)((double)n * (double)vi - tot);
         s_ig[lane] = d.sgj ? d.g * lin : d.g * (0.8f * (e * kInvPreScale) + 0.2f * lin);
     }
+}
+
+// The simplified all-to-all form with the voltage sum taken once per step:
+// the workgroup adds the fp64 group sums k_vsum wrote in a fixed order, then
+// each of the tile's rows (up to kMaxTileRows) takes g (n Vd_i - sum).
+template <int BLOCK>
+__device__ __forceinline__ void gap_uniform_sum(const StepArgs& a, const InstDesc& d, const Tile& t,
+                                                const float* __restrict__ vd, float* s_ig, double* s_red) {
+    constexpr int W = BLOCK / 64;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const double* gs = reinterpret_cast<const double*>(a.psym + d.psym_off);
+    double vsum = 0.0;
+    for (int k = threadIdx.x; k < vsum_groups(d.n); k += BLOCK) vsum += gs[k];
+    for (int m = 32; m > 0; m >>= 1) vsum += __shfl_xor(vsum, m, 64);
+    if (lane == 0) s_red[wave] = vsum;
+    __syncthreads();
+    double tot = 0.0;
+    for (int w = 0; w < W; ++w) tot += s_red[w];
+    for (int k = threadIdx.x; k < t.row1 - t.row0; k += BLOCK)
+        s_ig[k] = d.g * (float)((double)d.n * (double)vd[t.row0 + k] - tot);
 }
 
 // ---------------------------------------------------------------- all-to-all, each unordered pair once
@@ -415,6 +449,22 @@ static __global__ __launch_bounds__(256) void k_pairs_sym(const float* __restric
     if (s == 0 && w == 0)
         pdiag[(int64_t)J * 64 + lane] = ((s_row[0][kSymMaxKi][lane] + s_row[1][kSymMaxKi][lane]) +
                                          s_row[2][kSymMaxKi][lane]) + s_row[3][kSymMaxKi][lane];
+}
+
+// One workgroup per kVsumCells cells: thread k adds voltages k, k + 256, ..
+// in fp64, the lanes combine by a fixed butterfly and the waves in wave order,
+// so the step's sum of the groups' sums is the same every step.
+static __global__ __launch_bounds__(256) void k_vsum(const float* __restrict__ vd, int n,
+                                                     double* __restrict__ out) {
+    __shared__ double s_w[4];
+    const int base = blockIdx.x * kVsumCells;
+    const int m = min(kVsumCells, n - base);
+    double s = 0.0;
+    for (int k = threadIdx.x; k < m; k += 256) s += (double)vd[base + k];
+    for (int h = 32; h > 0; h >>= 1) s += __shfl_xor(s, h, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
 }
 
 template <int BLOCK>
@@ -1332,7 +1382,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const float* __rest
         for (int k = threadIdx.x; k < nrows; k += BLOCK) s_ig[k] = 0.0f;
     } else {
         switch (d.conn) {
-            case CONN_UNIFORM: gap_uniform<BLOCK>(a, d, t, vd, s_ig, s_v4, s_part, s_red); break;
+            case CONN_UNIFORM:
+                if (d.sgj && d.sym) gap_uniform_sum<BLOCK>(a, d, t, vd, s_ig, s_red);
+                else gap_uniform<BLOCK>(a, d, t, vd, s_ig, s_v4, s_part, s_red);
+                break;
             case CONN_DENSE: gap_dense<BLOCK>(a, d, t, vd, s_ig); break;
             case CONN_CSR:
                 if (d.bitmap) gap_bitmap<BLOCK>(a, d, t, vd, reinterpret_cast<float*>(s_v4), s_part, s_ig);

@@ -284,7 +284,8 @@ def mlp_adam_step(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e
 
 
 GAP_KIND = {"rgj": 0, "sgj": 1}
-GAP_PATH = ("none", "uniform", "dense", "csr_gather", "csr_chunked", "csr_bitmap", "csr_stream", "uniform_sym")
+GAP_PATH = ("none", "uniform", "dense", "csr_gather", "csr_chunked", "csr_bitmap", "csr_stream", "uniform_sym",
+            "uniform_sum")
 
 
 class _SpecHolder:

@@ -264,6 +264,19 @@ def test_unordered_pair_roofline_counts_its_own_work():
         "infoli::k_pairs_sym + infoli::k_step<1024, 2>"
 
 
+def test_voltage_sum_once_keeps_the_byte_roofline():
+    """The simplified all-to-all form with the voltage sum taken once per step:
+    two kernels named, bound by the bytes of the compartment update (the sum
+    adds 8 bytes per 4,096 cells)."""
+    net = I.Network(n=40000, conn="uniform", g=0.001, gap="sgj")
+    info = {"step_mode": 0, "n_tiles_wide": 0, "n_tiles": 157, "wide_threads": 1024}
+    assert bench.step_kernel_name(info, [net], ["uniform_sum"]) == \
+        "infoli::k_vsum + infoli::k_step<256, 2>"
+    r = bench.roofline([net], 1e-5, "k", ["uniform_sum"])
+    assert r["bound"] == "hbm"
+    assert r["algorithmic_bytes_per_launch"] == bench.algorithmic_bytes([net], ["uniform"])
+
+
 def test_source_hash_ignores_comments_only():
     """The traffic records are keyed by the kernel sources' code: comments and
     layout do not count, string literals and code do."""

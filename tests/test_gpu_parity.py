@@ -954,6 +954,51 @@ def test_sgj_mixed_batch_matches_standalone_bitwise(infoli):
         s.close()
 
 
+@pytest.mark.parametrize("n", [1, 65, 4095, 4097, 9000, 33000])
+def test_sgj_voltage_sum_once_gap_current(infoli, o64, n):
+    """The simplified all-to-all form with the sum of all voltages taken once
+    per step (fp64 sums of each 4,096 cells by a separate kernel, added by
+    every tile): gap currents against the fp64 oracle with one group, a
+    ragged last group and several; a lone network of 20,480 cells or more
+    takes it by default."""
+    rs = I.rng(n + 41)
+    net = I.Network(n=n, conn="uniform", g=0.04 * 96 / max(n, 96), jitter=rs.uniform(-15, 15, (3, n)), gap="sgj")
+    x0 = infoli.initial_state(net)
+    opt = {} if n >= 20480 else {"pair_path": 2, "autotune": 0}     # the largest tuned at init
+    sim = infoli.Simulator(net, init_states=[x0], step_mode="graph", **opt)
+    assert sim.gap_path(0)[0] == "uniform_sum"
+    got = sim.read_gap_current(0).astype(np.float64)
+    sim.close()
+    ref = o64.gap(net, x0[0].astype(np.float64))
+    tol = gap_bound(net, x0[0])
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
+def test_sgj_voltage_sum_once_trajectory_and_repeatable(infoli, o32, o64):
+    """1,000 steps of a 5,000-cell simplified all-to-all network with the sum
+    taken once against the oracle, spikes included; graph replays and single
+    launches give the same bits; below 20,480 cells every tile sums by
+    itself unless asked."""
+    net = _sgj(I.config2(seed=2, n=5000, pulse=True))
+    net.pulses = [I.Pulse(100, 600, 6.0)]
+    x0 = infoli.initial_state(net)
+    got, c, t = gpu_trace(infoli, net, 1000, 50, x0, pair_path=2, step_mode="graph", autotune=0)
+    ref = o32.run(net, 1000, x0=x0, trace_every=50, trace_cells=net.n)
+    r64 = o64.run(net, 1000, x0=x0.astype(np.float64), trace_every=50, trace_cells=net.n)
+    check_state_bounds(got, ref["trace"], r64["trace"], net.label)
+    compare_spikes(c, t, ref["counts"], ref["times"], 64)
+    runs = []
+    for mode in ("graph", "launch"):
+        sim = infoli.Simulator(net, init_states=[x0], pair_path=2, step_mode=mode, graph_chunk=50, autotune=0)
+        sim.step(200)
+        runs.append(sim.read_state(0))
+        sim.close()
+    np.testing.assert_array_equal(runs[0], runs[1])
+    sim = infoli.Simulator(net, init_states=[x0], autotune=0)
+    assert sim.gap_path(0)[0] == "uniform"
+    sim.close()
+
+
 # ------------------------------------------------------------------ per-cell parameters
 def _het(n, seed):
     rs = I.rng(seed)
