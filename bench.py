@@ -30,6 +30,9 @@ Workloads (--workload):
            steps
   sgj16k   the uni16k network with simplified gap junctions (the closed
            form g (N Vd_i - sum Vd)), 4,000 steps
+  sgj1m    2^20 cells all-to-all with simplified gap junctions, the sum of
+           all voltages taken once per step, 2,000 steps (no CPU baseline:
+           the oracle evaluates all 1.1e12 pairs of a step)
   batch256 256 independent networks, N_k ~ U{64..2048}, density ~ U{5, 25,
            100 %} (100 % all-to-all, else ER CSR), g_k ~ U[0.01, 0.08],
            pulse amplitude ~ U[2, 10] uA/cm^2, 10,000 steps, one launch per
@@ -217,7 +220,10 @@ WORKLOADS = {
     "valid120k": dict(steps=120000, warmup=1000),
     "sgj65k": dict(steps=2000, warmup=100),
     "sgj16k": dict(steps=4000, warmup=200),
+    "sgj1m": dict(steps=2000, warmup=100),
 }
+# workloads whose oracle step is beyond a bounded CPU sample
+NO_CPU_BASELINE = {"sgj1m": "the oracle evaluates every pair by its definition, 1.1e12 per step"}
 
 
 def build_workload(name):
@@ -258,6 +264,11 @@ def build_workload(name):
         nets[0].gap = "sgj"
         desc = ("16,384 cells all-to-all, simplified gap junctions w*dV (closed form g*(N*Vd_i - sum Vd)), "
                 "g=0.04*96/N mS/cm^2, +-1 mV jitter, no input, FP32, dt=0.05 ms")
+    elif name == "sgj1m":
+        nets = [I.config2(n=1 << 20)]
+        nets[0].gap = "sgj"
+        desc = ("1,048,576 cells all-to-all, simplified gap junctions w*dV (closed form g*(N*Vd_i - sum Vd), "
+                "the sum taken once per step), g=0.04*96/N mS/cm^2, +-1 mV jitter, no input, FP32, dt=0.05 ms")
     elif name == "ngj16m":
         n = 1 << 24
         nets = [I.Network(n=n, conn="none", jitter=I.voltage_jitter(n, 2000), bias=I.input_bias(n, 3000),
@@ -1031,7 +1042,10 @@ def main():
     }
     out["roofline"]["traffic_key"] = traffic_key(args.workload, step_kernel_name(info, nets, paths), paths, info)
     out["roofline"]["traffic"] = measured_traffic(out["roofline"]["traffic_key"])
-    if not args.no_cpu_baseline:
+    if args.workload in NO_CPU_BASELINE:
+        out["cpu_baseline"] = None
+        out["cpu_baseline_note"] = NO_CPU_BASELINE[args.workload]
+    elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nets, args.cpu_budget)
     print(json.dumps(out), flush=True)
 

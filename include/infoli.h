@@ -191,7 +191,7 @@ typedef struct infoli_options {
                                     cells). With the simplified term (the closed form of
                                     Section 2.3.2 needs the sum of all voltages): 0 =>
                                     that sum once per step by a separate kernel for a
-                                    context's only network from 20,480 cells on, else by
+                                    context's only network from 12,288 cells on, else by
                                     every tile; 1 => by every tile; 2 => once per step
                                     (8 bytes per 4,096 cells)                              */
 } infoli_options;

@@ -205,10 +205,10 @@ __host__ __device__ constexpr int64_t sym_floats(int n, int ki) {
 // all voltages. Each tile adding all n of them is O(n^2 / 64) loads per
 // step; from kSgjSumCells cells on, a context's only such network has k_vsum
 // write one fp64 sum per kVsumCells cells ahead of the step instead (one
-// more launch; measured 0.9 us slower per step at 16,384 cells, 4.9 us
-// faster at 20,480).
+// more launch; measured 0.1 us slower per step at 8,192 cells, 1.0 us faster
+// at 12,288).
 constexpr int kVsumCells = 4096;
-constexpr int kSgjSumCells = 20480;
+constexpr int kSgjSumCells = 12288;
 __host__ __device__ constexpr int vsum_groups(int n) { return (n + kVsumCells - 1) / kVsumCells; }
 __host__ __device__ constexpr int64_t vsum_floats(int n) { return (2 * (int64_t)vsum_groups(n) + 63) / 64 * 64; }
 
@@ -453,14 +453,24 @@ static __global__ __launch_bounds__(256) void k_pairs_sym(const float* __restric
 
 // One workgroup per kVsumCells cells: thread k adds voltages k, k + 256, ..
 // in fp64, the lanes combine by a fixed butterfly and the waves in wave order,
-// so the step's sum of the groups' sums is the same every step.
+// so the step's sum of the groups' sums is the same every step. The loads
+// are all issued before the first add (one memory round trip per thread).
 static __global__ __launch_bounds__(256) void k_vsum(const float* __restrict__ vd, int n,
                                                      double* __restrict__ out) {
+    constexpr int kPer = kVsumCells / 256;
     __shared__ double s_w[4];
     const int base = blockIdx.x * kVsumCells;
     const int m = min(kVsumCells, n - base);
+    float v[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {   // past the last cell: load it again, add 0
+        const int k = threadIdx.x + 256 * i;
+        const float x = vd[base + min(k, m - 1)];
+        v[i] = k < m ? x : 0.0f;
+    }
     double s = 0.0;
-    for (int k = threadIdx.x; k < m; k += 256) s += (double)vd[base + k];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) s += (double)v[i];
     for (int h = 32; h > 0; h >>= 1) s += __shfl_xor(s, h, 64);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
     __syncthreads();

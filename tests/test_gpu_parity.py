@@ -959,12 +959,12 @@ def test_sgj_voltage_sum_once_gap_current(infoli, o64, n):
     """The simplified all-to-all form with the sum of all voltages taken once
     per step (fp64 sums of each 4,096 cells by a separate kernel, added by
     every tile): gap currents against the fp64 oracle with one group, a
-    ragged last group and several; a lone network of 20,480 cells or more
+    ragged last group and several; a lone network of 12,288 cells or more
     takes it by default."""
     rs = I.rng(n + 41)
     net = I.Network(n=n, conn="uniform", g=0.04 * 96 / max(n, 96), jitter=rs.uniform(-15, 15, (3, n)), gap="sgj")
     x0 = infoli.initial_state(net)
-    opt = {} if n >= 20480 else {"pair_path": 2, "autotune": 0}     # the largest tuned at init
+    opt = {} if n >= 12288 else {"pair_path": 2, "autotune": 0}     # the largest tuned at init
     sim = infoli.Simulator(net, init_states=[x0], step_mode="graph", **opt)
     assert sim.gap_path(0)[0] == "uniform_sum"
     got = sim.read_gap_current(0).astype(np.float64)
@@ -977,7 +977,7 @@ def test_sgj_voltage_sum_once_gap_current(infoli, o64, n):
 def test_sgj_voltage_sum_once_trajectory_and_repeatable(infoli, o32, o64):
     """1,000 steps of a 5,000-cell simplified all-to-all network with the sum
     taken once against the oracle, spikes included; graph replays and single
-    launches give the same bits; below 20,480 cells every tile sums by
+    launches give the same bits; below 12,288 cells every tile sums by
     itself unless asked."""
     net = _sgj(I.config2(seed=2, n=5000, pulse=True))
     net.pulses = [I.Pulse(100, 600, 6.0)]
