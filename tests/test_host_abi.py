@@ -28,6 +28,17 @@ def test_library_exports_every_declared_function():
     assert set(infoli.EXPORTS) == set(names)
 
 
+def test_gap_path_names_follow_header_enum():
+    """The binding's gap-path names are indexed by the header's
+    infoli_gap_path codes."""
+    text = open(HEADER).read()
+    body = re.search(r"typedef enum infoli_gap_path \{(.*?)\} infoli_gap_path;", text, flags=re.S).group(1)
+    codes = {name.lower(): int(v) for name, v in re.findall(r"INFOLI_PATH_([A-Z_0-9]+)\s*=\s*(\d+)", body)}
+    assert sorted(codes.values()) == list(range(len(infoli.GAP_PATH)))
+    for name, v in codes.items():
+        assert infoli.GAP_PATH[v] == name, (name, v)
+
+
 def test_struct_layout_matches_header(tmp_path):
     """The ctypes mirrors have the C compiler's sizes and field offsets."""
     src = tmp_path / "sz.c"
